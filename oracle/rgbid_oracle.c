@@ -460,12 +460,14 @@ double or_estimate_nu(const double* r, int n, double mu, double sigma)
     return 0.5 * (lo + hi);
 }
 
-/* Systematic sample stride (sec. 6.3, N = sample_max): s = max(1,
-   floor(sqrt(w h / N))); the sample is the pixels with u = v = 0 (mod s). */
+/* Systematic sample (sec. 6.3, "a sample with a maximum size of N"): the
+   pixels with u = v = 0 (mod s), with s the smallest stride >= 1 whose sample
+   grid ceil(w/s) x ceil(h/s) holds at most N pixels. */
 int or_sample_stride(int w, int h, int nmax)
 {
-    int s = (int)floor(sqrt((double)w * h / nmax));
-    return s < 1 ? 1 : s;
+    int s = 1;
+    while ((long long)((w + s - 1) / s) * ((h + s - 1) / s) > nmax) ++s;
+    return s;
 }
 
 /* ---------------------------------------------------------------- solve */

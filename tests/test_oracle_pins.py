@@ -403,6 +403,11 @@ def test_sample_strides():
     assert oracle.sample_stride(1280, 960) == 8
     assert oracle.sample_stride(320, 240) == 2
     assert oracle.sample_stride(160, 120) == 1
+    # the sample never exceeds N, also for sizes that are not 640x480 multiples
+    for w, h in [(300, 250), (641, 481), (139, 139), (1000, 20), (7, 5)]:
+        s = oracle.sample_stride(w, h)
+        assert -(-w // s) * -(-h // s) <= 19200
+        assert s == 1 or -(-w // (s - 1)) * -(-h // (s - 1)) > 19200
     for l in range(3):
         s = oracle.sample_stride(640 >> l, 480 >> l)
         assert len(range(0, 640 >> l, s)) * len(range(0, 480 >> l, s)) == 19200
