@@ -1,0 +1,242 @@
+/*
+ * rgbid.h - C ABI of the MI355X (gfx950) dense RGB-D alignment library.
+ *
+ * The library estimates the rigid motion between two RGB-D frames by dense
+ * frame-to-keyframe alignment in inverse-depth parametrisation and fuses
+ * inverse-depth maps into a keyframe, following Gutierrez-Gomez & Guerrero,
+ * "RGBiD-SLAM for Accurate Real-time Localisation and 3D Mapping":
+ *   - problem statement and frames A (reference) / B (current): sec. 6.1;
+ *   - coarse-to-fine Gauss-Newton / IRLS with the photometric and
+ *     inverse-depth residuals and the pose update: sec. 6.2;
+ *   - robust location / scale / degrees of freedom on a systematic sample:
+ *     sec. 6.3;
+ *   - inverse geometric warping: sec. 5.3;
+ *   - keyframe fusion with the covisibility test: sec. 7.2 and sec. 6.4.
+ *
+ * Conventions (all calls)
+ *   Images are row-major; element (u, v) is at index v * pitch + u, with u the
+ *   column and v the row, pixel centres at integer coordinates.  Intensity is
+ *   in grey levels; inverse depth W = 1/Z in 1/m, and W <= 0 or non-finite
+ *   marks a hole.  Device pointers are HIP device memory on the context's
+ *   device (a torch tensor's data_ptr() is fine).
+ *   A pose is T = (R, t), R row-major, the pose of B in A: X_A = R X_B + t
+ *   (the paper's T_A^B).  Twists are xi = (v, theta), translation first.
+ *
+ * Errors
+ *   Every call returns an rgbid_status; nothing throws or aborts across the
+ *   ABI.  rgbid_last_error() returns a text description of the last failure
+ *   on that context.  Calls on one context are not thread-safe; use one
+ *   context per host thread (each with its own stream).
+ *
+ * Synchrony
+ *   Calls enqueue work on the context's stream.  Calls that return host
+ *   results (poses, statistics, counts) synchronise that stream before
+ *   returning; calls that only produce device data do not.
+ */
+#ifndef RGBID_H
+#define RGBID_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RGBID_OK = 0,
+    RGBID_E_ARG = -1,         /* invalid argument (NULL, range, mismatched parameters) */
+    RGBID_E_SHAPE = -2,       /* image sizes / formats of the operands do not match */
+    RGBID_E_DEVICE = -3,      /* a HIP runtime call failed */
+    RGBID_E_NOMEM = -4,       /* device or pinned-host allocation failed */
+    RGBID_E_DEGENERATE = -5   /* normal equations not positive definite, or fewer
+                                 than 6 valid residuals: the pose keeps its last value */
+} rgbid_status;
+
+/* Level-0 pinhole camera of undistorted images (sec. 4.1 without the
+   distortion term).  Level l uses f/2^l and (c + 0.5)/2^l - 0.5. */
+typedef struct {
+    int width, height;
+    double fx, fy, cx, cy;
+} rgbid_camera;
+
+/* T_A^B: X_A = R X_B + t, R row-major. */
+typedef struct {
+    double R[9];
+    double t[3];
+} rgbid_pose;
+
+/* Storage format of pyramid images: FP32, or FP16 (per-pixel arithmetic is
+   FP32 either way). */
+typedef enum { RGBID_F32 = 0, RGBID_F16 = 1 } rgbid_format;
+
+/* Robust weight: Student-t with estimated degrees of freedom (sec. 6.3), or
+   Huber with threshold huber_k on the normalised residual. */
+typedef enum { RGBID_W_STUDENT_T = 0, RGBID_W_HUBER = 1 } rgbid_weight;
+
+/* FULLRES: every iteration warps B at full resolution and downsamples the
+   warped images to the current level (sec. 6.2).  PER_LEVEL: warps the
+   level-l images of B directly (a cheaper variant). */
+typedef enum { RGBID_WARP_FULLRES = 0, RGBID_WARP_PER_LEVEL = 1 } rgbid_warp_mode;
+
+typedef struct {
+    int levels;              /* pyramid levels used, 1..8 (<= the pyramids' levels) */
+    int iters[8];            /* Gauss-Newton iterations at each level (index = level) */
+    int weight;              /* rgbid_weight */
+    double huber_k;          /* Huber threshold, default 1.345 */
+    int estimate_nu;         /* Student-t: estimate nu by bisection on [2, 10] (default 1) */
+    int sample_max;          /* N, maximum size of the systematic sample (default 19200,
+                                at most 24576) */
+    int scale_iters;         /* fixed-point iterations for location and scale (default 20) */
+    int warp;                /* rgbid_warp_mode */
+    double stop_eps_t;       /* early stop of a level when |v| < eps_t and |theta| < eps_r; */
+    double stop_eps_r;       /*   both 0 = fixed schedule (default) */
+} rgbid_align_params;
+
+/* Statistics of the last linearisation of an alignment.  H is the upper
+   triangle of the 6x6 normal matrix, row-major (H00 H01 .. H05 H11 .. H55);
+   g = sum w J^T r, so that the step is xi = -H^-1 g.  H is the inverse of the
+   pose covariance (sec. 6.2). */
+typedef struct {
+    double H[21], g[6];
+    double mu_I, sigma_I, nu_I, mu_W, sigma_W, nu_W;
+    double cost;                   /* sum of w r^2 over both channels */
+    long long n_valid_I, n_valid_W;
+    int iters_done[8];
+    int status;                    /* rgbid_status of this pair */
+} rgbid_align_stats;
+
+typedef struct rgbid_ctx rgbid_ctx;
+typedef struct rgbid_pyr rgbid_pyr;
+typedef struct rgbid_kf rgbid_kf;
+
+/* Fills p with the defaults: 4 levels, 10 iterations per level, Huber
+   k = 1.345, nu estimated (Student-t only), N = 19200, 20 scale iterations,
+   FULLRES warp, fixed schedule. */
+void rgbid_default_params(rgbid_align_params* p);
+
+/* ------------------------------------------------------------ lifecycle */
+
+/* Creates a context on HIP device `device`, enqueuing on `hip_stream` (a
+   hipStream_t; NULL = the legacy default stream).  The context owns its
+   scratch memory.  *ctx is NULL on failure. */
+rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream);
+
+/* Releases the context and its scratch memory (synchronises its stream).
+   Pyramids and keyframes must be freed separately.  NULL is ignored. */
+void rgbid_destroy(rgbid_ctx* ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by the context. */
+const char* rgbid_last_error(const rgbid_ctx* ctx);
+
+/* ------------------------------------------------------------ pyramid */
+
+/* Builds a `levels`-level image pyramid (sec. 6.2: images are downsampled at
+   every level) from caller-owned FP32 device images I_dev, W_dev of size
+   cam->width x cam->height with row pitch `pitch_elems` (elements, >= width).
+   Level l+1 is the 2x2 mean of level l (size floor(w/2) x floor(h/2)); the
+   inverse depth mean skips holes and is a hole when all four are holes.
+   Images are stored in `storage` format (FP16 rounds to nearest even).
+   The input is copied (not aliased) and may be released when the call
+   returns; the call does not synchronise.  *out is library-owned; free it
+   with rgbid_pyramid_free.  Errors: E_ARG (NULL, levels outside 1..8, a
+   level smaller than 1x1), E_NOMEM, E_DEVICE. */
+rgbid_status rgbid_pyramid(rgbid_ctx* ctx, const rgbid_camera* cam, int levels,
+                           rgbid_format storage, const float* I_dev, const float* W_dev,
+                           size_t pitch_elems, rgbid_pyr** out);
+
+/* Rebuilds an existing pyramid in place from new images of the same size
+   (no allocation).  Same arguments and errors as rgbid_pyramid. */
+rgbid_status rgbid_pyramid_update(rgbid_ctx* ctx, rgbid_pyr* pyr, const float* I_dev,
+                                  const float* W_dev, size_t pitch_elems);
+
+/* Rebuilds n existing pyramids in place in one batched launch per level.
+   I_dev[i], W_dev[i], pitch_elems[i] describe frame i as in rgbid_pyramid and
+   must match pyrs[i]'s size.  All pyramids share one storage format.  Does
+   not synchronise.  Errors: E_ARG, E_SHAPE, E_NOMEM, E_DEVICE. */
+rgbid_status rgbid_pyramid_update_batch(rgbid_ctx* ctx, int n, rgbid_pyr* const* pyrs,
+                                        const float* const* I_dev, const float* const* W_dev,
+                                        const size_t* pitch_elems);
+
+/* Copies level `level` of a pyramid into caller-owned FP32 device buffers of
+   size w_l x h_l (dense rows), converting from the storage format.  Holes
+   read as 0.  Does not synchronise.  Errors: E_ARG. */
+rgbid_status rgbid_pyramid_read(rgbid_ctx* ctx, const rgbid_pyr* pyr, int level,
+                                float* I_out_dev, float* W_out_dev);
+
+/* Level size of a pyramid (host-side, no device work). */
+rgbid_status rgbid_pyramid_level_size(const rgbid_pyr* pyr, int level, int* w, int* h);
+
+void rgbid_pyramid_free(rgbid_pyr* pyr);
+
+/* ------------------------------------------------------------ alignment */
+
+/* Estimates T_A^B between reference A and current frame B (sec. 6.2):
+   coarse-to-fine from level params->levels-1 to 0, params->iters[l]
+   iterations at level l; each iteration warps B towards A at the current
+   estimate (sec. 5.3), forms the photometric and inverse-depth residuals
+   with their Jacobians, estimates location / scale (and nu) on the systematic
+   sample (sec. 6.3), reduces the weighted 6x6 normal equations, solves them
+   by Cholesky in FP64 on the device and applies T <- exp(xi)^-1 T.
+   `init` NULL = identity (sec. 6.2).  Writes the pose to *out and, if
+   stats != NULL, the statistics of the last linearisation.  Synchronises.
+   A degenerate system stops the iteration and returns E_DEGENERATE with the
+   last good pose in *out.  Errors: E_ARG, E_SHAPE (A and B differ in size,
+   format or levels), E_NOMEM, E_DEVICE. */
+rgbid_status rgbid_align(rgbid_ctx* ctx, const rgbid_pyr* A, const rgbid_pyr* B,
+                         const rgbid_pose* init, const rgbid_align_params* params,
+                         rgbid_pose* out, rgbid_align_stats* stats);
+
+/* Aligns n independent pairs (A[i], B[i]) of possibly different sizes in one
+   schedule: every iteration of every level is a fixed sequence of launches
+   that covers all pairs, replayed from a cached HIP graph when the batch
+   shape repeats.  All pyramids must share one storage format and have at
+   least params->levels levels.  init: n poses or NULL (identity); out: n
+   poses; stats: n entries or NULL.  Per-pair failure is reported in
+   stats[i].status (the call itself returns OK unless an argument or the
+   device failed).  Synchronises. */
+rgbid_status rgbid_align_batch(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
+                               const rgbid_pyr* const* B, const rgbid_pose* init,
+                               const rgbid_align_params* params, rgbid_pose* out,
+                               rgbid_align_stats* stats);
+
+/* One linearisation without an update: the normal equations of the pair at
+   pyramid level `level` and pose T, with the same sampling and weights as an
+   alignment iteration (diagnostic; also the Hessian for a covariance).
+   Synchronises.  Errors as rgbid_align; E_DEGENERATE is not raised (the
+   counts in *out tell). */
+rgbid_status rgbid_normal_equations(rgbid_ctx* ctx, const rgbid_pyr* A, const rgbid_pyr* B,
+                                    int level, const rgbid_pose* T,
+                                    const rgbid_align_params* params,
+                                    rgbid_align_stats* out);
+
+/* ------------------------------------------------------------ keyframe fusion */
+
+/* Creates a keyframe from a caller-owned FP32 inverse-depth map (copied) with
+   weight C = 1 everywhere (sec. 7.2).  Does not synchronise. */
+rgbid_status rgbid_keyframe_init(rgbid_ctx* ctx, const rgbid_camera* cam, const float* W_dev,
+                                 size_t pitch_elems, rgbid_kf** out);
+
+/* Fuses frame k's FP32 inverse-depth map into the keyframe (sec. 7.2): every
+   keyframe pixel with valid W_kf is transferred into frame k with T_kf_k
+   (the pose of frame k in the keyframe: X_kf = R X_k + t), W_k is sampled
+   bilinearly (four valid taps), and if |W_k(p_w) - 1/Y_z| < tol (the
+   covisibility test of sec. 6.4, tol = 3 sigma_W) the warped inverse depth W*
+   is merged: W_kf <- (W_kf C_kf + C_k W*)/(C_kf + C_k), C_kf <- C_kf + C_k,
+   with C_k the inverse-variance weight of the warp.  Keyframe holes stay
+   holes.  If n_fused != NULL the number of fused pixels is written there
+   (synchronises); otherwise the call does not synchronise.  Errors: E_ARG. */
+rgbid_status rgbid_fuse(rgbid_ctx* ctx, rgbid_kf* kf, const float* Wk_dev, size_t pitch_elems,
+                        const rgbid_pose* T_kf_k, double tol, long long* n_fused);
+
+/* Copies the keyframe's W and C maps into caller-owned FP32 device buffers
+   (dense rows).  Either pointer may be NULL.  Does not synchronise. */
+rgbid_status rgbid_keyframe_read(rgbid_ctx* ctx, const rgbid_kf* kf, float* W_out_dev,
+                                 float* C_out_dev);
+
+void rgbid_keyframe_free(rgbid_kf* kf);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGBID_H */

@@ -1,0 +1,816 @@
+// One Gauss-Newton / IRLS iteration of dense RGB-D alignment in inverse-depth
+// parametrisation (sec. 6.2), for a batch of frame pairs at one pyramid level.
+//
+//   k_warp    inverse geometric warp of {I_B, W_B} towards A (sec. 5.3) and,
+//             in FULLRES mode, the downsampling of the warped images to the
+//             level (sec. 6.2); writes the residuals of the systematic sample
+//             (sec. 6.3) and, in store mode, the warped level images.
+//   k_scale   location / scale fixed point and the nu bisection of sec. 6.3
+//             on the sample, one workgroup per (pair, channel).
+//   k_reduce  residuals, Jacobians (eq:res_int, eq:res_depth, eq:DeltaX),
+//             lambda_n and robust weights; reduction of the 21 + 6 normal-
+//             equation terms (2eq:minimisationIRLS) into per-chunk compensated
+//             FP32 partials.
+//   k_solve   FP64 cross-chunk sum, 6x6 Cholesky and the update
+//             T <- exp(xi)^-1 T with the decoupled exponential (sec. 3).
+//
+// Pixel work is organised in tiles of 64 consecutive pixels (raster order)
+// of a level grid; a workgroup walks a chunk of tiles of one pair.  In FULLRES
+// mode a level-l pixel has 4^l full-resolution children: the lanes of a
+// wavefront split the children, reduce them with cross-lane shuffles, and in
+// the end every lane owns one level-l pixel.
+#include "rgbid_internal.h"
+
+namespace rgbid {
+namespace {
+
+__device__ __forceinline__ bool w_valid(float w) { return w > 0.0f && w < INFINITY; }
+
+template <bool F16>
+__device__ __forceinline__ float2 load_iw(const void* p, int i)
+{
+    if constexpr (F16) return __half22float2(static_cast<const __half2*>(p)[i]);
+    else return static_cast<const float2*>(p)[i];
+}
+
+template <bool F16>
+__device__ __forceinline__ float load_w(const void* p, int i)
+{
+    if constexpr (F16) return __half2float(static_cast<const __half*>(p)[i]);
+    else return static_cast<const float*>(p)[i];
+}
+
+// Row / column of raster index idx in a grid of width gw (idx < 2^24).
+__device__ __forceinline__ void split_index(int idx, int gw, float inv_gw, int& gu, int& gv)
+{
+    int v = (int)((float)idx * inv_gw);
+    int u = idx - v * gw;
+    if (u < 0) { u += gw; --v; }
+    else if (u >= gw) { u -= gw; ++v; }
+    gu = u;
+    gv = v;
+}
+
+__device__ __forceinline__ int chunk_of_block(int b, int n, int remap)
+{
+    if (!remap) return b;
+    // Consecutive chunks on one XCD: XCD x = b % 8 runs a contiguous range.
+    const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
+// Warp parameters of one pair at the warp level.
+struct Geom {
+    float m[9];       // R^T
+    float q[3];       // R^T t
+    float fx, fy, cx, cy, ifx, ify;
+    int w, h;
+    const void* WA;   // W plane of A at the warp level
+    const void* Biw;  // interleaved (I, W) of B at the warp level
+};
+
+__device__ __forceinline__ Geom make_geom(const PairState& S, const LevelView& A, const LevelView& B)
+{
+    Geom G;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G.m[k] = S.RT[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G.q[k] = S.Rtt[k];
+    G.fx = A.fx;
+    G.fy = A.fy;
+    G.cx = A.cx;
+    G.cy = A.cy;
+    G.ifx = 1.0f / A.fx;
+    G.ify = 1.0f / A.fy;
+    G.w = A.w;
+    G.h = A.h;
+    G.WA = A.wp;
+    G.Biw = B.iw;
+    return G;
+}
+
+// Inverse geometric warp of one pixel (u, v) of A (sec. 5.3).  With
+// x = K^-1 p and w_a = W_A(p), W_A(p) * R^T (x / w_a - t) = R^T x - w_a R^T t
+// locates p_B; I* is the bilinear I_B(p_B) and
+// W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) with w_b the bilinear W_B(p_B).
+// Valid iff W_A(p) valid, in front, p_B in [-0.5, w-0.5) x [-0.5, h-0.5),
+// four valid W taps and W* positive and finite.
+template <bool F16>
+__device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, float& Wo)
+{
+    const float wa = load_w<F16>(G.WA, v * G.w + u);
+    if (!w_valid(wa)) return false;
+    const float rx = ((float)u - G.cx) * G.ifx, ry = ((float)v - G.cy) * G.ify;
+    const float ax = fmaf(G.m[0], rx, fmaf(G.m[1], ry, G.m[2]));
+    const float ay = fmaf(G.m[3], rx, fmaf(G.m[4], ry, G.m[5]));
+    const float az = fmaf(G.m[6], rx, fmaf(G.m[7], ry, G.m[8]));
+    const float yx = fmaf(-wa, G.q[0], ax), yy = fmaf(-wa, G.q[1], ay), yz = fmaf(-wa, G.q[2], az);
+    if (!(yz > 0.0f)) return false;
+    const float iz = 1.0f / yz;
+    const float ub = fmaf(G.fx * yx, iz, G.cx), vb = fmaf(G.fy * yy, iz, G.cy);
+    if (!(ub >= -0.5f && ub < (float)G.w - 0.5f && vb >= -0.5f && vb < (float)G.h - 0.5f))
+        return false;
+    const float fu = floorf(ub), fv = floorf(vb);
+    const float a = ub - fu, b = vb - fv;
+    int x0 = (int)fu, y0 = (int)fv;
+    const int x1 = min(x0 + 1, G.w - 1), y1 = min(y0 + 1, G.h - 1);
+    x0 = max(x0, 0);
+    y0 = max(y0, 0);
+    const float2 p00 = load_iw<F16>(G.Biw, y0 * G.w + x0);
+    const float2 p10 = load_iw<F16>(G.Biw, y0 * G.w + x1);
+    const float2 p01 = load_iw<F16>(G.Biw, y1 * G.w + x0);
+    const float2 p11 = load_iw<F16>(G.Biw, y1 * G.w + x1);
+    if (!(w_valid(p00.y) && w_valid(p10.y) && w_valid(p01.y) && w_valid(p11.y))) return false;
+    const float c00 = (1.0f - a) * (1.0f - b), c10 = a * (1.0f - b);
+    const float c01 = (1.0f - a) * b, c11 = a * b;
+    const float ib = c00 * p00.x + c10 * p10.x + c01 * p01.x + c11 * p11.x;
+    const float wb = c00 * p00.y + c10 * p10.y + c01 * p01.y + c11 * p11.y;
+    const float ws = az * wb / fmaf(wb, G.q[2], 1.0f);
+    if (!w_valid(ws)) return false;
+    Io = ib;
+    Wo = ws;
+    return true;
+}
+
+// Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
+// children at the warp level; LPP = min(C, 64) lanes share one pixel, GPP =
+// 64 / LPP pixels are warped per pass, and each lane handles CPL = C / LPP
+// children.
+template <int LOG2B>
+struct ChildLayout {
+    static constexpr int B = 1 << LOG2B;
+    static constexpr int C = B * B;
+    static constexpr int LPP = C < 64 ? C : 64;
+    static constexpr int GPP = 64 / LPP;
+    static constexpr int CPL = C / LPP;
+};
+
+// One pass: the GPP consecutive grid pixels first .. first+GPP-1 (grid of
+// width gw, grid stride gs in level pixels).  Every lane of group g = lane /
+// LPP returns the mean warped values of pixel first + g and whether all its
+// children are warp-valid (the strict downsampling rule).
+template <bool F16, int LOG2B>
+__device__ __forceinline__ void warp_pass(const Geom& G, int first, int gw, float inv_gw, int ngrid,
+                                          int gs, int lane, float& Io, float& Wo, bool& Vo,
+                                          int& idxo)
+{
+    using CL = ChildLayout<LOG2B>;
+    const int j = lane % CL::LPP, g = lane / CL::LPP;
+    const int idx = first + g;
+    const bool in = idx < ngrid;
+    int gu = 0, gv = 0;
+    if (in) split_index(idx, gw, inv_gw, gu, gv);
+    float sI = 0.0f, sW = 0.0f;
+    bool ok = in;
+#pragma unroll
+    for (int m = 0; m < CL::CPL; ++m) {
+        const int c = j + CL::LPP * m;
+        float ci = 0.0f, cw = 0.0f;
+        if (ok)
+            ok = warp_px<F16>(G, gu * gs * CL::B + (c % CL::B), gv * gs * CL::B + (c / CL::B),
+                              ci, cw);
+        sI += ci;
+        sW += cw;
+    }
+#pragma unroll
+    for (int off = 1; off < CL::LPP; off <<= 1) {
+        sI += __shfl_xor(sI, off);
+        sW += __shfl_xor(sW, off);
+    }
+    bool gvalid = ok;
+    if constexpr (CL::LPP > 1) {
+        const unsigned long long bal = __ballot(ok);
+        const unsigned long long full =
+            CL::LPP == 64 ? ~0ull : ((1ull << CL::LPP) - 1ull) << (unsigned)(g * CL::LPP);
+        gvalid = (bal & full) == full;
+    }
+    constexpr float invC = 1.0f / (float)CL::C;
+    Io = sI * invC;
+    Wo = sW * invC;
+    Vo = gvalid;
+    idxo = idx;
+}
+
+// A tile of 64 consecutive grid pixels in LPP passes; afterwards lane L owns
+// the tile pixel q = (L % LPP) * GPP + L / LPP.
+template <bool F16, int LOG2B>
+__device__ __forceinline__ void warp_tile(const Geom& G, int tile_first, int gw, float inv_gw,
+                                          int ngrid, int gs, int lane, float& Io, float& Wo,
+                                          bool& Vo, int& uo, int& vo, int& idxo)
+{
+    using CL = ChildLayout<LOG2B>;
+    const int j = lane % CL::LPP, g = lane / CL::LPP;
+    float mI = 0.0f, mW = 0.0f;
+    bool mV = false;
+#pragma unroll 1
+    for (int k = 0; k < CL::LPP; ++k) {
+        float pI, pW;
+        bool pV;
+        int pidx;
+        warp_pass<F16, LOG2B>(G, tile_first + k * CL::GPP, gw, inv_gw, ngrid, gs, lane, pI, pW,
+                              pV, pidx);
+        if (j == k) {
+            mI = pI;
+            mW = pW;
+            mV = pV;
+        }
+    }
+    idxo = tile_first + j * CL::GPP + g;
+    const bool in = idxo < ngrid;
+    int gu = 0, gv = 0;
+    if (in) split_index(idxo, gw, inv_gw, gu, gv);
+    uo = gu * gs;
+    vo = gv * gs;
+    Io = mI;
+    Wo = mW;
+    Vo = in && mV;
+}
+
+// Residuals (and Jacobians) of one level pixel (sec. 6.2).  r_I needs an
+// interior pixel, a valid W_A and warped values; r_W additionally the four
+// W_A neighbours (central-difference gradient).
+struct Terms {
+    bool vI, vW;
+    float rI, rW, lam;
+    float JI[6], JW[6];
+};
+
+template <bool F16, bool JAC>
+__device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float ify, int u, int v,
+                                            float Is, float Ws, bool wv, Terms& T)
+{
+    T.vI = T.vW = false;
+    if (!wv || u < 1 || v < 1 || u > A.w - 2 || v > A.h - 2) return;
+    const int i = v * A.w + u;
+    const float2 c = load_iw<F16>(A.iw, i);
+    if (!w_valid(c.y)) return;
+    const float2 l = load_iw<F16>(A.iw, i - 1), r = load_iw<F16>(A.iw, i + 1);
+    const float2 t = load_iw<F16>(A.iw, i - A.w), b = load_iw<F16>(A.iw, i + A.w);
+    T.vI = true;
+    T.rI = Is - c.x;
+    T.vW = w_valid(l.y) && w_valid(r.y) && w_valid(t.y) && w_valid(b.y);
+    T.rW = Ws - c.y;
+    if constexpr (JAC) {
+        const float wa = c.y, Z = 1.0f / wa;
+        const float du = A.cx - (float)u, dv = A.cy - (float)v;
+        const float xu = -du * ifx, xv = -dv * ify;
+        const float X0 = Z * xu, X1 = Z * xv, X2 = Z;
+        const float gu = 0.5f * (r.x - l.x), gv = 0.5f * (b.x - t.x);
+        const float a0 = wa * gu * A.fx, a1 = wa * gv * A.fy, a2 = wa * fmaf(gu, du, gv * dv);
+        T.JI[0] = a0;
+        T.JI[1] = a1;
+        T.JI[2] = a2;
+        T.JI[3] = X1 * a2 - X2 * a1;
+        T.JI[4] = X2 * a0 - X0 * a2;
+        T.JI[5] = X0 * a1 - X1 * a0;
+        if (T.vW) {
+            const float wu = 0.5f * (r.y - l.y), wv2 = 0.5f * (b.y - t.y);
+            const float k0 = wu * A.fx, k1 = wv2 * A.fy, k2 = fmaf(wu, du, wv2 * dv);
+            const float b0 = wa * k0, b1 = wa * k1, b2 = wa * (k2 + Ws);
+            T.JW[0] = b0;
+            T.JW[1] = b1;
+            T.JW[2] = b2;
+            T.JW[3] = X1 * b2 - X2 * b1;
+            T.JW[4] = X2 * b0 - X0 * b2;
+            T.JW[5] = X0 * b1 - X1 * b0;
+            // n~ = Z grad W (K - p e_z^T) + e_z, n~ . x = 1, lambda = 1/(|n~||x|)
+            const float n0 = Z * k0, n1 = Z * k1, n2 = fmaf(Z, k2, 1.0f);
+            const float nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+            const float xx = fmaf(xu, xu, fmaf(xv, xv, 1.0f));
+            T.lam = 1.0f / sqrtf(nn * xx);
+        }
+    }
+}
+
+__device__ __forceinline__ float omega(int kind, float x, float nu, float k)
+{
+    if (kind == RGBID_W_HUBER) {
+        const float ax = fabsf(x);
+        return ax <= k ? 1.0f : k / ax;
+    }
+    return (nu + 1.0f) / fmaf(x, x, nu);
+}
+
+__device__ __forceinline__ void accum(float* acc, const float* J, float w, float r)
+{
+    float s[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) s[a] = w * J[a];
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b) {
+            acc[k] = fmaf(s[a], J[b], acc[k]);
+            ++k;
+        }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc[21 + a] = fmaf(s[a], r, acc[21 + a]);
+    acc[27] = fmaf(w * r, r, acc[27]);
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Grid of a level for the pixel kernels: the full level grid, or the sample
+// grid (every s-th pixel in both directions).
+struct GridDim {
+    int gw, n, gs;
+    float inv_gw;
+};
+
+__device__ __forceinline__ GridDim level_grid(const LevelView& A)
+{
+    GridDim d;
+    d.gw = A.w;
+    d.n = A.w * A.h;
+    d.gs = 1;
+    d.inv_gw = 1.0f / (float)A.w;
+    return d;
+}
+
+__device__ __forceinline__ GridDim sample_grid(const PairDesc& D, int l)
+{
+    GridDim d;
+    d.gw = D.sw[l];
+    d.n = D.sw[l] * D.sh[l];
+    d.gs = D.stride[l];
+    d.inv_gw = 1.0f / (float)D.sw[l];
+    return d;
+}
+
+// ------------------------------------------------------------------ k_warp
+
+// Tiles of this kernel are single passes of GPP grid pixels.  The group
+// leader of each pixel stores the warped values (store mode) and, for sample
+// pixels, the two residuals (NaN = not defined).
+template <bool F16, int LOG2B>
+__global__ void __launch_bounds__(512) k_warp(IterLaunch L)
+{
+    using CL = ChildLayout<LOG2B>;
+    const int ci = chunk_of_block(blockIdx.x, L.n_warp_chunks, L.tune.xcd_remap);
+    const Chunk ch = L.warp_chunks[ci];
+    const PairState& S = L.states[ch.pair];
+    if (!S.active || S.level_stop) return;
+    const PairDesc& D = L.pairs[ch.pair];
+    const int l = L.level;
+    const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
+    const Geom G = make_geom(S, D.A[wl], D.B[wl]);
+    const LevelView& A = D.A[l];
+    const float ifx = 1.0f / A.fx, ify = 1.0f / A.fy;
+    const bool fused = L.tune.fused;
+    const GridDim gd = fused ? sample_grid(D, l) : level_grid(A);
+    const int s = D.stride[l], sw = D.sw[l];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int end = ch.first + ch.count;
+    for (int tile = ch.first + wave; tile < end; tile += waves) {
+        float Is, Ws;
+        bool wv;
+        int idx;
+        warp_pass<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane, Is, Ws,
+                              wv, idx);
+        if ((lane % CL::LPP) != 0 || idx >= gd.n) continue;
+        int gu, gv;
+        split_index(idx, gd.gw, gd.inv_gw, gu, gv);
+        const int u = gu * gd.gs, v = gv * gd.gs;
+        if (!fused) D.warped[idx] = make_float2(Is, wv ? Ws : 0.0f);
+        int sidx;
+        if (fused) sidx = idx;
+        else if ((u % s) == 0 && (v % s) == 0) sidx = (v / s) * sw + u / s;
+        else continue;
+        Terms T;
+        pixel_terms<F16, false>(A, ifx, ify, u, v, Is, Ws, wv, T);
+        D.sample[sidx] = make_float2(T.vI ? T.rI : __int_as_float(0x7fc00000),
+                                     T.vW ? T.rW : __int_as_float(0x7fc00000));
+    }
+}
+
+// ------------------------------------------------------------------ k_scale
+
+struct Sum3 {
+    double a, b, c;
+};
+
+__device__ __forceinline__ Sum3 block_sum3(Sum3 v, double* lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v.a = wave_sum_d(v.a);
+    v.b = wave_sum_d(v.b);
+    v.c = wave_sum_d(v.c);
+    if (lane == 0) {
+        lds[3 * wave] = v.a;
+        lds[3 * wave + 1] = v.b;
+        lds[3 * wave + 2] = v.c;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        Sum3 t{0.0, 0.0, 0.0};
+        if (lane < nw) {
+            t.a = lds[3 * lane];
+            t.b = lds[3 * lane + 1];
+            t.c = lds[3 * lane + 2];
+        }
+        t.a = wave_sum_d(t.a);
+        t.b = wave_sum_d(t.b);
+        t.c = wave_sum_d(t.c);
+        if (lane == 0) {
+            lds[96] = t.a;
+            lds[97] = t.b;
+            lds[98] = t.c;
+        }
+    }
+    __syncthreads();
+    Sum3 r{lds[96], lds[97], lds[98]};
+    return r;
+}
+
+// psi(x), x > 0: upward recurrence to x >= 12 then the Stirling-type series
+// psi(x) ~ ln x - 1/(2x) - sum_k B_2k / (2k x^2k) (Abramowitz & Stegun 6.3.18).
+__device__ double digamma_d(double x)
+{
+    double r = 0.0;
+    while (x < 12.0) {
+        r -= 1.0 / x;
+        x += 1.0;
+    }
+    const double z = 1.0 / (x * x);
+    const double series =
+        z * (1.0 / 12 + z * (-1.0 / 120 + z * (1.0 / 252 + z * (-1.0 / 240 + z * (1.0 / 132)))));
+    return r + log(x) - 0.5 / x - series;
+}
+
+// One workgroup per (pair, channel): location mu and scale sigma of the
+// channel's sample residuals by the fixed point of the two stationarity
+// equations of sec. 6.3 (weights from the previous estimate), starting at
+// mu = 0, sigma^2 = mean r^2, with nu = 5 for Student-t; then (Student-t with
+// estimation) nu by bisection of the nu equation on [2, 10] with the
+// normalised residuals frozen.
+__global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
+{
+    __shared__ double lds[100];
+    const int p = blockIdx.x, ch = blockIdx.y;
+    PairState& S = L.states[p];
+    if (!S.active || S.level_stop) return;
+    const PairDesc& D = L.pairs[p];
+    const int n_all = D.sw[L.level] * D.sh[L.level];
+    const float floor_s = ch == 0 ? 1e-3f : 1e-6f;
+    float r[kScalePerThread];
+    float cnt = 0.0f, sq = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kScalePerThread; ++k) {
+        const int i = threadIdx.x + k * kScaleThreads;
+        float x = __int_as_float(0x7fc00000);
+        if (i < n_all) {
+            const float2 e = D.sample[i];
+            x = ch == 0 ? e.x : e.y;
+        }
+        r[k] = x;
+        if (x == x) {
+            cnt += 1.0f;
+            sq = fmaf(x, x, sq);
+        }
+    }
+    Sum3 t = block_sum3(Sum3{(double)cnt, (double)sq, 0.0}, lds);
+    const double n = t.a;
+    double mu = 0.0, sigma = floor_s;
+    float nu = 5.0f;
+    if (n > 0.0) {
+        sigma = fmax(sqrt(t.b / n), (double)floor_s);
+        const float k = L.ip.huber_k;
+        for (int it = 0; it < L.ip.scale_iters; ++it) {
+            const float fmu = (float)mu, isg = (float)(1.0 / sigma);
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kScalePerThread; ++q) {
+                if (r[q] == r[q]) {
+                    const float d = r[q] - fmu;
+                    const float w = omega(L.ip.weight, d * isg, 5.0f, k);
+                    s0 += w;
+                    s1 = fmaf(w, d, s1);
+                    s2 = fmaf(w * d, d, s2);
+                }
+            }
+            const Sum3 z = block_sum3(Sum3{(double)s0, (double)s1, (double)s2}, lds);
+            // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
+            const double dm = z.b / z.a;
+            mu += dm;
+            const double var = fmax((z.c - z.b * dm) / n, 0.0);
+            sigma = fmax(sqrt(var), (double)floor_s);
+        }
+        if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
+            const float fmu = (float)mu, isg = (float)(1.0 / sigma);
+            float x2[kScalePerThread];
+#pragma unroll
+            for (int q = 0; q < kScalePerThread; ++q) {
+                const float x = (r[q] - fmu) * isg;
+                x2[q] = x * x;     // NaN stays NaN
+            }
+            auto f = [&](double nud) -> double {
+                const float nf = (float)nud;
+                float acc = 0.0f;
+#pragma unroll
+                for (int q = 0; q < kScalePerThread; ++q) {
+                    if (x2[q] == x2[q]) {
+                        const float w = (nf + 1.0f) / (nf + x2[q]);
+                        acc += 1.0f + logf(w) - w;
+                    }
+                }
+                const Sum3 z = block_sum3(Sum3{(double)acc, 0.0, 0.0}, lds);
+                const double c = -digamma_d(0.5 * nud) + log(0.5 * nud) +
+                                 digamma_d(0.5 * (nud + 1.0)) - log(0.5 * (nud + 1.0));
+                return n * c + z.a;
+            };
+            double nv;
+            if (f(10.0) > 0.0) nv = 10.0;
+            else if (f(2.0) < 0.0) nv = 2.0;
+            else {
+                double lo = 2.0, hi = 10.0;
+                for (int it = 0; it < 30; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (f(mid) > 0.0) lo = mid;
+                    else hi = mid;
+                }
+                nv = 0.5 * (lo + hi);
+            }
+            nu = (float)nv;
+        }
+    }
+    if (threadIdx.x == 0) {
+        S.mu[ch] = (float)mu;
+        S.sigma[ch] = (float)sigma;
+        S.nu[ch] = nu;
+        S.ns[ch] = (int)n;
+    }
+}
+
+// ------------------------------------------------------------------ k_reduce
+
+template <bool F16, int LOG2B, bool FUSED>
+__global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
+{
+    __shared__ float lds[8 * kNSum];
+    const int ci = chunk_of_block(blockIdx.x, L.n_red_chunks, L.tune.xcd_remap);
+    const Chunk ch = L.red_chunks[ci];
+    const PairState& S = L.states[ch.pair];
+    if (!S.active || S.level_stop) return;
+    const PairDesc& D = L.pairs[ch.pair];
+    const int l = L.level;
+    const LevelView& A = D.A[l];
+    const float ifx = 1.0f / A.fx, ify = 1.0f / A.fy;
+    const GridDim gd = level_grid(A);
+
+    const int kind = L.ip.weight;
+    const float kh = L.ip.huber_k;
+    const bool enI = S.ns[0] > 0, enW = S.ns[1] > 0;
+    const float muI = S.mu[0], isI = 1.0f / S.sigma[0], muW = S.mu[1], isW = 1.0f / S.sigma[1];
+    const float nuW = S.nu[1];
+    const float nuI = (kind == RGBID_W_STUDENT_T && L.ip.estimate_nu) ? fmaxf(S.nu[0], nuW) : S.nu[0];
+    const float wI0 = isI * isI, wW0 = isW * isW;
+
+    float acc[kNSum];
+#pragma unroll
+    for (int k = 0; k < kNSum; ++k) acc[k] = 0.0f;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int end = ch.first + ch.count;
+    for (int tile = ch.first + wave; tile < end; tile += waves) {
+        float Is = 0.0f, Ws = 0.0f;
+        bool wv = false;
+        int u = 0, v = 0, idx;
+        if constexpr (FUSED) {
+            const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
+            const Geom G = make_geom(S, D.A[wl], D.B[wl]);
+            warp_tile<F16, LOG2B>(G, tile * 64, gd.gw, gd.inv_gw, gd.n, 1, lane, Is, Ws, wv, u,
+                                  v, idx);
+        } else {
+            idx = tile * 64 + lane;
+            if (idx < gd.n) {
+                const float2 e = D.warped[idx];
+                Is = e.x;
+                Ws = e.y;
+                wv = Ws > 0.0f;
+                split_index(idx, gd.gw, gd.inv_gw, u, v);
+            }
+        }
+        if (idx >= gd.n) continue;
+        Terms T;
+        pixel_terms<F16, true>(A, ifx, ify, u, v, Is, Ws, wv, T);
+        if (T.vI && enI) {
+            const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
+            accum(acc, T.JI, w, T.rI);
+            acc[28] += 1.0f;
+        }
+        if (T.vW && enW) {
+            const float w = T.lam * omega(kind, (T.rW - muW) * isW, nuW, kh) * wW0;
+            accum(acc, T.JW, w, T.rW);
+            acc[29] += 1.0f;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kNSum; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kNSum; ++k) lds[wave * kNSum + k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kNSum) {
+        // compensated (two-sum) FP32 sum over the waves of the workgroup
+        float hi = 0.0f, lo = 0.0f;
+        for (int w = 0; w < waves; ++w) {
+            const float x = lds[w * kNSum + threadIdx.x];
+            const float s = hi + x;
+            const float bp = s - hi;
+            lo += (hi - (s - bp)) + (x - bp);
+            hi = s;
+        }
+        L.partials[(size_t)ci * kNSum + threadIdx.x] = make_float2(hi, lo);
+    }
+}
+
+// ------------------------------------------------------------------ k_solve
+
+// Rotation of the axis-angle vector th: cos|th| I + sin|th| [k]x +
+// (1 - cos|th|) k k^T with k = th/|th| (identity + [th]x + [th]x^2/2 for
+// |th| < 1e-8).
+__device__ void rot_of(const double th[3], double E[9])
+{
+    const double n = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    if (n < 1e-8) {
+        const double S[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s2 = 0;
+                for (int k = 0; k < 3; ++k) s2 += S[3 * i + k] * S[3 * k + j];
+                E[3 * i + j] = (i == j) + S[3 * i + j] + 0.5 * s2;
+            }
+        return;
+    }
+    const double k[3] = {th[0] / n, th[1] / n, th[2] / n};
+    const double c = cos(n), s = sin(n), oc = 1.0 - c;
+    E[0] = c + oc * k[0] * k[0];
+    E[1] = oc * k[0] * k[1] - s * k[2];
+    E[2] = oc * k[0] * k[2] + s * k[1];
+    E[3] = oc * k[1] * k[0] + s * k[2];
+    E[4] = c + oc * k[1] * k[1];
+    E[5] = oc * k[1] * k[2] - s * k[0];
+    E[6] = oc * k[2] * k[0] - s * k[1];
+    E[7] = oc * k[2] * k[1] + s * k[0];
+    E[8] = c + oc * k[2] * k[2];
+}
+
+__global__ void __launch_bounds__(64) k_solve(IterLaunch L)
+{
+    const int p = blockIdx.x;
+    PairState& S = L.states[p];
+    if (!S.active || S.level_stop) return;
+    const int lane = threadIdx.x;
+    const int beg = L.pair_red_begin[p], end = L.pair_red_begin[p + 1];
+    double s[kNSum];
+#pragma unroll
+    for (int k = 0; k < kNSum; ++k) s[k] = 0.0;
+    for (int c = beg + lane; c < end; c += 64) {
+        const float2* P = L.partials + (size_t)c * kNSum;
+#pragma unroll
+        for (int k = 0; k < kNSum; ++k) s[k] += (double)P[k].x + (double)P[k].y;
+    }
+#pragma unroll
+    for (int k = 0; k < kNSum; ++k) s[k] = wave_sum_d(s[k]);
+    if (lane != 0) return;
+
+    for (int k = 0; k < 21; ++k) S.H[k] = s[k];
+    for (int k = 0; k < 6; ++k) S.g[k] = s[21 + k];
+    S.cost = s[27];
+    S.nI = (long long)(s[28] + 0.5);
+    S.nW = (long long)(s[29] + 0.5);
+    if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) S.nu[0] = fmaxf(S.nu[0], S.nu[1]);
+    if (!L.update) return;
+
+    // 6x6 Cholesky of H (upper triangle, row-major) and xi = -H^-1 g
+    double A[6][6];
+    {
+        int k = 0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b) A[a][b] = A[b][a] = s[k++];
+    }
+    double dmax = 0.0;
+    for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A[a][a]);
+    bool ok = (S.nI + S.nW >= 6) && dmax > 0.0;
+    double Lm[6][6] = {};
+    for (int j = 0; j < 6 && ok; ++j) {
+        double d = A[j][j];
+        for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
+        if (!(d > 1e-12 * dmax)) {
+            ok = false;
+            break;
+        }
+        Lm[j][j] = sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double e = A[i][j];
+            for (int k = 0; k < j; ++k) e -= Lm[i][k] * Lm[j][k];
+            Lm[i][j] = e / Lm[j][j];
+        }
+    }
+    if (!ok) {
+        S.status = RGBID_E_DEGENERATE;
+        S.active = 0;
+        return;
+    }
+    double y[6], xi[6];
+    for (int i = 0; i < 6; ++i) {
+        double e = -s[21 + i];
+        for (int k = 0; k < i; ++k) e -= Lm[i][k] * y[k];
+        y[i] = e / Lm[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double e = y[i];
+        for (int k = i + 1; k < 6; ++k) e -= Lm[k][i] * xi[k];
+        xi[i] = e / Lm[i][i];
+    }
+    // T <- exp(xi)^-1 T = (E^T R, E^T (t - v))
+    double E[9];
+    rot_of(xi + 3, E);
+    double Rn[9], tn[3];
+    const double d[3] = {S.t[0] - xi[0], S.t[1] - xi[1], S.t[2] - xi[2]};
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            Rn[3 * i + j] = E[i] * S.R[j] + E[3 + i] * S.R[3 + j] + E[6 + i] * S.R[6 + j];
+        tn[i] = E[i] * d[0] + E[3 + i] * d[1] + E[6 + i] * d[2];
+    }
+    for (int k = 0; k < 9; ++k) S.R[k] = Rn[k];
+    for (int k = 0; k < 3; ++k) S.t[k] = tn[k];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) S.RT[3 * i + j] = (float)Rn[3 * j + i];
+        S.Rtt[i] = (float)(Rn[i] * tn[0] + Rn[3 + i] * tn[1] + Rn[6 + i] * tn[2]);
+    }
+    S.iters_done[L.level] += 1;
+    if (L.ip.stop_eps_t > 0.0 || L.ip.stop_eps_r > 0.0) {
+        const double nv = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+        const double nr = sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+        if (nv < L.ip.stop_eps_t && nr < L.ip.stop_eps_r) S.level_stop = 1;
+    }
+}
+
+__global__ void k_level_start(PairState* states, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) states[i].level_stop = 0;
+}
+
+template <bool F16, int LOG2B>
+hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L)
+{
+    const dim3 blk(64 * L.tune.waves);
+    if (L.n_warp_chunks > 0)
+        hipLaunchKernelGGL((k_warp<F16, LOG2B>), dim3(L.n_warp_chunks), blk, 0, s, L);
+    hipLaunchKernelGGL(k_scale, dim3(L.npairs, 2), dim3(kScaleThreads), 0, s, L);
+    if (L.n_red_chunks > 0) {
+        if (L.tune.fused)
+            hipLaunchKernelGGL((k_reduce<F16, LOG2B, true>), dim3(L.n_red_chunks), blk, 0, s, L);
+        else
+            hipLaunchKernelGGL((k_reduce<F16, LOG2B, false>), dim3(L.n_red_chunks), blk, 0, s, L);
+    }
+    hipLaunchKernelGGL(k_solve, dim3(L.npairs), dim3(64), 0, s, L);
+    return hipGetLastError();
+}
+
+template <bool F16>
+hipError_t launch_iteration_f(hipStream_t s, const IterLaunch& L)
+{
+    switch (L.block_log2) {
+    case 0: return launch_iteration_t<F16, 0>(s, L);
+    case 1: return launch_iteration_t<F16, 1>(s, L);
+    case 2: return launch_iteration_t<F16, 2>(s, L);
+    case 3: return launch_iteration_t<F16, 3>(s, L);
+    case 4: return launch_iteration_t<F16, 4>(s, L);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_iteration(hipStream_t s, const IterLaunch& L)
+{
+    if (L.tune.waves < 1 || L.tune.waves > 8) return hipErrorInvalidValue;
+    return L.f16 ? launch_iteration_f<true>(s, L) : launch_iteration_f<false>(s, L);
+}
+
+hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs)
+{
+    hipLaunchKernelGGL(k_level_start, dim3((npairs + 63) / 64), dim3(64), 0, s, states, npairs);
+    return hipGetLastError();
+}
+
+}  // namespace rgbid

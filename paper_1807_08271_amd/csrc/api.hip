@@ -1,0 +1,809 @@
+// C ABI of the library (include/rgbid.h): contexts, pyramids, the batched
+// coarse-to-fine alignment driver with HIP-graph replay, normal equations and
+// keyframe fusion.  All device work of the method runs in the kernels of
+// pyramid.hip, align.hip and fuse.hip; this file validates arguments, lays
+// out device tables and enqueues launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rgbid_internal.h"
+
+using namespace rgbid;
+
+struct rgbid_pyr {
+    int device;
+    rgbid_camera cam;
+    int levels;
+    int f16;
+    int w[kMaxLevels], h[kMaxLevels];
+    double fx[kMaxLevels], fy[kMaxLevels], cx[kMaxLevels], cy[kMaxLevels];
+    void* base;
+    void* iw[kMaxLevels];
+    void* wp[kMaxLevels];
+};
+
+struct rgbid_kf {
+    int device;
+    rgbid_camera cam;
+    float* W;
+    float* C;
+    unsigned long long* count;
+    void* base;
+};
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Launch tables of one batch shape, laid out in one device buffer.
+struct LevelTables {
+    size_t warp_off, red_off, begin_off;   // byte offsets into the table buffer
+    int n_warp, n_red;
+};
+
+}  // namespace
+
+struct rgbid_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;    // work stream (the caller's)
+    hipStream_t cap = nullptr;       // private stream for graph capture
+    std::string err;
+    DevBuf pairs, states, tables, partials, warped, sample, frames;
+    void* h_stage = nullptr;         // pinned upload staging
+    size_t h_stage_bytes = 0;
+    hipEvent_t stage_done = nullptr; // last upload from h_stage finished
+    void* h_down = nullptr;          // pinned download buffer
+    size_t h_down_bytes = 0;
+    int generation = 0;              // bumps when a workspace buffer moves
+    bool use_graphs = true;
+    std::map<std::string, std::pair<int, hipGraphExec_t>> graphs;
+    std::map<std::string, LevelTune> tunes;   // per (level shape) launch shape
+};
+
+namespace {
+
+rgbid_status set_err(rgbid_ctx* c, rgbid_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return set_err((ctx), e_ == hipErrorOutOfMemory ? RGBID_E_NOMEM : RGBID_E_DEVICE,   \
+                           "%s failed: %s", #expr, hipGetErrorString(e_));                     \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+rgbid_status ensure(rgbid_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (b.bytes >= bytes) return RGBID_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (b.p) HIPCHK(c, hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    const size_t nb = align_up(bytes + bytes / 4, 4096);
+    HIPCHK(c, hipMalloc(&b.p, nb));
+    b.bytes = nb;
+    c->generation++;
+    return RGBID_OK;
+}
+
+// Host staging for uploads: one region per call; the next call waits for the
+// previous upload to have left the pinned buffer.
+rgbid_status stage_begin(rgbid_ctx* c, size_t bytes, char** out)
+{
+    HIPCHK(c, hipEventSynchronize(c->stage_done));
+    if (c->h_stage_bytes < bytes) {
+        if (c->h_stage) HIPCHK(c, hipHostFree(c->h_stage));
+        c->h_stage = nullptr;
+        c->h_stage_bytes = 0;
+        const size_t nb = align_up(bytes + bytes / 4, 4096);
+        HIPCHK(c, hipHostMalloc(&c->h_stage, nb, hipHostMallocDefault));
+        c->h_stage_bytes = nb;
+    }
+    *out = static_cast<char*>(c->h_stage);
+    return RGBID_OK;
+}
+
+rgbid_status stage_end(rgbid_ctx* c)
+{
+    HIPCHK(c, hipEventRecord(c->stage_done, c->stream));
+    return RGBID_OK;
+}
+
+rgbid_status ensure_down(rgbid_ctx* c, size_t bytes)
+{
+    if (c->h_down_bytes >= bytes) return RGBID_OK;
+    if (c->h_down) HIPCHK(c, hipHostFree(c->h_down));
+    c->h_down = nullptr;
+    c->h_down_bytes = 0;
+    const size_t nb = align_up(bytes + bytes / 4, 4096);
+    HIPCHK(c, hipHostMalloc(&c->h_down, nb, hipHostMallocDefault));
+    c->h_down_bytes = nb;
+    return RGBID_OK;
+}
+
+// Smallest stride s >= 1 whose sample grid ceil(w/s) x ceil(h/s) has at most
+// nmax pixels (systematic sample of maximum size N, sec. 6.3).
+int sample_stride(int w, int h, int nmax)
+{
+    int s = 1;
+    while ((long long)((w + s - 1) / s) * ((h + s - 1) / s) > nmax) ++s;
+    return s;
+}
+
+void level_camera(const rgbid_camera& c0, int l, double& fx, double& fy, double& cx, double& cy)
+{
+    const double s = std::ldexp(1.0, -l);
+    fx = c0.fx * s;
+    fy = c0.fy * s;
+    cx = (c0.cx + 0.5) * s - 0.5;
+    cy = (c0.cy + 0.5) * s - 0.5;
+}
+
+LevelTune default_tune(int block_log2)
+{
+    LevelTune t;
+    if (block_log2 == 0) {
+        t.fused = 1;
+        t.waves = 4;
+        t.tiles_per_wave = 4;
+    } else {
+        t.fused = 0;
+        t.waves = 4;
+        t.tiles_per_wave = 2;
+    }
+    t.xcd_remap = 1;
+    return t;
+}
+
+void pose_floats(const double R[9], const double t[3], float RT[9], float Rtt[3])
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) RT[3 * i + j] = (float)R[3 * j + i];
+        Rtt[i] = (float)(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
+    }
+}
+
+bool params_ok(const rgbid_align_params* p, std::string& why)
+{
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->levels < 1 || p->levels > kMaxLevels) { why = "levels outside 1..8"; return false; }
+    for (int l = 0; l < p->levels; ++l)
+        if (p->iters[l] < 0 || p->iters[l] > 10000) { why = "iters outside 0..10000"; return false; }
+    if (p->weight != RGBID_W_STUDENT_T && p->weight != RGBID_W_HUBER) { why = "unknown weight"; return false; }
+    if (!(p->huber_k > 0.0)) { why = "huber_k must be > 0"; return false; }
+    if (p->sample_max < 1 || p->sample_max > kMaxSample) { why = "sample_max outside 1..24576"; return false; }
+    if (p->scale_iters < 0 || p->scale_iters > 1000) { why = "scale_iters outside 0..1000"; return false; }
+    if (p->warp != RGBID_WARP_FULLRES && p->warp != RGBID_WARP_PER_LEVEL) { why = "unknown warp mode"; return false; }
+    if (p->warp == RGBID_WARP_FULLRES && p->levels > 5) { why = "FULLRES warp supports at most 5 levels"; return false; }
+    if (p->stop_eps_t < 0 || p->stop_eps_r < 0) { why = "negative stop epsilon"; return false; }
+    return true;
+}
+
+struct Step {
+    int level;
+    int iters;
+};
+
+// The batched driver: n pairs, a schedule of (level, iterations), update on
+// or off.  Writes poses and stats (host) and returns OK unless an argument or
+// the device failed.
+rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                       const rgbid_pose* init, const rgbid_align_params* P,
+                       const std::vector<Step>& sched, int update, rgbid_pose* out,
+                       rgbid_align_stats* stats)
+{
+    if (!c) return RGBID_E_ARG;
+    if (n < 1 || !A || !B) return set_err(c, RGBID_E_ARG, "need n >= 1 and pyramid arrays");
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    const int f16 = A[0] ? A[0]->f16 : 0;
+    for (int i = 0; i < n; ++i) {
+        if (!A[i] || !B[i]) return set_err(c, RGBID_E_ARG, "pyramid %d is NULL", i);
+        if (A[i]->device != c->device || B[i]->device != c->device)
+            return set_err(c, RGBID_E_ARG, "pyramid %d lives on another device", i);
+        if (A[i]->w[0] != B[i]->w[0] || A[i]->h[0] != B[i]->h[0] || A[i]->f16 != B[i]->f16)
+            return set_err(c, RGBID_E_SHAPE, "pair %d: A and B differ in size or format", i);
+        if (A[i]->cam.fx != B[i]->cam.fx || A[i]->cam.fy != B[i]->cam.fy ||
+            A[i]->cam.cx != B[i]->cam.cx || A[i]->cam.cy != B[i]->cam.cy)
+            return set_err(c, RGBID_E_SHAPE, "pair %d: A and B have different cameras", i);
+        if (A[i]->levels < P->levels || B[i]->levels < P->levels)
+            return set_err(c, RGBID_E_SHAPE, "pair %d: pyramid has fewer levels than params", i);
+        if (A[i]->f16 != f16)
+            return set_err(c, RGBID_E_SHAPE, "all pyramids of a batch need one storage format");
+    }
+    const int L = P->levels;
+    const bool fullres = P->warp == RGBID_WARP_FULLRES;
+
+    // ---- launch shapes and tables
+    LevelTune tune[kMaxLevels];
+    std::vector<int> stride(n * L), sw(n * L), sh(n * L);
+    std::vector<std::vector<Chunk>> wch(L), rch(L);
+    std::vector<std::vector<int>> rbeg(L);
+    size_t max_red = 0, warped_per_pair_total = 0;
+    std::vector<size_t> warped_off(n, 0);
+    for (int l = 0; l < L; ++l) {
+        const int b = fullres ? l : 0;
+        char key[96];
+        snprintf(key, sizeof key, "w%d_h%d_l%d_m%d_f%d", A[0]->w[0], A[0]->h[0], l, P->warp, f16);
+        auto it = c->tunes.find(key);
+        tune[l] = it != c->tunes.end() ? it->second : default_tune(b);
+        const int lpp = std::min(1 << (2 * b), 64), gpp = 64 / lpp;
+        const int wtiles_per_chunk = tune[l].waves * tune[l].tiles_per_wave;
+        rbeg[l].push_back(0);
+        for (int i = 0; i < n; ++i) {
+            const int w = A[i]->w[l], h = A[i]->h[l];
+            const int s = sample_stride(w, h, P->sample_max);
+            stride[i * L + l] = s;
+            sw[i * L + l] = (w + s - 1) / s;
+            sh[i * L + l] = (h + s - 1) / s;
+            const long long ngrid = tune[l].fused ? (long long)sw[i * L + l] * sh[i * L + l]
+                                                  : (long long)w * h;
+            const long long wt = (ngrid + gpp - 1) / gpp;
+            for (long long t = 0; t < wt; t += wtiles_per_chunk)
+                wch[l].push_back(Chunk{i, (int)t, (int)std::min<long long>(wtiles_per_chunk, wt - t)});
+            const long long rt = ((long long)w * h + 63) / 64;
+            for (long long t = 0; t < rt; t += wtiles_per_chunk)
+                rch[l].push_back(Chunk{i, (int)t, (int)std::min<long long>(wtiles_per_chunk, rt - t)});
+            rbeg[l].push_back((int)rch[l].size());
+        }
+        max_red = std::max(max_red, rch[l].size());
+    }
+    for (int i = 0; i < n; ++i) {
+        size_t need = 0;
+        for (int l = 0; l < L; ++l)
+            if (!tune[l].fused) need = std::max(need, (size_t)A[i]->w[l] * A[i]->h[l]);
+        warped_off[i] = warped_per_pair_total;
+        warped_per_pair_total += align_up(need, 64);
+    }
+
+    // ---- workspace
+    rgbid_status st;
+    size_t tbytes = 0;
+    std::vector<LevelTables> lt(L);
+    for (int l = 0; l < L; ++l) {
+        lt[l].warp_off = tbytes;
+        tbytes = align_up(tbytes + wch[l].size() * sizeof(Chunk), 256);
+        lt[l].red_off = tbytes;
+        tbytes = align_up(tbytes + rch[l].size() * sizeof(Chunk), 256);
+        lt[l].begin_off = tbytes;
+        tbytes = align_up(tbytes + rbeg[l].size() * sizeof(int), 256);
+        lt[l].n_warp = (int)wch[l].size();
+        lt[l].n_red = (int)rch[l].size();
+    }
+    if ((st = ensure(c, c->pairs, n * sizeof(PairDesc))) != RGBID_OK) return st;
+    if ((st = ensure(c, c->states, n * sizeof(PairState))) != RGBID_OK) return st;
+    if ((st = ensure(c, c->tables, tbytes)) != RGBID_OK) return st;
+    if ((st = ensure(c, c->partials, std::max<size_t>(1, max_red) * kNSum * sizeof(float2))) != RGBID_OK) return st;
+    if ((st = ensure(c, c->warped, std::max<size_t>(1, warped_per_pair_total) * sizeof(float2))) != RGBID_OK) return st;
+    if ((st = ensure(c, c->sample, (size_t)n * P->sample_max * sizeof(float2))) != RGBID_OK) return st;
+
+    // ---- host tables
+    const size_t pairs_bytes = n * sizeof(PairDesc), states_bytes = n * sizeof(PairState);
+    char* stage;
+    if ((st = stage_begin(c, pairs_bytes + states_bytes + tbytes, &stage)) != RGBID_OK) return st;
+    PairDesc* pd = reinterpret_cast<PairDesc*>(stage);
+    PairState* ps = reinterpret_cast<PairState*>(stage + pairs_bytes);
+    char* tb = stage + pairs_bytes + states_bytes;
+    std::memset(stage, 0, pairs_bytes + states_bytes + tbytes);
+    for (int i = 0; i < n; ++i) {
+        PairDesc& d = pd[i];
+        for (int l = 0; l < L; ++l) {
+            const rgbid_pyr* Pa = A[i];
+            const rgbid_pyr* Pb = B[i];
+            d.A[l] = LevelView{Pa->iw[l], Pa->wp[l], Pa->w[l], Pa->h[l], (float)Pa->fx[l],
+                               (float)Pa->fy[l], (float)Pa->cx[l], (float)Pa->cy[l]};
+            d.B[l] = LevelView{Pb->iw[l], Pb->wp[l], Pb->w[l], Pb->h[l], (float)Pb->fx[l],
+                               (float)Pb->fy[l], (float)Pb->cx[l], (float)Pb->cy[l]};
+            d.stride[l] = stride[i * L + l];
+            d.sw[l] = sw[i * L + l];
+            d.sh[l] = sh[i * L + l];
+        }
+        d.warped = static_cast<float2*>(c->warped.p) + warped_off[i];
+        d.sample = static_cast<float2*>(c->sample.p) + (size_t)i * P->sample_max;
+        PairState& s = ps[i];
+        if (init) {
+            std::memcpy(s.R, init[i].R, sizeof s.R);
+            std::memcpy(s.t, init[i].t, sizeof s.t);
+        } else {
+            s.R[0] = s.R[4] = s.R[8] = 1.0;
+        }
+        pose_floats(s.R, s.t, s.RT, s.Rtt);
+        s.status = RGBID_OK;
+        s.active = 1;
+        s.sigma[0] = s.sigma[1] = 1.0f;
+        s.nu[0] = s.nu[1] = 5.0f;
+    }
+    for (int l = 0; l < L; ++l) {
+        std::memcpy(tb + lt[l].warp_off, wch[l].data(), wch[l].size() * sizeof(Chunk));
+        std::memcpy(tb + lt[l].red_off, rch[l].data(), rch[l].size() * sizeof(Chunk));
+        std::memcpy(tb + lt[l].begin_off, rbeg[l].data(), rbeg[l].size() * sizeof(int));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->pairs.p, pd, pairs_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->states.p, ps, states_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->tables.p, tb, tbytes, hipMemcpyHostToDevice, c->stream));
+    if ((st = stage_end(c)) != RGBID_OK) return st;
+
+    // ---- enqueue (directly or through a cached graph)
+    IterParams ip;
+    ip.weight = P->weight;
+    ip.huber_k = (float)P->huber_k;
+    ip.estimate_nu = P->estimate_nu;
+    ip.scale_iters = P->scale_iters;
+    ip.warp_mode = P->warp;
+    ip.stop_eps_t = P->stop_eps_t;
+    ip.stop_eps_r = P->stop_eps_r;
+    auto enqueue = [&](hipStream_t s) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (const Step& stp : sched) {
+            const int l = stp.level;
+            if ((e = launch_level_start(s, static_cast<PairState*>(c->states.p), n)) != hipSuccess)
+                return e;
+            IterLaunch il;
+            il.pairs = static_cast<const PairDesc*>(c->pairs.p);
+            il.states = static_cast<PairState*>(c->states.p);
+            il.npairs = n;
+            il.level = l;
+            il.ip = ip;
+            il.tune = tune[l];
+            il.f16 = f16;
+            il.block_log2 = fullres ? l : 0;
+            char* tbase = static_cast<char*>(c->tables.p);
+            il.warp_chunks = reinterpret_cast<const Chunk*>(tbase + lt[l].warp_off);
+            il.n_warp_chunks = lt[l].n_warp;
+            il.red_chunks = reinterpret_cast<const Chunk*>(tbase + lt[l].red_off);
+            il.n_red_chunks = lt[l].n_red;
+            il.pair_red_begin = reinterpret_cast<const int*>(tbase + lt[l].begin_off);
+            il.partials = static_cast<float2*>(c->partials.p);
+            il.update = update;
+            for (int it = 0; it < stp.iters; ++it)
+                if ((e = launch_iteration(s, il)) != hipSuccess) return e;
+        }
+        return e;
+    };
+    if (c->use_graphs) {
+        std::string key;
+        {
+            char buf[160];
+            snprintf(buf, sizeof buf, "n%d f%d u%d L%d g%d|", n, f16, update, L, c->generation);
+            key = buf;
+            for (int i = 0; i < n; ++i) {
+                snprintf(buf, sizeof buf, "%dx%d,", A[i]->w[0], A[i]->h[0]);
+                key += buf;
+            }
+            key += "|";
+            for (const Step& stp : sched) {
+                snprintf(buf, sizeof buf, "%d:%d,", stp.level, stp.iters);
+                key += buf;
+            }
+            key.append(reinterpret_cast<const char*>(&ip), sizeof ip);
+            key.append(reinterpret_cast<const char*>(tune), sizeof(LevelTune) * L);
+        }
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue(c->cap);
+            hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return set_err(c, RGBID_E_DEVICE, "graph capture failed: %s",
+                               hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return set_err(c, RGBID_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+            if (c->graphs.size() > 64) {
+                for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
+                c->graphs.clear();
+            }
+            it = c->graphs.emplace(key, std::make_pair(c->generation, ex)).first;
+        }
+        HIPCHK(c, hipGraphLaunch(it->second.second, c->stream));
+    } else {
+        HIPCHK(c, enqueue(c->stream));
+    }
+
+    // ---- results
+    if ((st = ensure_down(c, states_bytes)) != RGBID_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->h_down, c->states.p, states_bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const PairState* res = static_cast<const PairState*>(c->h_down);
+    for (int i = 0; i < n; ++i) {
+        const PairState& s = res[i];
+        if (out) {
+            std::memcpy(out[i].R, s.R, sizeof s.R);
+            std::memcpy(out[i].t, s.t, sizeof s.t);
+        }
+        if (stats) {
+            rgbid_align_stats& o = stats[i];
+            std::memcpy(o.H, s.H, sizeof o.H);
+            std::memcpy(o.g, s.g, sizeof o.g);
+            o.mu_I = s.mu[0];
+            o.sigma_I = s.sigma[0];
+            o.nu_I = s.nu[0];
+            o.mu_W = s.mu[1];
+            o.sigma_W = s.sigma[1];
+            o.nu_W = s.nu[1];
+            o.cost = s.cost;
+            o.n_valid_I = s.nI;
+            o.n_valid_W = s.nW;
+            for (int l = 0; l < 8; ++l) o.iters_done[l] = l < kMaxLevels ? s.iters_done[l] : 0;
+            o.status = s.status;
+        }
+    }
+    return RGBID_OK;
+}
+
+rgbid_status build_pyramids(rgbid_ctx* c, int n, rgbid_pyr* const* pyrs, const float* const* I,
+                            const float* const* W, const size_t* pitch)
+{
+    rgbid_status st;
+    if ((st = ensure(c, c->frames, n * sizeof(PyrFrame))) != RGBID_OK) return st;
+    char* stage;
+    if ((st = stage_begin(c, n * sizeof(PyrFrame), &stage)) != RGBID_OK) return st;
+    PyrFrame* fr = reinterpret_cast<PyrFrame*>(stage);
+    int levels = 0, mw[kMaxLevels] = {0}, mh[kMaxLevels] = {0};
+    for (int i = 0; i < n; ++i) {
+        const rgbid_pyr* p = pyrs[i];
+        PyrFrame& f = fr[i];
+        std::memset(&f, 0, sizeof f);
+        f.I = I[i];
+        f.W = W[i];
+        f.pitch = (long long)pitch[i];
+        f.levels = p->levels;
+        for (int l = 0; l < p->levels; ++l) {
+            f.iw[l] = p->iw[l];
+            f.wp[l] = p->wp[l];
+            f.w[l] = p->w[l];
+            f.h[l] = p->h[l];
+            mw[l] = std::max(mw[l], p->w[l]);
+            mh[l] = std::max(mh[l], p->h[l]);
+        }
+        levels = std::max(levels, p->levels);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->frames.p, fr, n * sizeof(PyrFrame), hipMemcpyHostToDevice, c->stream));
+    if ((st = stage_end(c)) != RGBID_OK) return st;
+    HIPCHK(c, launch_pyramid(c->stream, static_cast<const PyrFrame*>(c->frames.p), n, levels,
+                             pyrs[0]->f16, mw, mh));
+    return RGBID_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void rgbid_default_params(rgbid_align_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->levels = 4;
+    for (int l = 0; l < 8; ++l) p->iters[l] = 10;
+    p->weight = RGBID_W_HUBER;
+    p->huber_k = 1.345;
+    p->estimate_nu = 1;
+    p->sample_max = 19200;
+    p->scale_iters = 20;
+    p->warp = RGBID_WARP_FULLRES;
+}
+
+rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream)
+{
+    if (!ctx) return RGBID_E_ARG;
+    *ctx = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RGBID_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return RGBID_E_DEVICE;
+    rgbid_ctx* c = new (std::nothrow) rgbid_ctx();
+    if (!c) return RGBID_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return RGBID_E_DEVICE;
+    }
+    const char* g = std::getenv("RGBID_NO_GRAPH");
+    c->use_graphs = !(g && g[0] == '1');
+    *ctx = c;
+    return RGBID_OK;
+}
+
+void rgbid_destroy(rgbid_ctx* c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
+    for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
+                      &c->frames})
+        if (b->p) hipFree(b->p);
+    if (c->h_stage) hipHostFree(c->h_stage);
+    if (c->h_down) hipHostFree(c->h_down);
+    if (c->stage_done) hipEventDestroy(c->stage_done);
+    if (c->cap) hipStreamDestroy(c->cap);
+    delete c;
+}
+
+const char* rgbid_last_error(const rgbid_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rgbid_format storage,
+                           const float* I_dev, const float* W_dev, size_t pitch_elems,
+                           rgbid_pyr** out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out) return set_err(c, RGBID_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cam || !I_dev || !W_dev) return set_err(c, RGBID_E_ARG, "NULL camera or image");
+    if (levels < 1 || levels > kMaxLevels) return set_err(c, RGBID_E_ARG, "levels outside 1..8");
+    if (storage != RGBID_F32 && storage != RGBID_F16) return set_err(c, RGBID_E_ARG, "unknown storage");
+    if (cam->width < 1 || cam->height < 1 || pitch_elems < (size_t)cam->width)
+        return set_err(c, RGBID_E_ARG, "bad image size or pitch");
+    if ((long long)cam->width * cam->height >= (1ll << 24))
+        return set_err(c, RGBID_E_ARG, "images of 2^24 pixels or more are not supported");
+    if (!(cam->fx > 0 && cam->fy > 0)) return set_err(c, RGBID_E_ARG, "focal lengths must be > 0");
+    if ((cam->width >> (levels - 1)) < 1 || (cam->height >> (levels - 1)) < 1)
+        return set_err(c, RGBID_E_ARG, "level %d would be empty", levels - 1);
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_pyr* p = new (std::nothrow) rgbid_pyr();
+    if (!p) return set_err(c, RGBID_E_NOMEM, "host allocation failed");
+    p->device = c->device;
+    p->cam = *cam;
+    p->levels = levels;
+    p->f16 = storage == RGBID_F16;
+    const size_t e_iw = p->f16 ? 4 : 8, e_wp = p->f16 ? 2 : 4;
+    size_t off[2 * kMaxLevels], total = 0;
+    for (int l = 0; l < levels; ++l) {
+        p->w[l] = cam->width >> l;
+        p->h[l] = cam->height >> l;
+        level_camera(*cam, l, p->fx[l], p->fy[l], p->cx[l], p->cy[l]);
+        const size_t np = (size_t)p->w[l] * p->h[l];
+        off[2 * l] = total;
+        total = align_up(total + np * e_iw, 256);
+        off[2 * l + 1] = total;
+        total = align_up(total + np * e_wp, 256);
+    }
+    hipError_t e = hipMalloc(&p->base, total);
+    if (e != hipSuccess) {
+        delete p;
+        return set_err(c, RGBID_E_NOMEM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+    }
+    for (int l = 0; l < levels; ++l) {
+        p->iw[l] = static_cast<char*>(p->base) + off[2 * l];
+        p->wp[l] = static_cast<char*>(p->base) + off[2 * l + 1];
+    }
+    rgbid_pyr* const arr[1] = {p};
+    const float* const Is[1] = {I_dev};
+    const float* const Ws[1] = {W_dev};
+    const size_t pt[1] = {pitch_elems};
+    rgbid_status st = build_pyramids(c, 1, arr, Is, Ws, pt);
+    if (st != RGBID_OK) {
+        hipFree(p->base);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_pyramid_update(rgbid_ctx* c, rgbid_pyr* pyr, const float* I_dev,
+                                  const float* W_dev, size_t pitch_elems)
+{
+    rgbid_pyr* const arr[1] = {pyr};
+    const float* const Is[1] = {I_dev};
+    const float* const Ws[1] = {W_dev};
+    const size_t pt[1] = {pitch_elems};
+    return rgbid_pyramid_update_batch(c, 1, arr, Is, Ws, pt);
+}
+
+rgbid_status rgbid_pyramid_update_batch(rgbid_ctx* c, int n, rgbid_pyr* const* pyrs,
+                                        const float* const* I_dev, const float* const* W_dev,
+                                        const size_t* pitch_elems)
+{
+    if (!c) return RGBID_E_ARG;
+    if (n < 1 || !pyrs || !I_dev || !W_dev || !pitch_elems)
+        return set_err(c, RGBID_E_ARG, "need n >= 1 and non-NULL arrays");
+    for (int i = 0; i < n; ++i) {
+        if (!pyrs[i] || !I_dev[i] || !W_dev[i]) return set_err(c, RGBID_E_ARG, "NULL entry %d", i);
+        if (pyrs[i]->device != c->device) return set_err(c, RGBID_E_ARG, "pyramid on another device");
+        if (pitch_elems[i] < (size_t)pyrs[i]->w[0]) return set_err(c, RGBID_E_ARG, "pitch < width");
+        if (pyrs[i]->f16 != pyrs[0]->f16) return set_err(c, RGBID_E_SHAPE, "mixed storage formats");
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    return build_pyramids(c, n, pyrs, I_dev, W_dev, pitch_elems);
+}
+
+rgbid_status rgbid_pyramid_read(rgbid_ctx* c, const rgbid_pyr* p, int level, float* I_out,
+                                float* W_out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!p || level < 0 || level >= p->levels) return set_err(c, RGBID_E_ARG, "bad pyramid or level");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_level_read(c->stream, p->iw[level], p->w[level] * p->h[level], p->f16, I_out, W_out));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_pyramid_level_size(const rgbid_pyr* p, int level, int* w, int* h)
+{
+    if (!p || level < 0 || level >= p->levels) return RGBID_E_ARG;
+    if (w) *w = p->w[level];
+    if (h) *h = p->h[level];
+    return RGBID_OK;
+}
+
+void rgbid_pyramid_free(rgbid_pyr* p)
+{
+    if (!p) return;
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    hipFree(p->base);
+    delete p;
+}
+
+rgbid_status rgbid_align_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
+                               const rgbid_pyr* const* B, const rgbid_pose* init,
+                               const rgbid_align_params* P, rgbid_pose* out,
+                               rgbid_align_stats* stats)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out) return set_err(c, RGBID_E_ARG, "out is NULL");
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<Step> sched;
+    for (int l = P->levels - 1; l >= 0; --l)
+        if (P->iters[l] > 0) sched.push_back(Step{l, P->iters[l]});
+    return run_batch(c, n, A, B, init, P, sched, 1, out, stats);
+}
+
+rgbid_status rgbid_align(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B,
+                         const rgbid_pose* init, const rgbid_align_params* P, rgbid_pose* out,
+                         rgbid_align_stats* stats)
+{
+    if (!c) return RGBID_E_ARG;
+    rgbid_align_stats s;
+    const rgbid_pyr* const a[1] = {A};
+    const rgbid_pyr* const b[1] = {B};
+    rgbid_status st = rgbid_align_batch(c, 1, a, b, init, P, out, &s);
+    if (st != RGBID_OK) return st;
+    if (stats) *stats = s;
+    if (s.status != RGBID_OK)
+        return set_err(c, (rgbid_status)s.status, "alignment stopped: degenerate normal equations");
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_normal_equations(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B, int level,
+                                    const rgbid_pose* T, const rgbid_align_params* P,
+                                    rgbid_align_stats* out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out || !T) return set_err(c, RGBID_E_ARG, "NULL pose or output");
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    if (level < 0 || level >= P->levels) return set_err(c, RGBID_E_ARG, "level outside 0..levels-1");
+    HIPCHK(c, hipSetDevice(c->device));
+    const rgbid_pyr* const a[1] = {A};
+    const rgbid_pyr* const b[1] = {B};
+    std::vector<Step> sched{Step{level, 1}};
+    rgbid_pose o;
+    return run_batch(c, 1, a, b, T, P, sched, 0, &o, out);
+}
+
+rgbid_status rgbid_keyframe_init(rgbid_ctx* c, const rgbid_camera* cam, const float* W_dev,
+                                 size_t pitch_elems, rgbid_kf** out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out) return set_err(c, RGBID_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cam || !W_dev) return set_err(c, RGBID_E_ARG, "NULL camera or image");
+    if (cam->width < 1 || cam->height < 1 || pitch_elems < (size_t)cam->width)
+        return set_err(c, RGBID_E_ARG, "bad image size or pitch");
+    if (!(cam->fx > 0 && cam->fy > 0)) return set_err(c, RGBID_E_ARG, "focal lengths must be > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_kf* k = new (std::nothrow) rgbid_kf();
+    if (!k) return set_err(c, RGBID_E_NOMEM, "host allocation failed");
+    k->device = c->device;
+    k->cam = *cam;
+    const size_t np = (size_t)cam->width * cam->height;
+    const size_t bytes = align_up(np * 4, 256) * 2 + 256;
+    hipError_t e = hipMalloc(&k->base, bytes);
+    if (e != hipSuccess) {
+        delete k;
+        return set_err(c, RGBID_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
+    k->W = static_cast<float*>(k->base);
+    k->C = reinterpret_cast<float*>(static_cast<char*>(k->base) + align_up(np * 4, 256));
+    k->count = reinterpret_cast<unsigned long long*>(static_cast<char*>(k->base) +
+                                                     2 * align_up(np * 4, 256));
+    e = launch_copy_valid(c->stream, W_dev, (long long)pitch_elems, cam->width, cam->height, k->W);
+    if (e == hipSuccess) e = launch_fill(c->stream, k->C, (int)np, 1.0f);
+    if (e != hipSuccess) {
+        hipFree(k->base);
+        delete k;
+        return set_err(c, RGBID_E_DEVICE, "keyframe init failed: %s", hipGetErrorString(e));
+    }
+    *out = k;
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_fuse(rgbid_ctx* c, rgbid_kf* kf, const float* Wk_dev, size_t pitch_elems,
+                        const rgbid_pose* T, double tol, long long* n_fused)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!kf || !Wk_dev || !T) return set_err(c, RGBID_E_ARG, "NULL keyframe, image or pose");
+    if (kf->device != c->device) return set_err(c, RGBID_E_ARG, "keyframe on another device");
+    if (pitch_elems < (size_t)kf->cam.width) return set_err(c, RGBID_E_ARG, "pitch < width");
+    if (!(tol > 0.0)) return set_err(c, RGBID_E_ARG, "tol must be > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    FuseArgs a;
+    a.Wkf = kf->W;
+    a.Ckf = kf->C;
+    a.Wk = Wk_dev;
+    a.pitch = (long long)pitch_elems;
+    a.w = kf->cam.width;
+    a.h = kf->cam.height;
+    a.fx = (float)kf->cam.fx;
+    a.fy = (float)kf->cam.fy;
+    a.cx = (float)kf->cam.cx;
+    a.cy = (float)kf->cam.cy;
+    pose_floats(T->R, T->t, a.RT, a.Rtt);
+    a.tol = (float)tol;
+    a.count = n_fused ? kf->count : nullptr;
+    if (n_fused) HIPCHK(c, hipMemsetAsync(kf->count, 0, sizeof(unsigned long long), c->stream));
+    HIPCHK(c, launch_fuse(c->stream, a));
+    if (n_fused) {
+        rgbid_status st;
+        if ((st = ensure_down(c, sizeof(unsigned long long))) != RGBID_OK) return st;
+        HIPCHK(c, hipMemcpyAsync(c->h_down, kf->count, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *n_fused = (long long)*static_cast<unsigned long long*>(c->h_down);
+    }
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_keyframe_read(rgbid_ctx* c, const rgbid_kf* kf, float* W_out, float* C_out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!kf) return set_err(c, RGBID_E_ARG, "NULL keyframe");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t bytes = (size_t)kf->cam.width * kf->cam.height * sizeof(float);
+    if (W_out) HIPCHK(c, hipMemcpyAsync(W_out, kf->W, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (C_out) HIPCHK(c, hipMemcpyAsync(C_out, kf->C, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return RGBID_OK;
+}
+
+void rgbid_keyframe_free(rgbid_kf* kf)
+{
+    if (!kf) return;
+    hipSetDevice(kf->device);
+    hipDeviceSynchronize();
+    hipFree(kf->base);
+    delete kf;
+}
+
+}  // extern "C"

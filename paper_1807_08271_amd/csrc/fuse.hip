@@ -1,0 +1,123 @@
+// Keyframe inverse-depth fusion (sec. 7.2) by reverse warping (sec. 5.3).
+// One thread per keyframe pixel; each keyframe pixel is read and written by
+// exactly one thread, so no atomics touch the maps.  The covisibility check
+// is the one of sec. 6.4: the transferred inverse depth 1/Y_z must agree with
+// the frame's bilinear inverse depth within tol.
+#include "rgbid_internal.h"
+
+namespace rgbid {
+namespace {
+
+__device__ __forceinline__ bool w_valid(float w) { return w > 0.0f && w < INFINITY; }
+
+__global__ void __launch_bounds__(256) k_fuse(FuseArgs a)
+{
+    __shared__ unsigned int wave_counts[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool fused = false;
+    if (i < a.w * a.h) {
+        const int v = i / a.w, u = i - v * a.w;
+        const float wkf = a.Wkf[i];
+        if (w_valid(wkf)) {
+            const float rx = ((float)u - a.cx) / a.fx, ry = ((float)v - a.cy) / a.fy;
+            const float ax = fmaf(a.RT[0], rx, fmaf(a.RT[1], ry, a.RT[2]));
+            const float ay = fmaf(a.RT[3], rx, fmaf(a.RT[4], ry, a.RT[5]));
+            const float az = fmaf(a.RT[6], rx, fmaf(a.RT[7], ry, a.RT[8]));
+            // W_kf * Y with Y = R^T (x / W_kf - t)
+            const float yx = fmaf(-wkf, a.Rtt[0], ax), yy = fmaf(-wkf, a.Rtt[1], ay);
+            const float yz = fmaf(-wkf, a.Rtt[2], az);
+            if (yz > 0.0f) {
+                const float iz = 1.0f / yz;
+                const float ub = fmaf(a.fx * yx, iz, a.cx), vb = fmaf(a.fy * yy, iz, a.cy);
+                if (ub >= -0.5f && ub < (float)a.w - 0.5f && vb >= -0.5f && vb < (float)a.h - 0.5f) {
+                    const float fu = floorf(ub), fv = floorf(vb);
+                    const float al = ub - fu, be = vb - fv;
+                    int x0 = (int)fu, y0 = (int)fv;
+                    const int x1 = min(x0 + 1, a.w - 1), y1 = min(y0 + 1, a.h - 1);
+                    x0 = max(x0, 0);
+                    y0 = max(y0, 0);
+                    const float p00 = a.Wk[(long long)y0 * a.pitch + x0];
+                    const float p10 = a.Wk[(long long)y0 * a.pitch + x1];
+                    const float p01 = a.Wk[(long long)y1 * a.pitch + x0];
+                    const float p11 = a.Wk[(long long)y1 * a.pitch + x1];
+                    if (w_valid(p00) && w_valid(p10) && w_valid(p01) && w_valid(p11)) {
+                        const float wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 +
+                                         (1.0f - al) * be * p01 + al * be * p11;
+                        // predicted inverse depth in frame k: 1 / Y_z = W_kf / yz
+                        const float wk = wkf * iz;
+                        if (fabsf(wb - wk) < a.tol) {
+                            const float den = fmaf(wb, a.Rtt[2], 1.0f);
+                            const float ws = az * wb / den;
+                            const float q = den * den / az;
+                            const float ck = q * q;
+                            if (w_valid(ws) && ck > 0.0f && ck < INFINITY) {
+                                const float ckf = a.Ckf[i];
+                                a.Wkf[i] = (wkf * ckf + ck * ws) / (ckf + ck);
+                                a.Ckf[i] = ckf + ck;
+                                fused = true;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (a.count) {
+        const unsigned long long bal = __ballot(fused);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) wave_counts[wave] = (unsigned int)__popcll(bal);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned int n = wave_counts[0] + wave_counts[1] + wave_counts[2] + wave_counts[3];
+            if (n) atomicAdd(a.count, (unsigned long long)n);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fuse(hipStream_t s, const FuseArgs& a)
+{
+    const int n = a.w * a.h;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fuse, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace rgbid
+
+namespace rgbid {
+namespace {
+__global__ void __launch_bounds__(256) k_fill(float* p, int n, float v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void __launch_bounds__(256) k_copy_valid(const float* src, long long pitch, int w, int h,
+                                                   float* dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= w * h) return;
+    const int v = i / w, u = i - v * w;
+    const float x = src[(long long)v * pitch + u];
+    dst[i] = (x > 0.0f && x < INFINITY) ? x : 0.0f;
+}
+}  // namespace
+
+hipError_t launch_fill(hipStream_t s, float* p, int n, float v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_valid(hipStream_t s, const float* src, long long pitch, int w, int h,
+                             float* dst)
+{
+    const int n = w * h;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_valid, dim3((n + 255) / 256), dim3(256), 0, s, src, pitch, w, h, dst);
+    return hipGetLastError();
+}
+
+}  // namespace rgbid

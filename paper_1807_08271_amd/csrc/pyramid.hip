@@ -1,0 +1,119 @@
+// Image pyramid of {I, W} (sec. 6.2: the reference images are downsampled at
+// every level).  Level 0 is the caller's FP32 image converted to the storage
+// format; level l+1 is the 2x2 mean of level l, where the inverse-depth mean
+// skips holes and is a hole when all four children are holes.
+//
+// Layout per level: an interleaved (I, W) array (float2 / __half2), used for
+// bilinear gathers of the current frame and for stencils of the reference,
+// plus a separate W plane (float / __half) for the full-resolution warp,
+// which reads only W of the reference.
+#include "rgbid_internal.h"
+
+namespace rgbid {
+namespace {
+
+__device__ __forceinline__ bool w_valid(float w) { return w > 0.0f && w < INFINITY; }
+
+template <bool F16>
+__device__ __forceinline__ float2 load_iw(const void* p, int i)
+{
+    if constexpr (F16) return __half22float2(static_cast<const __half2*>(p)[i]);
+    else return static_cast<const float2*>(p)[i];
+}
+
+template <bool F16>
+__device__ __forceinline__ void store_level(void* iw, void* wp, int i, float I, float W)
+{
+    if constexpr (F16) {
+        __half2 h = __floats2half2_rn(I, W);
+        static_cast<__half2*>(iw)[i] = h;
+        static_cast<__half*>(wp)[i] = __high2half(h);
+    } else {
+        static_cast<float2*>(iw)[i] = make_float2(I, W);
+        static_cast<float*>(wp)[i] = W;
+    }
+}
+
+template <bool F16>
+__global__ void __launch_bounds__(256) k_level0(const PyrFrame* __restrict__ frames)
+{
+    const PyrFrame& f = frames[blockIdx.y];
+    const int w = f.w[0], h = f.h[0];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= w * h) return;
+    const int v = i / w, u = i - v * w;
+    const long long src = (long long)v * f.pitch + u;
+    const float I = f.I[src];
+    float W = f.W[src];
+    if (!w_valid(W)) W = 0.0f;
+    store_level<F16>(f.iw[0], f.wp[0], i, I, W);
+}
+
+template <bool F16>
+__global__ void __launch_bounds__(256) k_down(const PyrFrame* __restrict__ frames, int level)
+{
+    const PyrFrame& f = frames[blockIdx.y];
+    if (level >= f.levels) return;
+    const int w = f.w[level], h = f.h[level];
+    const int ws = f.w[level - 1];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= w * h) return;
+    const int v = i / w, u = i - v * w;
+    const void* src = f.iw[level - 1];
+    const int r0 = (2 * v) * ws + 2 * u, r1 = r0 + ws;
+    // children in the order (0,0), (1,0), (0,1), (1,1)
+    const float2 c0 = load_iw<F16>(src, r0), c1 = load_iw<F16>(src, r0 + 1);
+    const float2 c2 = load_iw<F16>(src, r1), c3 = load_iw<F16>(src, r1 + 1);
+    const float I = (((c0.x + c1.x) + c2.x) + c3.x) * 0.25f;
+    float sw = 0.0f;
+    int n = 0;
+    if (w_valid(c0.y)) { sw += c0.y; ++n; }
+    if (w_valid(c1.y)) { sw += c1.y; ++n; }
+    if (w_valid(c2.y)) { sw += c2.y; ++n; }
+    if (w_valid(c3.y)) { sw += c3.y; ++n; }
+    const float W = n ? sw / (float)n : 0.0f;
+    store_level<F16>(f.iw[level], f.wp[level], i, I, W);
+}
+
+template <bool F16>
+__global__ void __launch_bounds__(256) k_read(const void* __restrict__ iw, int n, float* I, float* W)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 p = load_iw<F16>(iw, i);
+    if (I) I[i] = p.x;
+    if (W) W[i] = p.y;
+}
+
+}  // namespace
+
+hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes, int levels,
+                          int f16, const int* max_w, const int* max_h)
+{
+    if (nframes <= 0) return hipSuccess;
+    {
+        const int n = max_w[0] * max_h[0];
+        dim3 grid((n + 255) / 256, nframes);
+        if (f16) hipLaunchKernelGGL(k_level0<true>, grid, dim3(256), 0, s, frames_dev);
+        else hipLaunchKernelGGL(k_level0<false>, grid, dim3(256), 0, s, frames_dev);
+    }
+    for (int l = 1; l < levels; ++l) {
+        const int n = max_w[l] * max_h[l];
+        if (n <= 0) break;
+        dim3 grid((n + 255) / 256, nframes);
+        if (f16) hipLaunchKernelGGL(k_down<true>, grid, dim3(256), 0, s, frames_dev, l);
+        else hipLaunchKernelGGL(k_down<false>, grid, dim3(256), 0, s, frames_dev, l);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_level_read(hipStream_t s, const void* iw, int n, int f16, float* I, float* W)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((n + 255) / 256);
+    if (f16) hipLaunchKernelGGL(k_read<true>, grid, dim3(256), 0, s, iw, n, I, W);
+    else hipLaunchKernelGGL(k_read<false>, grid, dim3(256), 0, s, iw, n, I, W);
+    return hipGetLastError();
+}
+
+}  // namespace rgbid

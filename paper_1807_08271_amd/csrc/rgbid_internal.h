@@ -1,0 +1,139 @@
+// Internal declarations of the gfx950 RGB-D alignment library: device-side
+// tables, per-pair state and the host launchers of each kernel family.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rgbid.h"
+
+namespace rgbid {
+
+constexpr int kMaxLevels = 8;
+constexpr int kWave = 64;
+// 21 unique entries of H, 6 of g, cost, and the two valid-pixel counts.
+constexpr int kNSum = 30;
+constexpr int kScaleThreads = 1024;
+constexpr int kScalePerThread = 24;   // sample_max <= 24576
+constexpr int kMaxSample = kScaleThreads * kScalePerThread;
+
+// One pyramid level as the kernels see it.
+struct LevelView {
+    const void* iw;   // interleaved (I, W): float2 or __half2, w*h, dense rows
+    const void* wp;   // W plane: float or __half, w*h
+    int w, h;
+    float fx, fy, cx, cy;
+};
+
+// Everything a kernel needs to know about one pair; uploaded per call.
+struct PairDesc {
+    LevelView A[kMaxLevels];
+    LevelView B[kMaxLevels];
+    float2* warped;                 // store mode: warped (I*, W*) of the level grid
+    float2* sample;                 // sample residuals (r_I, r_W), NaN = invalid
+    int stride[kMaxLevels];         // systematic-sample stride per level
+    int sw[kMaxLevels], sh[kMaxLevels];
+};
+
+// Per-pair iteration state, resident in device memory for a whole alignment.
+struct PairState {
+    double R[9], t[3];              // current estimate of T_A^B
+    double H[21], g[6], cost;       // last linearisation
+    long long nI, nW;
+    float RT[9];                    // R^T, row-major (FP32 copy for the warp)
+    float Rtt[3];                   // R^T t
+    float mu[2], sigma[2], nu[2];   // channel 0 = intensity, 1 = inverse depth
+    int ns[2];                      // valid sample sizes
+    int iters_done[kMaxLevels];
+    int status;                     // rgbid_status
+    int active;                     // 1 while the pair iterates
+    int level_stop;                 // early stop reached at the current level
+    int pad;
+};
+
+// A contiguous range of 64-pixel tiles of one pair's grid.
+struct Chunk {
+    int pair;
+    int first;
+    int count;
+};
+
+// Kernel-visible constants of one alignment call.
+struct IterParams {
+    int weight;          // rgbid_weight
+    float huber_k;
+    int estimate_nu;
+    int scale_iters;
+    int warp_mode;       // rgbid_warp_mode
+    double stop_eps_t, stop_eps_r;
+};
+
+// Launch shape of one level (picked by the autotuner or the defaults).
+struct LevelTune {
+    int fused;           // 1: reduce kernel warps itself; 0: warped images stored
+    int waves;           // waves per workgroup of the pixel kernels
+    int tiles_per_wave;  // tiles each wave walks
+    int xcd_remap;       // map consecutive chunks onto one XCD
+};
+
+// ---------------------------------------------------------------- launchers
+
+// One frame of a (batched) pyramid build.  Level 0 is read from the caller's
+// FP32 images; level l+1 is built from level l.
+struct PyrFrame {
+    const float* I;
+    const float* W;
+    long long pitch;                // elements
+    void* iw[kMaxLevels];
+    void* wp[kMaxLevels];
+    int w[kMaxLevels], h[kMaxLevels];
+    int levels;
+    int pad;
+};
+hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes, int levels,
+                          int f16, const int* max_w, const int* max_h);
+hipError_t launch_level_read(hipStream_t s, const void* iw, int n, int f16, float* I, float* W);
+
+// One Gauss-Newton iteration (or one linearisation without update) for all
+// pairs of a batch at `level`.
+struct IterLaunch {
+    const PairDesc* pairs;
+    PairState* states;
+    int npairs;
+    int level;
+    IterParams ip;
+    LevelTune tune;
+    int f16;
+    int block_log2;          // FULLRES: level (2^level children per side); PER_LEVEL: 0
+    const Chunk* warp_chunks;
+    int n_warp_chunks;
+    const Chunk* red_chunks;
+    int n_red_chunks;
+    const int* pair_red_begin;   // npairs + 1
+    float2* partials;            // n_red_chunks * kNSum
+    int update;                  // 0: normal equations only
+};
+hipError_t launch_iteration(hipStream_t s, const IterLaunch& L);
+hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs);
+
+struct FuseArgs {
+    float* Wkf;
+    float* Ckf;
+    const float* Wk;
+    long long pitch;
+    int w, h;
+    float fx, fy, cx, cy;
+    float RT[9];          // R^T of the pose of frame k in the keyframe
+    float Rtt[3];         // R^T t
+    float tol;
+    unsigned long long* count;
+};
+hipError_t launch_fuse(hipStream_t s, const FuseArgs& a);
+hipError_t launch_fill(hipStream_t s, float* p, int n, float v);
+// Dense copy of a pitched inverse-depth map with holes normalised to 0.
+hipError_t launch_copy_valid(hipStream_t s, const float* src, long long pitch, int w, int h,
+                             float* dst);
+
+}  // namespace rgbid

@@ -1,0 +1,325 @@
+"""ctypes binding of librgbid.so, the gfx950 dense RGB-D alignment library.
+
+Names mirror the C ABI in include/rgbid.h.  The binding only marshals
+arguments: torch tensors supply device memory (``data_ptr()``) and the HIP
+stream; every step of the method runs in the library's HIP kernels.  If the
+library is not built, loading raises immediately (there is no fallback).
+
+Poses are ``(R, t)`` numpy tuples, the pose of B in A (X_A = R X_B + t).
+Cameras are ``(width, height, fx, fy, cx, cy)`` tuples or objects with
+``as_tuple()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librgbid.so")
+
+RGBID_OK, RGBID_E_ARG, RGBID_E_SHAPE, RGBID_E_DEVICE, RGBID_E_NOMEM, RGBID_E_DEGENERATE = (
+    0, -1, -2, -3, -4, -5)
+RGBID_F32, RGBID_F16 = 0, 1
+RGBID_W_STUDENT_T, RGBID_W_HUBER = 0, 1
+RGBID_WARP_FULLRES, RGBID_WARP_PER_LEVEL = 0, 1
+
+_STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_DEVICE", -4: "E_NOMEM",
+                 -5: "E_DEGENERATE"}
+
+
+class RgbidError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class rgbid_camera(C.Structure):
+    _fields_ = [("width", C.c_int), ("height", C.c_int), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class rgbid_pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class rgbid_align_params(C.Structure):
+    _fields_ = [("levels", C.c_int), ("iters", C.c_int * 8), ("weight", C.c_int),
+                ("huber_k", C.c_double), ("estimate_nu", C.c_int), ("sample_max", C.c_int),
+                ("scale_iters", C.c_int), ("warp", C.c_int), ("stop_eps_t", C.c_double),
+                ("stop_eps_r", C.c_double)]
+
+
+class rgbid_align_stats(C.Structure):
+    _fields_ = [("H", C.c_double * 21), ("g", C.c_double * 6), ("mu_I", C.c_double),
+                ("sigma_I", C.c_double), ("nu_I", C.c_double), ("mu_W", C.c_double),
+                ("sigma_W", C.c_double), ("nu_W", C.c_double), ("cost", C.c_double),
+                ("n_valid_I", C.c_longlong), ("n_valid_W", C.c_longlong),
+                ("iters_done", C.c_int * 8), ("status", C.c_int)]
+
+    def as_dict(self):
+        H = np.zeros((6, 6))
+        k = 0
+        for a in range(6):
+            for b in range(a, 6):
+                H[a, b] = H[b, a] = self.H[k]
+                k += 1
+        return dict(H=H, g=np.array(self.g[:]), mu_I=self.mu_I, sigma_I=self.sigma_I,
+                    nu_I=self.nu_I, mu_W=self.mu_W, sigma_W=self.sigma_W, nu_W=self.nu_W,
+                    cost=self.cost, n_valid_I=self.n_valid_I, n_valid_W=self.n_valid_W,
+                    iters_done=list(self.iters_done[:]), status=self.status)
+
+
+_lib = None
+
+# Every exported entry point with (restype, argtypes).
+_P = C.c_void_p
+_SIGS = {
+    "rgbid_default_params": (None, [C.POINTER(rgbid_align_params)]),
+    "rgbid_create": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "rgbid_destroy": (None, [_P]),
+    "rgbid_last_error": (C.c_char_p, [_P]),
+    "rgbid_pyramid": (C.c_int, [_P, C.POINTER(rgbid_camera), C.c_int, C.c_int, _P, _P, C.c_size_t,
+                                C.POINTER(_P)]),
+    "rgbid_pyramid_update": (C.c_int, [_P, _P, _P, _P, C.c_size_t]),
+    "rgbid_pyramid_update_batch": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                             C.POINTER(_P), C.POINTER(C.c_size_t)]),
+    "rgbid_pyramid_read": (C.c_int, [_P, _P, C.c_int, _P, _P]),
+    "rgbid_pyramid_level_size": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "rgbid_pyramid_free": (None, [_P]),
+    "rgbid_align": (C.c_int, [_P, _P, _P, C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
+                              C.POINTER(rgbid_pose), C.POINTER(rgbid_align_stats)]),
+    "rgbid_align_batch": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                    C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
+                                    C.POINTER(rgbid_pose), C.POINTER(rgbid_align_stats)]),
+    "rgbid_normal_equations": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(rgbid_pose),
+                                         C.POINTER(rgbid_align_params),
+                                         C.POINTER(rgbid_align_stats)]),
+    "rgbid_keyframe_init": (C.c_int, [_P, C.POINTER(rgbid_camera), _P, C.c_size_t, C.POINTER(_P)]),
+    "rgbid_fuse": (C.c_int, [_P, _P, _P, C.c_size_t, C.POINTER(rgbid_pose), C.c_double,
+                             C.POINTER(C.c_longlong)]),
+    "rgbid_keyframe_read": (C.c_int, [_P, _P, _P, _P]),
+    "rgbid_keyframe_free": (None, [_P]),
+}
+
+
+def lib():
+    """Loads librgbid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librgbid.so is not built: run `python -m paper_1807_08271_amd.build`"
+                               " (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+# ----------------------------------------------------------------- helpers
+
+
+def _cam(cam) -> rgbid_camera:
+    if isinstance(cam, rgbid_camera):
+        return cam
+    w, h, fx, fy, cx, cy = cam.as_tuple() if hasattr(cam, "as_tuple") else cam
+    return rgbid_camera(int(w), int(h), float(fx), float(fy), float(cx), float(cy))
+
+
+def make_pose(R=None, t=None) -> rgbid_pose:
+    p = rgbid_pose()
+    R = np.eye(3) if R is None else np.asarray(R, dtype=np.float64).reshape(9)
+    t = np.zeros(3) if t is None else np.asarray(t, dtype=np.float64).reshape(3)
+    for i in range(9):
+        p.R[i] = float(np.ravel(R)[i])
+    for i in range(3):
+        p.t[i] = float(t[i])
+    return p
+
+
+def pose_tuple(p: rgbid_pose):
+    return np.array(p.R[:]).reshape(3, 3), np.array(p.t[:])
+
+
+def _check(ctx, rc, allow=()):
+    if rc != RGBID_OK and rc not in allow:
+        raise RgbidError(rc, rgbid_last_error(ctx))
+    return rc
+
+
+def _img(t):
+    """(pointer, pitch in elements) of a 2-D float32 device tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.dtype != torch.float32:
+        raise TypeError("expected a 2-D float32 torch tensor")
+    if not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if t.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    return C.c_void_p(t.data_ptr()), int(t.stride(0))
+
+
+# ----------------------------------------------------------------- ABI
+
+
+def rgbid_default_params(**overrides) -> rgbid_align_params:
+    p = rgbid_align_params()
+    lib().rgbid_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if k == "iters":
+            its = list(v) + [0] * (8 - len(v))
+            for i in range(8):
+                p.iters[i] = int(its[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def rgbid_create(device: int = 0, stream=None):
+    """stream: a torch stream, a raw hipStream_t int, or None for torch's
+    current stream on `device`."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    ctx = C.c_void_p()
+    rc = lib().rgbid_create(C.byref(ctx), int(device), C.c_void_p(handle))
+    if rc != RGBID_OK:
+        raise RgbidError(rc, "rgbid_create failed")
+    return ctx
+
+
+def rgbid_destroy(ctx):
+    lib().rgbid_destroy(ctx)
+
+
+def rgbid_last_error(ctx) -> str:
+    s = lib().rgbid_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def rgbid_pyramid(ctx, cam, levels: int, storage: int, I, W):
+    pI, pitch = _img(I)
+    pW, pitchW = _img(W)
+    if pitch != pitchW:
+        raise ValueError("I and W need the same row pitch")
+    out = C.c_void_p()
+    c = _cam(cam)
+    _check(ctx, lib().rgbid_pyramid(ctx, C.byref(c), int(levels), int(storage), pI, pW, pitch,
+                                    C.byref(out)))
+    return out
+
+
+def rgbid_pyramid_update(ctx, pyr, I, W):
+    pI, pitch = _img(I)
+    pW, _ = _img(W)
+    _check(ctx, lib().rgbid_pyramid_update(ctx, pyr, pI, pW, pitch))
+
+
+def rgbid_pyramid_update_batch(ctx, pyrs, Is, Ws):
+    n = len(pyrs)
+    arr = (C.c_void_p * n)(*[p.value for p in pyrs])
+    pis, pws, pts = [], [], []
+    for I, W in zip(Is, Ws):
+        a, pitch = _img(I)
+        b, _ = _img(W)
+        pis.append(a.value)
+        pws.append(b.value)
+        pts.append(pitch)
+    _check(ctx, lib().rgbid_pyramid_update_batch(ctx, n, arr, (C.c_void_p * n)(*pis),
+                                                 (C.c_void_p * n)(*pws),
+                                                 (C.c_size_t * n)(*pts)))
+
+
+def rgbid_pyramid_level_size(pyr, level: int):
+    w, h = C.c_int(), C.c_int()
+    rc = lib().rgbid_pyramid_level_size(pyr, int(level), C.byref(w), C.byref(h))
+    if rc != RGBID_OK:
+        raise RgbidError(rc, "bad pyramid or level")
+    return w.value, h.value
+
+
+def rgbid_pyramid_read(ctx, pyr, level: int, device=None):
+    import torch
+    w, h = rgbid_pyramid_level_size(pyr, level)
+    I = torch.empty((h, w), dtype=torch.float32, device=device or "cuda")
+    W = torch.empty((h, w), dtype=torch.float32, device=device or "cuda")
+    _check(ctx, lib().rgbid_pyramid_read(ctx, pyr, int(level), C.c_void_p(I.data_ptr()),
+                                         C.c_void_p(W.data_ptr())))
+    return I, W
+
+
+def rgbid_pyramid_free(pyr):
+    lib().rgbid_pyramid_free(pyr)
+
+
+def rgbid_align(ctx, A, B, params: rgbid_align_params, init=None):
+    """Returns (R, t, stats dict, status); E_DEGENERATE is reported in status."""
+    out = rgbid_pose()
+    st = rgbid_align_stats()
+    ini = make_pose(*init) if init is not None else None
+    rc = lib().rgbid_align(ctx, A, B, C.byref(ini) if ini is not None else None, C.byref(params),
+                           C.byref(out), C.byref(st))
+    _check(ctx, rc, allow=(RGBID_E_DEGENERATE,))
+    R, t = pose_tuple(out)
+    return R, t, st.as_dict(), rc
+
+
+def rgbid_align_batch(ctx, As, Bs, params: rgbid_align_params, inits=None):
+    """Returns (list of (R, t), list of stats dicts)."""
+    n = len(As)
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    ini = None
+    if inits is not None:
+        ini = (rgbid_pose * n)(*[make_pose(*x) for x in inits])
+    out = (rgbid_pose * n)()
+    st = (rgbid_align_stats * n)()
+    _check(ctx, lib().rgbid_align_batch(ctx, n, a, b, ini, C.byref(params), out, st))
+    return [pose_tuple(out[i]) for i in range(n)], [st[i].as_dict() for i in range(n)]
+
+
+def rgbid_normal_equations(ctx, A, B, level: int, T, params: rgbid_align_params):
+    st = rgbid_align_stats()
+    pose = make_pose(*T)
+    _check(ctx, lib().rgbid_normal_equations(ctx, A, B, int(level), C.byref(pose), C.byref(params),
+                                             C.byref(st)))
+    return st.as_dict()
+
+
+def rgbid_keyframe_init(ctx, cam, W):
+    pW, pitch = _img(W)
+    out = C.c_void_p()
+    c = _cam(cam)
+    _check(ctx, lib().rgbid_keyframe_init(ctx, C.byref(c), pW, pitch, C.byref(out)))
+    return out
+
+
+def rgbid_fuse(ctx, kf, Wk, T, tol: float, count: bool = True):
+    pW, pitch = _img(Wk)
+    pose = make_pose(*T)
+    n = C.c_longlong(0)
+    _check(ctx, lib().rgbid_fuse(ctx, kf, pW, pitch, C.byref(pose), float(tol),
+                                 C.byref(n) if count else None))
+    return n.value if count else None
+
+
+def rgbid_keyframe_read(ctx, kf, shape, device=None):
+    import torch
+    h, w = shape
+    W = torch.empty((h, w), dtype=torch.float32, device=device or "cuda")
+    Cm = torch.empty((h, w), dtype=torch.float32, device=device or "cuda")
+    _check(ctx, lib().rgbid_keyframe_read(ctx, kf, C.c_void_p(W.data_ptr()), C.c_void_p(Cm.data_ptr())))
+    return W, Cm
+
+
+def rgbid_keyframe_free(kf):
+    lib().rgbid_keyframe_free(kf)

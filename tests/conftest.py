@@ -18,3 +18,27 @@ def _oracle_built():
     import oracle
     oracle.build(force=False)
     yield
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """A library context on cuda:0 (GPU tests only)."""
+    import torch
+    from paper_1807_08271_amd import rgbid
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = rgbid.rgbid_create(0)
+    yield c
+    torch.cuda.synchronize()
+    rgbid.rgbid_destroy(c)
+
+
+@pytest.fixture(scope="session")
+def c1_pairs():
+    import synth
+    return [synth.pair_c1(i) for i in range(3)]
+
+
+@pytest.fixture(scope="session")
+def c2_pairs():
+    import synth
+    return [synth.pair_c2(i, ss=2) for i in range(2)]

@@ -1,0 +1,30 @@
+"""The C-ABI library loads and exports every entry point include/rgbid.h
+declares (no device calls: runs without a GPU)."""
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rgbid.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rgbid_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1807_08271_amd import rgbid
+    lib = rgbid.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(rgbid.exported_symbols())
+
+
+def test_default_params():
+    from paper_1807_08271_amd import rgbid
+    p = rgbid.rgbid_default_params()
+    assert p.levels == 4 and list(p.iters)[:4] == [10] * 4
+    assert p.weight == rgbid.RGBID_W_HUBER and abs(p.huber_k - 1.345) < 1e-15
+    assert p.sample_max == 19200 and p.scale_iters == 20 and p.warp == rgbid.RGBID_WARP_FULLRES

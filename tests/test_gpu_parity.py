@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (the targets of this build):
+  normal equations  |dH_ij| <= 1e-4 sqrt(H_ii H_jj), |dg_i| <= 1e-4 sqrt(H_ii cost),
+                    valid counts within 20 threshold flips;
+  poses             <= 1e-5 rad and <= 1e-5 m after the same schedule;
+  fused W           <= 1e-5 relative where both sides take the same
+                    covisibility decision.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _parity import check_normal_equations, rot_err, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _rg():
+    from paper_1807_08271_amd import rgbid
+    return rgbid
+
+
+def _pyr(ctx, cam, levels, frame, storage=0):
+    rg = _rg()
+    I, W = upload(frame.I, frame.W)
+    return rg.rgbid_pyramid(ctx, cam, levels, storage, I, W)
+
+
+def _params(levels, iters, weight="huber", warp="fullres", **kw):
+    rg = _rg()
+    return rg.rgbid_default_params(
+        levels=levels, iters=iters,
+        weight=rg.RGBID_W_HUBER if weight == "huber" else rg.RGBID_W_STUDENT_T,
+        warp=rg.RGBID_WARP_FULLRES if warp == "fullres" else rg.RGBID_WARP_PER_LEVEL, **kw)
+
+
+def _oparams(levels, iters, weight="huber", warp="fullres", storage="f32", **kw):
+    return oracle.Params(levels=levels, iters=iters, weight=weight, warp=warp, storage=storage, **kw)
+
+
+# ----------------------------------------------------------------- pyramid
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_pyramid_matches_oracle(ctx, c2_pairs, storage):
+    rg = _rg()
+    p = c2_pairs[0]
+    I0, W0 = p.A.I, p.A.W
+    if storage == 1:
+        I0, W0 = synth.to_fp16_grid(I0), synth.to_fp16_grid(W0)
+    pyr = _pyr(ctx, p.cam, 4, p.A, storage)
+    ref = oracle.pyramid(p.cam, 4, I0, W0, storage="f16" if storage else "f32")
+    for l in range(4):
+        Ig, Wg = rg.rgbid_pyramid_read(ctx, pyr, l)
+        Ig, Wg = Ig.cpu().numpy(), Wg.cpu().numpy()
+        Ir, Wr = ref[l]
+        assert Ig.shape == Ir.shape
+        np.testing.assert_array_equal(Wg > 0, Wr > 0)
+        if storage == 0:
+            np.testing.assert_allclose(Ig, Ir, rtol=2e-7, atol=0)
+            np.testing.assert_allclose(Wg, Wr, rtol=2e-7, atol=0)
+        else:
+            # FP16 levels: identical rounding except rare double-rounding ties
+            assert np.mean(Ig != Ir) < 1e-3 and np.mean(Wg != Wr) < 1e-3
+            np.testing.assert_allclose(Wg, Wr, rtol=1e-3)
+    rg.rgbid_pyramid_free(pyr)
+
+
+# ----------------------------------------------------------------- normal equations
+
+
+@pytest.mark.parametrize("weight", ["huber", "student_t"])
+@pytest.mark.parametrize("warp", ["fullres", "per_level"])
+def test_normal_equations_c2_all_levels(ctx, c2_pairs, weight, warp):
+    rg = _rg()
+    p = c2_pairs[1]
+    A = _pyr(ctx, p.cam, 4, p.A)
+    B = _pyr(ctx, p.cam, 4, p.B)
+    # a pose between identity and the truth
+    th = oracle.log_so3(p.R) * 0.6
+    R = oracle.exp_so3(th)
+    t = p.t * 0.6
+    gp = _params(4, [1] * 4, weight, warp)
+    op = _oparams(4, [1] * 4, weight, warp)
+    for level in range(4):
+        g = rg.rgbid_normal_equations(ctx, A, B, level, (R, t), gp)
+        r = oracle.normal_equations_at(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, level, R, t, op)
+        check_normal_equations(g, r, what="c2 %s %s level %d" % (weight, warp, level))
+        assert g["sigma_I"] == pytest.approx(r["sigma_I"], rel=1e-4)
+        assert g["sigma_W"] == pytest.approx(r["sigma_W"], rel=1e-4)
+        if weight == "student_t":
+            assert g["nu_I"] == pytest.approx(r["nu_I"], abs=1e-3)
+            assert g["nu_W"] == pytest.approx(r["nu_W"], abs=1e-3)
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+def test_normal_equations_identity_zero_gradient(ctx, c1_pairs):
+    # B = A at the identity: residuals vanish, so g ~ 0 and the step is ~0.
+    rg = _rg()
+    p = c1_pairs[0]
+    A = _pyr(ctx, p.cam, 1, p.A)
+    g = rg.rgbid_normal_equations(ctx, A, A, 0, (np.eye(3), np.zeros(3)), _params(1, [1]))
+    xi = np.linalg.solve(g["H"], -g["g"])
+    assert np.abs(xi).max() < 1e-6
+    assert g["n_valid_I"] > 0.9 * 158 * 118
+    rg.rgbid_pyramid_free(A)
+
+
+# ----------------------------------------------------------------- alignment
+
+
+@pytest.mark.parametrize("i", [0, 1, 2])
+def test_align_c1_matches_oracle(ctx, c1_pairs, i):
+    rg = _rg()
+    p = c1_pairs[i]
+    A = _pyr(ctx, p.cam, 1, p.A)
+    B = _pyr(ctx, p.cam, 1, p.B)
+    R, t, st, rc = rg.rgbid_align(ctx, A, B, _params(1, [10]))
+    Ro, to, sto = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(1, [10]))
+    assert rc == 0 and sto["status"] == 0
+    assert st["iters_done"][0] == 10
+    assert rot_err(R, Ro) <= 1e-5, rot_err(R, Ro)
+    assert np.linalg.norm(t - to) <= 1e-5, np.linalg.norm(t - to)
+    # and the estimate is near the truth (noise-limited)
+    assert rot_err(R, p.R) < 2e-3 and np.linalg.norm(t - p.t) < 5e-3
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+@pytest.mark.parametrize("warp", ["fullres", "per_level"])
+@pytest.mark.parametrize("weight", ["huber", "student_t"])
+def test_align_c2_matches_oracle(ctx, c2_pairs, warp, weight):
+    rg = _rg()
+    p = c2_pairs[0]
+    A = _pyr(ctx, p.cam, 4, p.A)
+    B = _pyr(ctx, p.cam, 4, p.B)
+    R, t, st, rc = rg.rgbid_align(ctx, A, B, _params(4, [10] * 4, weight, warp))
+    Ro, to, sto = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W,
+                               _oparams(4, [10] * 4, weight, warp))
+    assert rc == 0 and sto["status"] == 0
+    assert st["iters_done"][:4] == [10, 10, 10, 10]
+    assert rot_err(R, Ro) <= 1e-5, rot_err(R, Ro)
+    assert np.linalg.norm(t - to) <= 1e-5, np.linalg.norm(t - to)
+    assert rot_err(R, p.R) < 1e-3 and np.linalg.norm(t - p.t) < 2e-3
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+def test_align_fp16_storage_matches_oracle_on_rounded_inputs(ctx, c2_pairs):
+    rg = _rg()
+    p = c2_pairs[1]
+    A = _pyr(ctx, p.cam, 4, p.A, storage=1)
+    B = _pyr(ctx, p.cam, 4, p.B, storage=1)
+    R, t, st, rc = rg.rgbid_align(ctx, A, B, _params(4, [10] * 4))
+    h = synth.to_fp16_grid
+    Ro, to, _ = oracle.align(p.cam, h(p.A.I), h(p.A.W), h(p.B.I), h(p.B.W),
+                             _oparams(4, [10] * 4, storage="f16"))
+    assert rc == 0
+    assert rot_err(R, Ro) <= 1e-5 and np.linalg.norm(t - to) <= 1e-5
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+def test_align_initial_guess(ctx, c1_pairs):
+    rg = _rg()
+    p = c1_pairs[1]
+    A = _pyr(ctx, p.cam, 1, p.A)
+    B = _pyr(ctx, p.cam, 1, p.B)
+    R, t, st, rc = rg.rgbid_align(ctx, A, B, _params(1, [3]), init=(p.R, p.t))
+    Ro, to, _ = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(1, [3]), R0=p.R, t0=p.t)
+    assert rot_err(R, Ro) <= 1e-5 and np.linalg.norm(t - to) <= 1e-5
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+def test_align_batch_mixed_sizes_equals_single(ctx, c1_pairs, c2_pairs):
+    rg = _rg()
+    pairs = [c2_pairs[0], c1_pairs[0], c2_pairs[1], c1_pairs[2]]
+    As = [_pyr(ctx, p.cam, 3, p.A) for p in pairs]
+    Bs = [_pyr(ctx, p.cam, 3, p.B) for p in pairs]
+    prm = _params(3, [5, 5, 5])
+    poses, stats = rg.rgbid_align_batch(ctx, As, Bs, prm)
+    for i, p in enumerate(pairs):
+        R1, t1, _, _ = rg.rgbid_align(ctx, As[i], Bs[i], prm)
+        np.testing.assert_array_equal(poses[i][0], R1)     # deterministic reduction order
+        np.testing.assert_array_equal(poses[i][1], t1)
+        Ro, to, _ = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(3, [5, 5, 5]))
+        assert rot_err(poses[i][0], Ro) <= 1e-5 and np.linalg.norm(poses[i][1] - to) <= 1e-5
+        assert stats[i]["status"] == 0
+    for x in As + Bs:
+        rg.rgbid_pyramid_free(x)
+
+
+def test_align_is_deterministic(ctx, c2_pairs):
+    rg = _rg()
+    p = c2_pairs[0]
+    A = _pyr(ctx, p.cam, 4, p.A)
+    B = _pyr(ctx, p.cam, 4, p.B)
+    prm = _params(4, [10] * 4)
+    a = rg.rgbid_align(ctx, A, B, prm)
+    b = rg.rgbid_align(ctx, A, B, prm)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2]["H"], b[2]["H"])
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+# ----------------------------------------------------------------- edge cases
+
+
+def test_degenerate_all_holes(ctx):
+    rg = _rg()
+    import torch
+    cam = (64, 48, 60.0, 60.0, 31.5, 23.5)
+    I = torch.rand(48, 64, device="cuda") * 255
+    W = torch.zeros(48, 64, device="cuda")
+    A = rg.rgbid_pyramid(ctx, cam, 2, 0, I, W)
+    R, t, st, rc = rg.rgbid_align(ctx, A, A, _params(2, [3, 3]))
+    assert rc == rg.RGBID_E_DEGENERATE and st["status"] == rg.RGBID_E_DEGENERATE
+    np.testing.assert_array_equal(R, np.eye(3))
+    np.testing.assert_array_equal(t, np.zeros(3))
+    rg.rgbid_pyramid_free(A)
+
+
+def test_ragged_size_and_small_sample(ctx):
+    # 157x113: odd sizes (floor at every level), tiles with a ragged tail, and a
+    # sample of at most 1000 pixels (stride 5 at level 0).
+    rg = _rg()
+    p = synth.pair_c1(7)
+    I = np.ascontiguousarray(p.A.I[:113, :157])
+    W = np.ascontiguousarray(p.A.W[:113, :157])
+    Ib = np.ascontiguousarray(p.B.I[:113, :157])
+    Wb = np.ascontiguousarray(p.B.W[:113, :157])
+    cam = (157, 113, 131.25, 131.25, 79.5, 59.5)
+    A = rg.rgbid_pyramid(ctx, cam, 3, 0, *upload(I, W))
+    B = rg.rgbid_pyramid(ctx, cam, 3, 0, *upload(Ib, Wb))
+    prm = _params(3, [4, 4, 4], sample_max=1000)
+    R, t, st, rc = rg.rgbid_align(ctx, A, B, prm)
+    Ro, to, sto = oracle.align(cam, I, W, Ib, Wb, _oparams(3, [4, 4, 4], sample_max=1000))
+    assert rc == 0 and sto["status"] == 0
+    assert rot_err(R, Ro) <= 1e-5 and np.linalg.norm(t - to) <= 1e-5
+    for level in range(3):
+        g = rg.rgbid_normal_equations(ctx, A, B, level, (Ro, to), prm)
+        r = oracle.normal_equations_at(cam, I, W, Ib, Wb, level, Ro, to,
+                                       _oparams(3, [1] * 3, sample_max=1000))
+        check_normal_equations(g, r, what="ragged level %d" % level)
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+def test_argument_errors(ctx):
+    rg = _rg()
+    import torch
+    I = torch.zeros(8, 8, device="cuda")
+    with pytest.raises(rg.RgbidError) as e:
+        rg.rgbid_pyramid(ctx, (8, 8, 5.0, 5.0, 3.5, 3.5), 9, 0, I, I)
+    assert e.value.code == rg.RGBID_E_ARG
+    A = rg.rgbid_pyramid(ctx, (8, 8, 5.0, 5.0, 3.5, 3.5), 2, 0, I, I)
+    B = rg.rgbid_pyramid(ctx, (8, 8, 5.0, 5.0, 3.5, 3.5), 1, 0, I, I)
+    with pytest.raises(rg.RgbidError) as e:
+        rg.rgbid_align(ctx, A, B, _params(2, [1, 1]))
+    assert e.value.code == rg.RGBID_E_SHAPE
+    with pytest.raises(rg.RgbidError) as e:
+        rg.rgbid_align(ctx, A, A, _params(6, [1] * 6))
+    assert e.value.code == rg.RGBID_E_ARG
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+# ----------------------------------------------------------------- fusion
+
+
+def test_fuse_20_frames_matches_oracle(ctx):
+    rg = _rg()
+    import torch
+    cam, kf, frames, poses = synth.keyframe_sequence(20, seed=0, ss=2)
+    Wkf0 = kf.W.astype(np.float64)
+    Wd = torch.from_numpy(kf.W).cuda()
+    K = rg.rgbid_keyframe_init(ctx, cam, Wd)
+    Wr, Cr = Wkf0.copy(), np.ones_like(Wkf0)
+    tol = 0.01
+    for f, (R, t) in zip(frames, poses):
+        n = rg.rgbid_fuse(ctx, K, torch.from_numpy(f.W).cuda(), (R, t), tol)
+        Wr, Cr, nr = oracle.fuse(cam, Wr, Cr, f.W, R, t, tol)
+        assert abs(n - nr) <= 50, (n, nr)
+    Wg, Cg = rg.rgbid_keyframe_read(ctx, K, (cam.h, cam.w))
+    Wg, Cg = Wg.cpu().numpy().astype(np.float64), Cg.cpu().numpy().astype(np.float64)
+    same = np.isclose(Cg, Cr, rtol=1e-4)        # same set of fusion decisions
+    assert same.mean() > 0.995
+    np.testing.assert_allclose(Wg[same], Wr[same], rtol=1e-5)
+    assert np.all((Wg > 0) == (Wkf0 > 0))       # keyframe holes stay holes
+    rg.rgbid_keyframe_free(K)
