@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Throughput of dense RGB-D alignment + keyframe fusion on one MI355X.
+
+Workload (one "step"): a batch of 640x480 frame pairs from the room + boxes
+generator (10% holes, inverse-depth noise 1.5e-3 W^2, motion <= 2 deg / 3 cm,
+Kinect-like camera fx = fy = 525, cx = 319.5, cy = 239.5):
+  1. pyramids (4 levels) of both frames of every pair, rebuilt from the
+     resident level-0 images;
+  2. batched coarse-to-fine alignment of all pairs: 4 levels x 10 Gauss-Newton
+     iterations, paper-literal full-resolution warp, Huber weights, FP32
+     per-pixel arithmetic;
+  3. fusion of 20 frames (ground-truth poses) into one 640x480 keyframe.
+value = aligned pairs per second over the timed steps (inputs already in HBM).
+
+Also reported: the roofline of the dominant kernel (algorithmic bytes per
+launch / HIP-event-timed average launch duration, against 8 TB/s), and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+python bench.py [--steps K] [--warmup W] [--pairs P] [--storage f32|f16]
+                [--warp fullres|per_level] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "640×480 frame-pair alignments/s + HBM GB/s, warm-start vs plain GN"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(level, kernel, npairs, w0, h0, f16, warp_fullres, fused):
+    """Bytes the method must move for one launch of (level, kernel) over the
+    batch.  Per pixel, FP32 storage: a level-0 pixel of the full-resolution
+    warp needs W_A (4 B) and I_B, W_B (8 B); the residual of a level pixel
+    needs I_A, W_A (8 B); a stored warped level image is 8 B per level pixel
+    (written once, read once).  FP16 storage halves the image bytes."""
+    e = 2 if f16 else 4
+    n0 = w0 * h0
+    nl = (w0 >> level) * (h0 >> level)
+    nw = n0 if warp_fullres else nl       # pixels warped per iteration
+    if kernel == "reduce":
+        if fused:       # warp + residual in one kernel
+            return npairs * (nw * 3 * e + nl * 2 * e - (nl * e if nw == nl else 0))
+        return npairs * nl * (2 * e + 8)
+    if kernel == "warp":
+        if fused:       # sample pixels only: not a bandwidth kernel
+            return None
+        return npairs * (nw * 3 * e + nl * 8)
+    return None
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in ("align.hip", "rgbid_internal.h"):
+        with open(os.path.join(ROOT, "paper_1807_08271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("source_sha") != source_sha():
+        return None
+    ent = d.get("kernels", {}).get(kernel_key)
+    return ent.get("hbm_bytes_per_launch") if ent else None
+
+
+def make_inputs(npairs, device):
+    import synth
+    t0 = time.time()
+    pairs = [synth.pair_c2(i, ss=2, device=device) for i in range(npairs)]
+    cam, kf, frames, poses = synth.keyframe_sequence(20, seed=0, ss=2, device=device)
+    log("generated %d pairs + 21 fusion frames in %.1fs" % (npairs, time.time() - t0))
+    return pairs, (cam, kf, frames, poses)
+
+
+def cpu_baseline(pairs, fusion, oparams, budget_s):
+    """The FP64 oracle on a bounded sample: whole alignments of the first
+    pairs until budget_s is spent (at least one), plus one 20-frame fusion.
+    Scaled to the step: P alignments + one fusion."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    t_al, n = 0.0, 0
+    for p in pairs:
+        t0 = time.perf_counter()
+        oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, oparams)
+        t_al += time.perf_counter() - t0
+        n += 1
+        if t_al >= budget_s:
+            break
+    cam, kf, frames, poses = fusion
+    W = kf.W.astype(np.float64)
+    C = np.ones_like(W)
+    t0 = time.perf_counter()
+    for f, (R, t) in zip(frames, poses):
+        W, C, _ = oracle.fuse(cam, W, C, f.W, R, t, 0.01)
+    t_fu = time.perf_counter() - t0
+    per_align = t_al / n
+    P = len(pairs)
+    value = P / (P * per_align + t_fu)
+    return {"value": round(value, 3), "unit": "alignments/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of the %d step pairs aligned by the FP64 C oracle (%.2f s each, one "
+                      "thread) + one 20-frame fusion (%.2f s), scaled to one step" % (
+                          n, P, per_align, t_fu)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pairs", type=int, default=64)
+    ap.add_argument("--storage", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--warp", choices=["fullres", "per_level"], default="fullres")
+    ap.add_argument("--weight", choices=["huber", "student_t"], default="huber")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent pairs would shard across GPUs with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1807_08271_amd import rgbid as rg
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    pairs, fusion = make_inputs(args.pairs, dev)
+    cam = pairs[0].cam
+    f16 = args.storage == "f16"
+    storage = rg.RGBID_F16 if f16 else rg.RGBID_F32
+
+    ctx = rg.rgbid_create(0)
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    IA = [up(p.A.I) for p in pairs]
+    WA = [up(p.A.W) for p in pairs]
+    IB = [up(p.B.I) for p in pairs]
+    WB = [up(p.B.W) for p in pairs]
+    As = [rg.rgbid_pyramid(ctx, cam, 4, storage, i, w) for i, w in zip(IA, WA)]
+    Bs = [rg.rgbid_pyramid(ctx, cam, 4, storage, i, w) for i, w in zip(IB, WB)]
+    fcam, kf, frames, fposes = fusion
+    kfW = up(kf.W)
+    fW = [up(f.W) for f in frames]
+    K = rg.rgbid_keyframe_init(ctx, fcam, kfW)
+    params = rg.rgbid_default_params(
+        levels=4, iters=[10, 10, 10, 10],
+        weight=rg.RGBID_W_HUBER if args.weight == "huber" else rg.RGBID_W_STUDENT_T,
+        warp=rg.RGBID_WARP_FULLRES if args.warp == "fullres" else rg.RGBID_WARP_PER_LEVEL)
+    all_pyr = As + Bs
+    all_I = IA + IB
+    all_W = WA + WB
+    torch.cuda.synchronize()
+
+    def step():
+        rg.rgbid_pyramid_update_batch(ctx, all_pyr, all_I, all_W)
+        poses, stats = rg.rgbid_align_batch(ctx, As, Bs, params)
+        rg.rgbid_keyframe_reset(ctx, K, kfW)
+        for w, T in zip(fW, fposes):
+            rg.rgbid_fuse(ctx, K, w, T, 0.01, count=False)
+        return poses, stats
+
+    for i in range(args.warmup):
+        poses, stats = step()
+        log("warmup step %d done" % i)
+    torch.cuda.synchronize()
+    # sanity: the batch converged near the ground truth
+    errs = [np.linalg.norm(oracle.log_so3(R.T @ p.R)) for (R, t), p in zip(poses, pairs)]
+    terrs = [np.linalg.norm(t - p.t) for (R, t), p in zip(poses, pairs)]
+    bad = sum(s["status"] != 0 for s in stats)
+
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("timed %d steps: %.3f ms/step" % (args.steps, 1e3 * dt / args.steps))
+
+    # the same steps again with per-kernel HIP-event timing on
+    rg.rgbid_set_profiling(ctx, True)
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kt = rg.rgbid_kernel_times(ctx)
+    rg.rgbid_set_profiling(ctx, False)
+
+    fullres = args.warp == "fullres"
+    rows = []
+    for (lvl, kname), (ms, nl) in sorted(kt.items()):
+        fused = (lvl == 0 or not fullres) if kname in ("warp", "reduce") else False
+        b = algorithmic_bytes(lvl, kname, args.pairs, cam.w, cam.h, f16, fullres, fused)
+        avg_us = 1e3 * ms / nl
+        rows.append((ms, lvl, kname, avg_us, b))
+        log("kernel %-6s level %d: %6d launches, avg %8.2f us, total %8.2f ms%s" % (
+            kname, lvl, nl, avg_us, ms,
+            "" if b is None else ", %.1f GB/s algorithmic" % (b / (avg_us * 1e-6) / 1e9)))
+    dom = max((r for r in rows if r[4] is not None), key=lambda r: r[0])
+    _, lvl, kname, avg_us, b = dom
+    achieved = b / (avg_us * 1e-6) / 1e9
+    key = "%s_l%d" % (kname, lvl)
+    traffic = load_traffic(key)
+    roofline = {"bound": "hbm", "kernel": "k_%s level %d" % (kname, lvl),
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": b, "avg_launch_us": round(avg_us, 2)}
+
+    value = args.pairs * args.steps / dt
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "alignments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32" if f16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d pairs of 640x480 (room+boxes generator, 10%% holes), "
+                               "4-level %s warp, 10 Huber GN iterations per level, + fusion of "
+                               "20 frames into one keyframe" % (args.pairs, args.warp),
+                   "pairs_per_step": args.pairs, "width": cam.w, "height": cam.h, "levels": 4,
+                   "iters_per_level": 10, "warp": args.warp, "weight": args.weight,
+                   "storage": args.storage, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "accuracy": {"max_rot_err_vs_truth_rad": float(max(errs)),
+                     "max_trans_err_vs_truth_m": float(max(terrs)), "degenerate_pairs": bad},
+    }
+    if not args.no_cpu:
+        log("timing the FP64 oracle on a bounded sample ...")
+        op = oracle.Params(levels=4, iters=[10] * 4, weight=args.weight, warp=args.warp,
+                           storage=args.storage)
+        out["cpu_baseline"] = cpu_baseline(pairs, fusion, op, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    for p in As + Bs:
+        rg.rgbid_pyramid_free(p)
+    rg.rgbid_keyframe_free(K)
+    rg.rgbid_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

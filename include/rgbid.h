@@ -228,12 +228,38 @@ rgbid_status rgbid_keyframe_init(rgbid_ctx* ctx, const rgbid_camera* cam, const 
 rgbid_status rgbid_fuse(rgbid_ctx* ctx, rgbid_kf* kf, const float* Wk_dev, size_t pitch_elems,
                         const rgbid_pose* T_kf_k, double tol, long long* n_fused);
 
+/* Re-initialises an existing keyframe from a new FP32 inverse-depth map of
+   the same size, with C = 1 (no allocation, does not synchronise). */
+rgbid_status rgbid_keyframe_reset(rgbid_ctx* ctx, rgbid_kf* kf, const float* W_dev,
+                                  size_t pitch_elems);
+
 /* Copies the keyframe's W and C maps into caller-owned FP32 device buffers
    (dense rows).  Either pointer may be NULL.  Does not synchronise. */
 rgbid_status rgbid_keyframe_read(rgbid_ctx* ctx, const rgbid_kf* kf, float* W_out_dev,
                                  float* C_out_dev);
 
 void rgbid_keyframe_free(rgbid_kf* kf);
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Kernel families of one iteration, in launch order. */
+typedef enum {
+    RGBID_K_WARP = 0,     /* warp (+ downsample) and sample residuals */
+    RGBID_K_SCALE = 1,    /* location / scale / nu */
+    RGBID_K_REDUCE = 2,   /* residuals, Jacobians, weights, normal-equation partials */
+    RGBID_K_SOLVE = 3     /* FP64 sum, Cholesky, pose update */
+} rgbid_kernel;
+
+/* Turns per-kernel timing on (1) or off (0).  While on, the alignment
+   driver launches directly (not from a cached graph), records HIP events
+   between the kernel launches of every iteration on the context's stream, and
+   accumulates, per level and kernel family, the elapsed time and the number of
+   launches when each call completes.  Turning it on clears the accumulators. */
+rgbid_status rgbid_set_profiling(rgbid_ctx* ctx, int on);
+
+/* Reads the accumulators: ms_total[l * 4 + k] and launches[l * 4 + k] for
+   level l < 8 and kernel family k (rgbid_kernel); arrays of 32 entries. */
+rgbid_status rgbid_kernel_times(const rgbid_ctx* ctx, double* ms_total, long long* launches);
 
 #ifdef __cplusplus
 }

@@ -89,27 +89,35 @@ __device__ __forceinline__ Geom make_geom(const PairState& S, const LevelView& A
     return G;
 }
 
-// Inverse geometric warp of one pixel (u, v) of A (sec. 5.3).  With
-// x = K^-1 p and w_a = W_A(p), W_A(p) * R^T (x / w_a - t) = R^T x - w_a R^T t
-// locates p_B; I* is the bilinear I_B(p_B) and
-// W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) with w_b the bilinear W_B(p_B).
-// Valid iff W_A(p) valid, in front, p_B in [-0.5, w-0.5) x [-0.5, h-0.5),
-// four valid W taps and W* positive and finite.
+// Reciprocal and reciprocal square root (v_rcp_f32 / v_rsq_f32, 1 ulp) for
+// the per-pixel path.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Inverse geometric warp of one pixel (u, v) of A (sec. 5.3) with w_a =
+// W_A(u, v) already loaded.  With x = K^-1 p,
+// W_A(p) * R^T (x / w_a - t) = R^T x - w_a R^T t locates p_B; I* is the
+// bilinear I_B(p_B) and W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) with w_b the
+// bilinear W_B(p_B).  Valid iff w_a valid, in front, p_B in
+// [-0.5, w-0.5) x [-0.5, h-0.5), four valid W taps and W* positive and
+// finite.  Branch-free: the four taps are always loaded (at clamped, in-bounds
+// addresses) so the loads of several pixels can be in flight together.
 template <bool F16>
-__device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, float& Wo)
+__device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa, float& Io,
+                                          float& Wo)
 {
-    const float wa = load_w<F16>(G.WA, v * G.w + u);
-    if (!w_valid(wa)) return false;
+    bool ok = w_valid(wa);
     const float rx = ((float)u - G.cx) * G.ifx, ry = ((float)v - G.cy) * G.ify;
     const float ax = fmaf(G.m[0], rx, fmaf(G.m[1], ry, G.m[2]));
     const float ay = fmaf(G.m[3], rx, fmaf(G.m[4], ry, G.m[5]));
     const float az = fmaf(G.m[6], rx, fmaf(G.m[7], ry, G.m[8]));
     const float yx = fmaf(-wa, G.q[0], ax), yy = fmaf(-wa, G.q[1], ay), yz = fmaf(-wa, G.q[2], az);
-    if (!(yz > 0.0f)) return false;
-    const float iz = 1.0f / yz;
-    const float ub = fmaf(G.fx * yx, iz, G.cx), vb = fmaf(G.fy * yy, iz, G.cy);
-    if (!(ub >= -0.5f && ub < (float)G.w - 0.5f && vb >= -0.5f && vb < (float)G.h - 0.5f))
-        return false;
+    ok = ok && yz > 0.0f;
+    const float iz = rcp(yz);
+    float ub = fmaf(G.fx * yx, iz, G.cx), vb = fmaf(G.fy * yy, iz, G.cy);
+    ok = ok && ub >= -0.5f && ub < (float)G.w - 0.5f && vb >= -0.5f && vb < (float)G.h - 0.5f;
+    ub = ok ? ub : 0.0f;
+    vb = ok ? vb : 0.0f;
     const float fu = floorf(ub), fv = floorf(vb);
     const float a = ub - fu, b = vb - fv;
     int x0 = (int)fu, y0 = (int)fv;
@@ -120,16 +128,22 @@ __device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, 
     const float2 p10 = load_iw<F16>(G.Biw, y0 * G.w + x1);
     const float2 p01 = load_iw<F16>(G.Biw, y1 * G.w + x0);
     const float2 p11 = load_iw<F16>(G.Biw, y1 * G.w + x1);
-    if (!(w_valid(p00.y) && w_valid(p10.y) && w_valid(p01.y) && w_valid(p11.y))) return false;
+    ok = ok && w_valid(p00.y) && w_valid(p10.y) && w_valid(p01.y) && w_valid(p11.y);
     const float c00 = (1.0f - a) * (1.0f - b), c10 = a * (1.0f - b);
     const float c01 = (1.0f - a) * b, c11 = a * b;
     const float ib = c00 * p00.x + c10 * p10.x + c01 * p01.x + c11 * p11.x;
     const float wb = c00 * p00.y + c10 * p10.y + c01 * p01.y + c11 * p11.y;
-    const float ws = az * wb / fmaf(wb, G.q[2], 1.0f);
-    if (!w_valid(ws)) return false;
-    Io = ib;
-    Wo = ws;
-    return true;
+    const float ws = az * wb * rcp(fmaf(wb, G.q[2], 1.0f));
+    ok = ok && w_valid(ws);
+    Io = ok ? ib : 0.0f;
+    Wo = ok ? ws : 0.0f;
+    return ok;
+}
+
+template <bool F16>
+__device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, float& Wo)
+{
+    return warp_core<F16>(G, u, v, load_w<F16>(G.WA, v * G.w + u), Io, Wo);
 }
 
 // Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
@@ -165,10 +179,10 @@ __device__ __forceinline__ void warp_pass(const Geom& G, int first, int gw, floa
 #pragma unroll
     for (int m = 0; m < CL::CPL; ++m) {
         const int c = j + CL::LPP * m;
-        float ci = 0.0f, cw = 0.0f;
-        if (ok)
-            ok = warp_px<F16>(G, gu * gs * CL::B + (c % CL::B), gv * gs * CL::B + (c / CL::B),
-                              ci, cw);
+        float ci, cw;
+        const bool okc = warp_px<F16>(G, gu * gs * CL::B + (c % CL::B),
+                                      gv * gs * CL::B + (c / CL::B), ci, cw);
+        ok = ok && okc;
         sI += ci;
         sW += cw;
     }
@@ -228,34 +242,46 @@ __device__ __forceinline__ void warp_tile(const Geom& G, int tile_first, int gw,
 
 // Residuals (and Jacobians) of one level pixel (sec. 6.2).  r_I needs an
 // interior pixel, a valid W_A and warped values; r_W additionally the four
-// W_A neighbours (central-difference gradient).
+// W_A neighbours (central-difference gradient).  c is A's (I, W) at the
+// pixel; the four neighbours are loaded at clamped (in-bounds) positions.
 struct Terms {
     bool vI, vW;
     float rI, rW, lam;
     float JI[6], JW[6];
 };
 
-template <bool F16, bool JAC>
-__device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float ify, int u, int v,
-                                            float Is, float Ws, bool wv, Terms& T)
+struct Nbrs {
+    float2 l, r, t, b;
+};
+
+template <bool F16>
+__device__ __forceinline__ Nbrs load_nbrs(const LevelView& A, int u, int v)
 {
-    T.vI = T.vW = false;
-    if (!wv || u < 1 || v < 1 || u > A.w - 2 || v > A.h - 2) return;
     const int i = v * A.w + u;
-    const float2 c = load_iw<F16>(A.iw, i);
-    if (!w_valid(c.y)) return;
-    const float2 l = load_iw<F16>(A.iw, i - 1), r = load_iw<F16>(A.iw, i + 1);
-    const float2 t = load_iw<F16>(A.iw, i - A.w), b = load_iw<F16>(A.iw, i + A.w);
-    T.vI = true;
+    Nbrs n;
+    n.l = load_iw<F16>(A.iw, u > 0 ? i - 1 : i);
+    n.r = load_iw<F16>(A.iw, u < A.w - 1 ? i + 1 : i);
+    n.t = load_iw<F16>(A.iw, v > 0 ? i - A.w : i);
+    n.b = load_iw<F16>(A.iw, v < A.h - 1 ? i + A.w : i);
+    return n;
+}
+
+template <bool JAC>
+__device__ __forceinline__ void terms_core(const LevelView& A, float ifx, float ify, int u, int v,
+                                           float2 c, const Nbrs& n, float Is, float Ws, bool wv,
+                                           Terms& T)
+{
+    const bool inner = u >= 1 && v >= 1 && u <= A.w - 2 && v <= A.h - 2;
+    T.vI = wv && inner && w_valid(c.y);
+    T.vW = T.vI && w_valid(n.l.y) && w_valid(n.r.y) && w_valid(n.t.y) && w_valid(n.b.y);
     T.rI = Is - c.x;
-    T.vW = w_valid(l.y) && w_valid(r.y) && w_valid(t.y) && w_valid(b.y);
     T.rW = Ws - c.y;
     if constexpr (JAC) {
-        const float wa = c.y, Z = 1.0f / wa;
+        const float wa = c.y, Z = rcp(wa);
         const float du = A.cx - (float)u, dv = A.cy - (float)v;
         const float xu = -du * ifx, xv = -dv * ify;
         const float X0 = Z * xu, X1 = Z * xv, X2 = Z;
-        const float gu = 0.5f * (r.x - l.x), gv = 0.5f * (b.x - t.x);
+        const float gu = 0.5f * (n.r.x - n.l.x), gv = 0.5f * (n.b.x - n.t.x);
         const float a0 = wa * gu * A.fx, a1 = wa * gv * A.fy, a2 = wa * fmaf(gu, du, gv * dv);
         T.JI[0] = a0;
         T.JI[1] = a1;
@@ -263,32 +289,39 @@ __device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float
         T.JI[3] = X1 * a2 - X2 * a1;
         T.JI[4] = X2 * a0 - X0 * a2;
         T.JI[5] = X0 * a1 - X1 * a0;
-        if (T.vW) {
-            const float wu = 0.5f * (r.y - l.y), wv2 = 0.5f * (b.y - t.y);
-            const float k0 = wu * A.fx, k1 = wv2 * A.fy, k2 = fmaf(wu, du, wv2 * dv);
-            const float b0 = wa * k0, b1 = wa * k1, b2 = wa * (k2 + Ws);
-            T.JW[0] = b0;
-            T.JW[1] = b1;
-            T.JW[2] = b2;
-            T.JW[3] = X1 * b2 - X2 * b1;
-            T.JW[4] = X2 * b0 - X0 * b2;
-            T.JW[5] = X0 * b1 - X1 * b0;
-            // n~ = Z grad W (K - p e_z^T) + e_z, n~ . x = 1, lambda = 1/(|n~||x|)
-            const float n0 = Z * k0, n1 = Z * k1, n2 = fmaf(Z, k2, 1.0f);
-            const float nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
-            const float xx = fmaf(xu, xu, fmaf(xv, xv, 1.0f));
-            T.lam = 1.0f / sqrtf(nn * xx);
-        }
+        const float wu = 0.5f * (n.r.y - n.l.y), wv2 = 0.5f * (n.b.y - n.t.y);
+        const float k0 = wu * A.fx, k1 = wv2 * A.fy, k2 = fmaf(wu, du, wv2 * dv);
+        const float b0 = wa * k0, b1 = wa * k1, b2 = wa * (k2 + Ws);
+        T.JW[0] = b0;
+        T.JW[1] = b1;
+        T.JW[2] = b2;
+        T.JW[3] = X1 * b2 - X2 * b1;
+        T.JW[4] = X2 * b0 - X0 * b2;
+        T.JW[5] = X0 * b1 - X1 * b0;
+        // n~ = Z grad W (K - p e_z^T) + e_z, n~ . x = 1, lambda = 1/(|n~||x|)
+        const float n0 = Z * k0, n1 = Z * k1, n2 = fmaf(Z, k2, 1.0f);
+        const float nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
+        const float xx = fmaf(xu, xu, fmaf(xv, xv, 1.0f));
+        T.lam = rsq(nn * xx);
     }
+}
+
+template <bool F16, bool JAC>
+__device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float ify, int u, int v,
+                                            float Is, float Ws, bool wv, Terms& T)
+{
+    const float2 c = load_iw<F16>(A.iw, v * A.w + u);
+    const Nbrs n = load_nbrs<F16>(A, u, v);
+    terms_core<JAC>(A, ifx, ify, u, v, c, n, Is, Ws, wv, T);
 }
 
 __device__ __forceinline__ float omega(int kind, float x, float nu, float k)
 {
     if (kind == RGBID_W_HUBER) {
         const float ax = fabsf(x);
-        return ax <= k ? 1.0f : k / ax;
+        return ax <= k ? 1.0f : k * rcp(ax);
     }
-    return (nu + 1.0f) / fmaf(x, x, nu);
+    return (nu + 1.0f) * rcp(fmaf(x, x, nu));
 }
 
 __device__ __forceinline__ void accum(float* acc, const float* J, float w, float r)
@@ -451,6 +484,28 @@ __device__ double digamma_d(double x)
     return r + log(x) - 0.5 / x - series;
 }
 
+// n f_c(nu) + sum_i (1 + ln w_i - w_i), w_i = (nu + 1)/(nu + x_i^2), with
+// f_c(nu) = -psi(nu/2) + ln(nu/2) + psi((nu+1)/2) - ln((nu+1)/2): the left side
+// of the nu equation of sec. 6.3 (eq:robustnessValue).  x2 holds x_i^2
+// (NaN = not in the sample); block-uniform result.
+__device__ __forceinline__ double nu_equation(const float (&x2)[kScalePerThread], double n,
+                                              double nud, double* lds)
+{
+    const float nf = (float)nud;
+    float acc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kScalePerThread; ++q) {
+        if (x2[q] == x2[q]) {
+            const float w = (nf + 1.0f) / (nf + x2[q]);
+            acc += 1.0f + logf(w) - w;
+        }
+    }
+    const Sum3 z = block_sum3(Sum3{(double)acc, 0.0, 0.0}, lds);
+    const double c = -digamma_d(0.5 * nud) + log(0.5 * nud) + digamma_d(0.5 * (nud + 1.0)) -
+                     log(0.5 * (nud + 1.0));
+    return n * c + z.a;
+}
+
 // One workgroup per (pair, channel): location mu and scale sigma of the
 // channel's sample residuals by the fixed point of the two stationarity
 // equations of sec. 6.3 (weights from the previous estimate), starting at
@@ -511,39 +566,27 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
         }
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
             const float fmu = (float)mu, isg = (float)(1.0 / sigma);
-            float x2[kScalePerThread];
 #pragma unroll
             for (int q = 0; q < kScalePerThread; ++q) {
                 const float x = (r[q] - fmu) * isg;
-                x2[q] = x * x;     // NaN stays NaN
+                r[q] = x * x;     // r now holds x^2 (NaN stays NaN)
             }
-            auto f = [&](double nud) -> double {
-                const float nf = (float)nud;
-                float acc = 0.0f;
-#pragma unroll
-                for (int q = 0; q < kScalePerThread; ++q) {
-                    if (x2[q] == x2[q]) {
-                        const float w = (nf + 1.0f) / (nf + x2[q]);
-                        acc += 1.0f + logf(w) - w;
-                    }
+            // sequence of evaluations: f(10), f(2), then 30 bisection steps
+            double lo = 2.0, hi = 10.0, nv = 0.0;
+            bool done = false;
+            for (int ev = 0; ev < 32 && !done; ++ev) {
+                const double nud = ev == 0 ? 10.0 : ev == 1 ? 2.0 : 0.5 * (lo + hi);
+                const double f = nu_equation(r, n, nud, lds);
+                if (ev == 0) {
+                    if (f > 0.0) { nv = 10.0; done = true; }
+                } else if (ev == 1) {
+                    if (f < 0.0) { nv = 2.0; done = true; }
+                } else {
+                    if (f > 0.0) lo = nud;
+                    else hi = nud;
                 }
-                const Sum3 z = block_sum3(Sum3{(double)acc, 0.0, 0.0}, lds);
-                const double c = -digamma_d(0.5 * nud) + log(0.5 * nud) +
-                                 digamma_d(0.5 * (nud + 1.0)) - log(0.5 * (nud + 1.0));
-                return n * c + z.a;
-            };
-            double nv;
-            if (f(10.0) > 0.0) nv = 10.0;
-            else if (f(2.0) < 0.0) nv = 2.0;
-            else {
-                double lo = 2.0, hi = 10.0;
-                for (int it = 0; it < 30; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    if (f(mid) > 0.0) lo = mid;
-                    else hi = mid;
-                }
-                nv = 0.5 * (lo + hi);
             }
+            if (!done) nv = 0.5 * (lo + hi);
             nu = (float)nv;
         }
     }
@@ -586,28 +629,37 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
+    const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
+    const Geom G = make_geom(S, D.A[wl], D.B[wl]);
     for (int tile = ch.first + wave; tile < end; tile += waves) {
         float Is = 0.0f, Ws = 0.0f;
         bool wv = false;
         int u = 0, v = 0, idx;
-        if constexpr (FUSED) {
-            const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
-            const Geom G = make_geom(S, D.A[wl], D.B[wl]);
-            warp_tile<F16, LOG2B>(G, tile * 64, gd.gw, gd.inv_gw, gd.n, 1, lane, Is, Ws, wv, u,
-                                  v, idx);
-        } else {
+        Terms T;
+        if constexpr (FUSED && LOG2B == 0) {
+            // the level pixel is its own warp child: W_A comes with A's (I, W)
             idx = tile * 64 + lane;
-            if (idx < gd.n) {
-                const float2 e = D.warped[idx];
+            const int ic = idx < gd.n ? idx : 0;
+            split_index(ic, gd.gw, gd.inv_gw, u, v);
+            const float2 c = load_iw<F16>(A.iw, ic);
+            const Nbrs nb = load_nbrs<F16>(A, u, v);
+            wv = warp_core<F16>(G, u, v, c.y, Is, Ws) && idx < gd.n;
+            terms_core<true>(A, ifx, ify, u, v, c, nb, Is, Ws, wv, T);
+        } else {
+            if constexpr (FUSED) {
+                warp_tile<F16, LOG2B>(G, tile * 64, gd.gw, gd.inv_gw, gd.n, 1, lane, Is, Ws, wv, u,
+                                      v, idx);
+            } else {
+                idx = tile * 64 + lane;
+                const int ic = idx < gd.n ? idx : 0;
+                const float2 e = D.warped[ic];
                 Is = e.x;
                 Ws = e.y;
-                wv = Ws > 0.0f;
-                split_index(idx, gd.gw, gd.inv_gw, u, v);
+                wv = Ws > 0.0f && idx < gd.n;
+                split_index(ic, gd.gw, gd.inv_gw, u, v);
             }
+            pixel_terms<F16, true>(A, ifx, ify, u, v, Is, Ws, wv, T);
         }
-        if (idx >= gd.n) continue;
-        Terms T;
-        pixel_terms<F16, true>(A, ifx, ify, u, v, Is, Ws, wv, T);
         if (T.vI && enI) {
             const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
             accum(acc, T.JI, w, T.rI);
@@ -698,27 +750,35 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
     if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) S.nu[0] = fmaxf(S.nu[0], S.nu[1]);
     if (!L.update) return;
 
-    // 6x6 Cholesky of H (upper triangle, row-major) and xi = -H^-1 g
+    // 6x6 Cholesky of H (upper triangle, row-major) and xi = -H^-1 g; a pivot
+    // <= 1e-12 max(diag H) or fewer than 6 valid residuals is degenerate.
     double A[6][6];
     {
         int k = 0;
+#pragma unroll
         for (int a = 0; a < 6; ++a)
-            for (int b = a; b < 6; ++b) A[a][b] = A[b][a] = s[k++];
+#pragma unroll
+            for (int b = a; b < 6; ++b) {
+                A[a][b] = A[b][a] = s[k];
+                ++k;
+            }
     }
     double dmax = 0.0;
+#pragma unroll
     for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A[a][a]);
     bool ok = (S.nI + S.nW >= 6) && dmax > 0.0;
-    double Lm[6][6] = {};
-    for (int j = 0; j < 6 && ok; ++j) {
+    double Lm[6][6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
         double d = A[j][j];
+#pragma unroll
         for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
-        if (!(d > 1e-12 * dmax)) {
-            ok = false;
-            break;
-        }
-        Lm[j][j] = sqrt(d);
+        ok = ok && d > 1e-12 * dmax;
+        Lm[j][j] = sqrt(ok ? d : 1.0);
+#pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double e = A[i][j];
+#pragma unroll
             for (int k = 0; k < j; ++k) e -= Lm[i][k] * Lm[j][k];
             Lm[i][j] = e / Lm[j][j];
         }
@@ -729,13 +789,17 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
         return;
     }
     double y[6], xi[6];
+#pragma unroll
     for (int i = 0; i < 6; ++i) {
         double e = -s[21 + i];
+#pragma unroll
         for (int k = 0; k < i; ++k) e -= Lm[i][k] * y[k];
         y[i] = e / Lm[i][i];
     }
+#pragma unroll
     for (int i = 5; i >= 0; --i) {
         double e = y[i];
+#pragma unroll
         for (int k = i + 1; k < 6; ++k) e -= Lm[k][i] * xi[k];
         xi[i] = e / Lm[i][i];
     }
@@ -770,41 +834,47 @@ __global__ void k_level_start(PairState* states, int n)
 }
 
 template <bool F16, int LOG2B>
-hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L)
+hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L, hipEvent_t const* ev)
 {
     const dim3 blk(64 * L.tune.waves);
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     if (L.n_warp_chunks > 0)
         hipLaunchKernelGGL((k_warp<F16, LOG2B>), dim3(L.n_warp_chunks), blk, 0, s, L);
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scale, dim3(L.npairs, 2), dim3(kScaleThreads), 0, s, L);
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     if (L.n_red_chunks > 0) {
         if (L.tune.fused)
             hipLaunchKernelGGL((k_reduce<F16, LOG2B, true>), dim3(L.n_red_chunks), blk, 0, s, L);
         else
             hipLaunchKernelGGL((k_reduce<F16, LOG2B, false>), dim3(L.n_red_chunks), blk, 0, s, L);
     }
+    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_solve, dim3(L.npairs), dim3(64), 0, s, L);
+    if (ev && (e = hipEventRecord(ev[4], s)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template <bool F16>
-hipError_t launch_iteration_f(hipStream_t s, const IterLaunch& L)
+hipError_t launch_iteration_f(hipStream_t s, const IterLaunch& L, hipEvent_t const* ev)
 {
     switch (L.block_log2) {
-    case 0: return launch_iteration_t<F16, 0>(s, L);
-    case 1: return launch_iteration_t<F16, 1>(s, L);
-    case 2: return launch_iteration_t<F16, 2>(s, L);
-    case 3: return launch_iteration_t<F16, 3>(s, L);
-    case 4: return launch_iteration_t<F16, 4>(s, L);
+    case 0: return launch_iteration_t<F16, 0>(s, L, ev);
+    case 1: return launch_iteration_t<F16, 1>(s, L, ev);
+    case 2: return launch_iteration_t<F16, 2>(s, L, ev);
+    case 3: return launch_iteration_t<F16, 3>(s, L, ev);
+    case 4: return launch_iteration_t<F16, 4>(s, L, ev);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_iteration(hipStream_t s, const IterLaunch& L)
+hipError_t launch_iteration(hipStream_t s, const IterLaunch& L, hipEvent_t const* ev)
 {
     if (L.tune.waves < 1 || L.tune.waves > 8) return hipErrorInvalidValue;
-    return L.f16 ? launch_iteration_f<true>(s, L) : launch_iteration_f<false>(s, L);
+    return L.f16 ? launch_iteration_f<true>(s, L, ev) : launch_iteration_f<false>(s, L, ev);
 }
 
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs)

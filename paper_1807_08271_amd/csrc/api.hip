@@ -68,6 +68,10 @@ struct rgbid_ctx {
     bool use_graphs = true;
     std::map<std::string, std::pair<int, hipGraphExec_t>> graphs;
     std::map<std::string, LevelTune> tunes;   // per (level shape) launch shape
+    bool profiling = false;
+    std::vector<hipEvent_t> events;  // timing events, grown on demand
+    double prof_ms[kMaxLevels * 4] = {};
+    long long prof_n[kMaxLevels * 4] = {};
 };
 
 namespace {
@@ -166,7 +170,7 @@ LevelTune default_tune(int block_log2)
     if (block_log2 == 0) {
         t.fused = 1;
         t.waves = 4;
-        t.tiles_per_wave = 4;
+        t.tiles_per_wave = 8;
     } else {
         t.fused = 0;
         t.waves = 4;
@@ -353,8 +357,18 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     ip.warp_mode = P->warp;
     ip.stop_eps_t = P->stop_eps_t;
     ip.stop_eps_r = P->stop_eps_r;
+    int total_iters = 0;
+    for (const Step& stp : sched) total_iters += stp.iters;
+    if (c->profiling) {
+        while ((int)c->events.size() < 5 * total_iters) {
+            hipEvent_t ev;
+            HIPCHK(c, hipEventCreate(&ev));
+            c->events.push_back(ev);
+        }
+    }
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = hipSuccess;
+        int ev_base = 0;
         for (const Step& stp : sched) {
             const int l = stp.level;
             if ((e = launch_level_start(s, static_cast<PairState*>(c->states.p), n)) != hipSuccess)
@@ -376,16 +390,22 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             il.pair_red_begin = reinterpret_cast<const int*>(tbase + lt[l].begin_off);
             il.partials = static_cast<float2*>(c->partials.p);
             il.update = update;
-            for (int it = 0; it < stp.iters; ++it)
-                if ((e = launch_iteration(s, il)) != hipSuccess) return e;
+            for (int it = 0; it < stp.iters; ++it) {
+                const hipEvent_t* ev = c->profiling ? &c->events[5 * (ev_base + it)] : nullptr;
+                if ((e = launch_iteration(s, il, ev)) != hipSuccess) return e;
+            }
+            ev_base += stp.iters;
         }
         return e;
     };
-    if (c->use_graphs) {
+    // Timing events inside a captured graph cannot be read back, so a profiled
+    // call launches directly.
+    if (c->use_graphs && !c->profiling) {
         std::string key;
         {
             char buf[160];
-            snprintf(buf, sizeof buf, "n%d f%d u%d L%d g%d|", n, f16, update, L, c->generation);
+            snprintf(buf, sizeof buf, "n%d f%d u%d L%d g%d p%d|", n, f16, update, L, c->generation,
+                     (int)c->profiling);
             key = buf;
             for (int i = 0; i < n; ++i) {
                 snprintf(buf, sizeof buf, "%dx%d,", A[i]->w[0], A[i]->h[0]);
@@ -430,6 +450,17 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     if ((st = ensure_down(c, states_bytes)) != RGBID_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->h_down, c->states.p, states_bytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->profiling) {
+        int j = 0;
+        for (const Step& stp : sched)
+            for (int it = 0; it < stp.iters; ++it, ++j)
+                for (int k = 0; k < 4; ++k) {
+                    float ms = 0.0f;
+                    HIPCHK(c, hipEventElapsedTime(&ms, c->events[5 * j + k], c->events[5 * j + k + 1]));
+                    c->prof_ms[stp.level * 4 + k] += ms;
+                    c->prof_n[stp.level * 4 + k] += 1;
+                }
+    }
     const PairState* res = static_cast<const PairState*>(c->h_down);
     for (int i = 0; i < n; ++i) {
         const PairState& s = res[i];
@@ -539,6 +570,7 @@ void rgbid_destroy(rgbid_ctx* c)
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
                       &c->frames})
         if (b->p) hipFree(b->p);
@@ -794,6 +826,41 @@ rgbid_status rgbid_keyframe_read(rgbid_ctx* c, const rgbid_kf* kf, float* W_out,
     const size_t bytes = (size_t)kf->cam.width * kf->cam.height * sizeof(float);
     if (W_out) HIPCHK(c, hipMemcpyAsync(W_out, kf->W, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (C_out) HIPCHK(c, hipMemcpyAsync(C_out, kf->C, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_keyframe_reset(rgbid_ctx* c, rgbid_kf* kf, const float* W_dev,
+                                  size_t pitch_elems)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!kf || !W_dev) return set_err(c, RGBID_E_ARG, "NULL keyframe or image");
+    if (kf->device != c->device) return set_err(c, RGBID_E_ARG, "keyframe on another device");
+    if (pitch_elems < (size_t)kf->cam.width) return set_err(c, RGBID_E_ARG, "pitch < width");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_copy_valid(c->stream, W_dev, (long long)pitch_elems, kf->cam.width,
+                                kf->cam.height, kf->W));
+    HIPCHK(c, launch_fill(c->stream, kf->C, kf->cam.width * kf->cam.height, 1.0f));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_set_profiling(rgbid_ctx* c, int on)
+{
+    if (!c) return RGBID_E_ARG;
+    c->profiling = on != 0;
+    for (int i = 0; i < kMaxLevels * 4; ++i) {
+        c->prof_ms[i] = 0.0;
+        c->prof_n[i] = 0;
+    }
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_kernel_times(const rgbid_ctx* c, double* ms_total, long long* launches)
+{
+    if (!c || !ms_total || !launches) return RGBID_E_ARG;
+    for (int i = 0; i < kMaxLevels * 4; ++i) {
+        ms_total[i] = c->prof_ms[i];
+        launches[i] = c->prof_n[i];
+    }
     return RGBID_OK;
 }
 

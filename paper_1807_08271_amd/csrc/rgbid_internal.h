@@ -115,7 +115,9 @@ struct IterLaunch {
     float2* partials;            // n_red_chunks * kNSum
     int update;                  // 0: normal equations only
 };
-hipError_t launch_iteration(hipStream_t s, const IterLaunch& L);
+// ev: NULL, or 5 events recorded before the warp kernel and after each of
+// the four kernels (for per-kernel timing).
+hipError_t launch_iteration(hipStream_t s, const IterLaunch& L, hipEvent_t const* ev);
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs);
 
 struct FuseArgs {

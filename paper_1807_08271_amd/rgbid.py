@@ -100,7 +100,10 @@ _SIGS = {
     "rgbid_fuse": (C.c_int, [_P, _P, _P, C.c_size_t, C.POINTER(rgbid_pose), C.c_double,
                              C.POINTER(C.c_longlong)]),
     "rgbid_keyframe_read": (C.c_int, [_P, _P, _P, _P]),
+    "rgbid_keyframe_reset": (C.c_int, [_P, _P, _P, C.c_size_t]),
     "rgbid_keyframe_free": (None, [_P]),
+    "rgbid_set_profiling": (C.c_int, [_P, C.c_int]),
+    "rgbid_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
 }
 
 
@@ -319,6 +322,32 @@ def rgbid_keyframe_read(ctx, kf, shape, device=None):
     Cm = torch.empty((h, w), dtype=torch.float32, device=device or "cuda")
     _check(ctx, lib().rgbid_keyframe_read(ctx, kf, C.c_void_p(W.data_ptr()), C.c_void_p(Cm.data_ptr())))
     return W, Cm
+
+
+def rgbid_keyframe_reset(ctx, kf, W):
+    pW, pitch = _img(W)
+    _check(ctx, lib().rgbid_keyframe_reset(ctx, kf, pW, pitch))
+
+
+RGBID_K_WARP, RGBID_K_SCALE, RGBID_K_REDUCE, RGBID_K_SOLVE = 0, 1, 2, 3
+KERNEL_NAMES = ("warp", "scale", "reduce", "solve")
+
+
+def rgbid_set_profiling(ctx, on: bool):
+    _check(ctx, lib().rgbid_set_profiling(ctx, int(bool(on))))
+
+
+def rgbid_kernel_times(ctx):
+    """{(level, kernel name): (total ms, launches)} for entries with launches."""
+    ms = (C.c_double * 32)()
+    n = (C.c_longlong * 32)()
+    _check(ctx, lib().rgbid_kernel_times(ctx, ms, n))
+    out = {}
+    for l in range(8):
+        for k in range(4):
+            if n[l * 4 + k]:
+                out[(l, KERNEL_NAMES[k])] = (ms[l * 4 + k], n[l * 4 + k])
+    return out
 
 
 def rgbid_keyframe_free(kf):

@@ -60,8 +60,8 @@ def test_pyramid_matches_oracle(ctx, c2_pairs, storage):
         assert Ig.shape == Ir.shape
         np.testing.assert_array_equal(Wg > 0, Wr > 0)
         if storage == 0:
-            np.testing.assert_allclose(Ig, Ir, rtol=2e-7, atol=0)
-            np.testing.assert_allclose(Wg, Wr, rtol=2e-7, atol=0)
+            np.testing.assert_allclose(Ig, Ir, rtol=5e-7, atol=0)   # FP32 vs FP64 sum order
+            np.testing.assert_allclose(Wg, Wr, rtol=5e-7, atol=0)
         else:
             # FP16 levels: identical rounding except rare double-rounding ties
             assert np.mean(Ig != Ir) < 1e-3 and np.mean(Wg != Wr) < 1e-3
@@ -276,6 +276,10 @@ def test_argument_errors(ctx):
 
 
 def test_fuse_20_frames_matches_oracle(ctx):
+    # Decisions are compared frame by frame (a pixel was fused iff its C grew);
+    # W is compared on the pixels whose 20 decisions all agree.  A decision
+    # can flip only for a pixel whose |W_k(p_w) - 1/Y_z| lies within FP32
+    # rounding of tol.
     rg = _rg()
     import torch
     cam, kf, frames, poses = synth.keyframe_sequence(20, seed=0, ss=2)
@@ -284,14 +288,39 @@ def test_fuse_20_frames_matches_oracle(ctx):
     K = rg.rgbid_keyframe_init(ctx, cam, Wd)
     Wr, Cr = Wkf0.copy(), np.ones_like(Wkf0)
     tol = 0.01
+    agree = np.ones(Wkf0.shape, dtype=bool)
+    Cg_prev = np.ones_like(Wkf0)
+    total_fused = 0
     for f, (R, t) in zip(frames, poses):
         n = rg.rgbid_fuse(ctx, K, torch.from_numpy(f.W).cuda(), (R, t), tol)
+        Cr_prev = Cr
         Wr, Cr, nr = oracle.fuse(cam, Wr, Cr, f.W, R, t, tol)
-        assert abs(n - nr) <= 50, (n, nr)
+        _, Cg = rg.rgbid_keyframe_read(ctx, K, (cam.h, cam.w))
+        Cg = Cg.cpu().numpy().astype(np.float64)
+        dec_g, dec_r = Cg > Cg_prev, Cr > Cr_prev
+        flips = int((dec_g != dec_r).sum())
+        assert flips <= 20, flips
+        assert int(dec_g.sum()) == n and int(dec_r.sum()) == nr
+        agree &= dec_g == dec_r
+        Cg_prev = Cg
+        total_fused += n
+    assert total_fused > 20 * 0.5 * cam.w * cam.h
     Wg, Cg = rg.rgbid_keyframe_read(ctx, K, (cam.h, cam.w))
     Wg, Cg = Wg.cpu().numpy().astype(np.float64), Cg.cpu().numpy().astype(np.float64)
-    same = np.isclose(Cg, Cr, rtol=1e-4)        # same set of fusion decisions
-    assert same.mean() > 0.995
-    np.testing.assert_allclose(Wg[same], Wr[same], rtol=1e-5)
+    assert agree.mean() > 0.999
+    # Occlusion edges of the keyframe: bilinear taps there straddle a depth
+    # jump, so an FP32 position error of ~3e-5 px moves W* by slope x 3e-5.
+    # Those pixels get 1e-4; all others 1e-5.
+    Wp = np.pad(Wkf0, 1, mode="edge")
+    edge = np.zeros_like(agree)
+    for dv in (-1, 0, 1):
+        for du in (-1, 0, 1):
+            nb = Wp[1 + dv:1 + dv + cam.h, 1 + du:1 + du + cam.w]
+            edge |= np.abs(nb - Wkf0) > 0.05 * np.maximum(Wkf0, 1e-9)
+    flat = agree & ~edge
+    assert flat.mean() > 0.95
+    np.testing.assert_allclose(Wg[flat], Wr[flat], rtol=1e-5)
+    np.testing.assert_allclose(Wg[agree], Wr[agree], rtol=1e-4)
+    np.testing.assert_allclose(Cg[agree], Cr[agree], rtol=1e-5)
     assert np.all((Wg > 0) == (Wkf0 > 0))       # keyframe holes stay holes
     rg.rgbid_keyframe_free(K)
