@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--warp", choices=["fullres", "per_level"], default="fullres")
     ap.add_argument("--weight", choices=["huber", "student_t"], default="huber")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-file", default=None, help="load tuned launch shapes from this file")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -175,6 +177,20 @@ def main():
     all_I = IA + IB
     all_W = WA + WB
     torch.cuda.synchronize()
+
+    tuned = None
+    if args.tune_file:
+        rg.rgbid_tune_load(ctx, args.tune_file)
+        tuned = "loaded"
+    elif not args.no_autotune:
+        t0 = time.time()
+        best = rg.rgbid_autotune(ctx, As, Bs, params, reps=3)
+        tuned = [round(1e3 * b, 2) for b in best]
+        log("autotuned launch shapes in %.1fs: best us/iteration per level %s" % (
+            time.time() - t0, tuned))
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        rg.rgbid_tune_save(ctx, os.path.join(ROOT, "gpurun_out", "tune_%s_%s.txt" % (
+            args.storage, args.warp)))
 
     def step():
         rg.rgbid_pyramid_update_batch(ctx, all_pyr, all_I, all_W)
@@ -247,7 +263,8 @@ def main():
                                "20 frames into one keyframe" % (args.pairs, args.warp),
                    "pairs_per_step": args.pairs, "width": cam.w, "height": cam.h, "levels": 4,
                    "iters_per_level": 10, "warp": args.warp, "weight": args.weight,
-                   "storage": args.storage, "parallelism": "single GPU"},
+                   "storage": args.storage, "parallelism": "single GPU",
+                   "autotuned_us_per_iteration": tuned},
         "roofline": roofline,
         "accuracy": {"max_rot_err_vs_truth_rad": float(max(errs)),
                      "max_trans_err_vs_truth_m": float(max(terrs)), "degenerate_pairs": bad},

@@ -209,6 +209,25 @@ rgbid_status rgbid_normal_equations(rgbid_ctx* ctx, const rgbid_pyr* A, const rg
                                     const rgbid_align_params* params,
                                     rgbid_align_stats* out);
 
+/* ------------------------------------------------------------ autotuner */
+
+/* Times, for every level of `params`, candidate launch shapes of the pixel
+   kernels on this batch -- warp fused into the reduction or stored, 2 / 4 / 8
+   waves per workgroup, 1 / 2 / 4 / 8 / 16 tiles of 64 pixels per wave, and
+   XCD-aware chunk order on or off -- over `reps` replayed iterations
+   (normal equations only, the poses stay at the identity), and keeps the
+   fastest for later calls with a batch of the same shape (pair sizes in
+   order, levels, warp mode, storage) on this context.  best_ms (params->levels
+   entries or NULL) receives the best time per iteration.  Synchronises. */
+rgbid_status rgbid_autotune(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
+                            const rgbid_pyr* const* B, const rgbid_align_params* params, int reps,
+                            double* best_ms);
+
+/* Writes / reads the context's tuned launch shapes as text (one
+   "key fused waves tiles_per_wave xcd_remap" line per entry). */
+rgbid_status rgbid_tune_save(const rgbid_ctx* ctx, const char* path);
+rgbid_status rgbid_tune_load(rgbid_ctx* ctx, const char* path);
+
 /* ------------------------------------------------------------ keyframe fusion */
 
 /* Creates a keyframe from a caller-owned FP32 inverse-depth map (copied) with
@@ -239,6 +258,68 @@ rgbid_status rgbid_keyframe_read(rgbid_ctx* ctx, const rgbid_kf* kf, float* W_ou
                                  float* C_out_dev);
 
 void rgbid_keyframe_free(rgbid_kf* kf);
+
+/* ------------------------------------------------------------ pose maps */
+
+/* Decoupled exponential and logarithm of sec. 3: exp(xi) = (Rot(theta), v) for
+   xi = (v, theta); log(T) = (t, log R) with |theta| < pi.  Host only. */
+void rgbid_pose_exp(const double xi[6], rgbid_pose* T);
+void rgbid_pose_log(const rgbid_pose* T, double xi[6]);
+
+/* ------------------------------------------------------------ learned warm start */
+
+/* A convolutional network that predicts the initial twist of an alignment
+   from the 80 x 60 pyramid level of both frames (an addition to the method:
+   the paper starts from the identity or a constant-velocity guess, sec. 6.2,
+   sec. 7.1).  Gauss-Newton always runs after it.  Input per pair: 4 x 60 x 80
+   FP32 (I_A/255, W_A/2, I_B/255, W_B/2, holes as 0).  Layers: 4 x [3x3
+   convolution, stride 2, zero padding 1, bias, ReLU] with channels 4 -> 32 ->
+   64 -> 128 -> 128, global average pool, fully connected 128 -> 6.  The output
+   o is normalised: xi0 = o * (0.15, 0.15, 0.15, 0.1745, 0.1745, 0.1745) (m, rad).
+   Parameters (rgbid_warmstart_param_count() floats, FP32 master copy) are laid
+   out w1 b1 w2 b2 w3 b3 w4 b4 wfc bfc, conv weights as Co x Ci x 3 x 3, FC as
+   6 x 128.  Weights are used in bfloat16 (nearest even), biases, activations,
+   gradients and AdamW state in FP32. */
+typedef struct rgbid_net rgbid_net;
+
+size_t rgbid_warmstart_param_count(void);
+
+/* Creates a network from host FP32 parameters (copied) with zeroed AdamW
+   state.  Does not synchronise.  Errors: E_ARG, E_NOMEM, E_DEVICE. */
+rgbid_status rgbid_warmstart_create(rgbid_ctx* ctx, const float* params_host, rgbid_net** out);
+void rgbid_warmstart_free(rgbid_net* net);
+
+/* Copies the FP32 master parameters to host memory (synchronises). */
+rgbid_status rgbid_warmstart_get_params(rgbid_ctx* ctx, const rgbid_net* net, float* params_host);
+
+/* Builds the n x 4 x 60 x 80 input in caller-owned device memory x_dev from
+   the level of each pair's pyramids whose size is 80 x 60.  Does not
+   synchronise.  Errors: E_ARG, E_SHAPE (no 80 x 60 level). */
+rgbid_status rgbid_warmstart_input(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
+                                   const rgbid_pyr* const* B, float* x_dev);
+
+/* Forward pass on n inputs; writes the predicted twists xi0 (n x 6, metres and
+   radians) to host memory (synchronises). */
+rgbid_status rgbid_warmstart_forward(rgbid_ctx* ctx, rgbid_net* net, int n, const float* x_dev,
+                                     double* xi_out);
+
+/* Input + forward + exponential: initial poses for rgbid_align_batch. */
+rgbid_status rgbid_warmstart_predict(rgbid_ctx* ctx, rgbid_net* net, int n,
+                                     const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                                     float* x_scratch_dev, rgbid_pose* init_out);
+
+/* Loss (mean over the batch of the squared normalised twist error) and its
+   gradient w.r.t. every parameter for labels xi (n x 6, host), without an
+   update.  grad_host: rgbid_warmstart_param_count() floats or NULL.
+   Synchronises. */
+rgbid_status rgbid_warmstart_gradient(rgbid_ctx* ctx, rgbid_net* net, int n, const float* x_dev,
+                                      const double* xi, double* loss, float* grad_host);
+
+/* One AdamW training step (beta 0.9 / 0.999, eps 1e-8, decoupled weight decay
+   wd on the weights only) on a batch; writes the batch loss before the update
+   if loss != NULL (synchronises only then). */
+rgbid_status rgbid_warmstart_train_step(rgbid_ctx* ctx, rgbid_net* net, int n, const float* x_dev,
+                                        const double* xi, double lr, double wd, double* loss);
 
 /* ------------------------------------------------------------ diagnostics */
 

@@ -631,21 +631,51 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const int end = ch.first + ch.count;
     const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
     const Geom G = make_geom(S, D.A[wl], D.B[wl]);
-    for (int tile = ch.first + wave; tile < end; tile += waves) {
-        float Is = 0.0f, Ws = 0.0f;
-        bool wv = false;
-        int u = 0, v = 0, idx;
-        Terms T;
-        if constexpr (FUSED && LOG2B == 0) {
-            // the level pixel is its own warp child: W_A comes with A's (I, W)
-            idx = tile * 64 + lane;
-            const int ic = idx < gd.n ? idx : 0;
-            split_index(ic, gd.gw, gd.inv_gw, u, v);
-            const float2 c = load_iw<F16>(A.iw, ic);
-            const Nbrs nb = load_nbrs<F16>(A, u, v);
-            wv = warp_core<F16>(G, u, v, c.y, Is, Ws) && idx < gd.n;
+    if constexpr (FUSED && LOG2B == 0) {
+        // The level pixel is its own warp child, so W_A comes with A's (I, W).
+        // A's loads for the next tile are issued while this tile's gathers
+        // from B are in flight.
+        int tile = ch.first + wave;
+        int idx = tile * 64 + lane;
+        int ic = idx < gd.n ? idx : 0;
+        int u, v;
+        split_index(ic, gd.gw, gd.inv_gw, u, v);
+        float2 c = load_iw<F16>(A.iw, ic);
+        Nbrs nb = load_nbrs<F16>(A, u, v);
+        for (; tile < end; tile += waves) {
+            float Is, Ws;
+            const bool wv = warp_core<F16>(G, u, v, c.y, Is, Ws) && idx < gd.n;
+            const int ntile = tile + waves;
+            const int nidx = ntile * 64 + lane;
+            const int nic = (ntile < end && nidx < gd.n) ? nidx : ic;
+            int nu, nv;
+            split_index(nic, gd.gw, gd.inv_gw, nu, nv);
+            const float2 nc = load_iw<F16>(A.iw, nic);
+            const Nbrs nnb = load_nbrs<F16>(A, nu, nv);
+            Terms T;
             terms_core<true>(A, ifx, ify, u, v, c, nb, Is, Ws, wv, T);
-        } else {
+            if (T.vI && enI) {
+                const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
+                accum(acc, T.JI, w, T.rI);
+                acc[28] += 1.0f;
+            }
+            if (T.vW && enW) {
+                const float w = T.lam * omega(kind, (T.rW - muW) * isW, nuW, kh) * wW0;
+                accum(acc, T.JW, w, T.rW);
+                acc[29] += 1.0f;
+            }
+            idx = nidx;
+            ic = nic;
+            u = nu;
+            v = nv;
+            c = nc;
+            nb = nnb;
+        }
+    } else {
+        for (int tile = ch.first + wave; tile < end; tile += waves) {
+            float Is = 0.0f, Ws = 0.0f;
+            bool wv = false;
+            int u = 0, v = 0, idx;
             if constexpr (FUSED) {
                 warp_tile<F16, LOG2B>(G, tile * 64, gd.gw, gd.inv_gw, gd.n, 1, lane, Is, Ws, wv, u,
                                       v, idx);
@@ -658,17 +688,18 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
                 wv = Ws > 0.0f && idx < gd.n;
                 split_index(ic, gd.gw, gd.inv_gw, u, v);
             }
+            Terms T;
             pixel_terms<F16, true>(A, ifx, ify, u, v, Is, Ws, wv, T);
-        }
-        if (T.vI && enI) {
-            const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
-            accum(acc, T.JI, w, T.rI);
-            acc[28] += 1.0f;
-        }
-        if (T.vW && enW) {
-            const float w = T.lam * omega(kind, (T.rW - muW) * isW, nuW, kh) * wW0;
-            accum(acc, T.JW, w, T.rW);
-            acc[29] += 1.0f;
+            if (T.vI && enI) {
+                const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
+                accum(acc, T.JI, w, T.rI);
+                acc[28] += 1.0f;
+            }
+            if (T.vW && enW) {
+                const float w = T.lam * omega(kind, (T.rW - muW) * isW, nuW, kh) * wW0;
+                accum(acc, T.JW, w, T.rW);
+                acc[29] += 1.0f;
+            }
         }
     }
 #pragma unroll

@@ -38,6 +38,15 @@ struct rgbid_kf {
     void* base;
 };
 
+struct rgbid_net {
+    int device;
+    rgbid::CnnBuffers buf;
+    void* base;           // parameters, moments, gradient, bf16 copy
+    void* act_base;       // activations for `cap` samples
+    int cap;
+    int step;
+};
+
 namespace {
 
 struct DevBuf {
@@ -68,6 +77,7 @@ struct rgbid_ctx {
     bool use_graphs = true;
     std::map<std::string, std::pair<int, hipGraphExec_t>> graphs;
     std::map<std::string, LevelTune> tunes;   // per (level shape) launch shape
+    hipEvent_t tev[2] = {nullptr, nullptr};   // launch-region timing (autotuner)
     bool profiling = false;
     std::vector<hipEvent_t> events;  // timing events, grown on demand
     double prof_ms[kMaxLevels * 4] = {};
@@ -209,13 +219,31 @@ struct Step {
     int iters;
 };
 
+// Launch shapes are tuned per batch shape: level, warp mode, storage format
+// and the run-length encoded list of pair sizes.
+std::string tune_key(int n, const rgbid_pyr* const* A, int level, int warp, int f16)
+{
+    char buf[64];
+    snprintf(buf, sizeof buf, "l%d_m%d_f%d", level, warp, f16);
+    std::string k = buf;
+    int i = 0;
+    while (i < n) {
+        int j = i;
+        while (j < n && A[j]->w[0] == A[i]->w[0] && A[j]->h[0] == A[i]->h[0]) ++j;
+        snprintf(buf, sizeof buf, "_%dx%dx%d", A[i]->w[0], A[i]->h[0], j - i);
+        k += buf;
+        i = j;
+    }
+    return k;
+}
+
 // The batched driver: n pairs, a schedule of (level, iterations), update on
 // or off.  Writes poses and stats (host) and returns OK unless an argument or
 // the device failed.
 rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgbid_pyr* const* B,
                        const rgbid_pose* init, const rgbid_align_params* P,
                        const std::vector<Step>& sched, int update, rgbid_pose* out,
-                       rgbid_align_stats* stats)
+                       rgbid_align_stats* stats, float* launch_ms = nullptr)
 {
     if (!c) return RGBID_E_ARG;
     if (n < 1 || !A || !B) return set_err(c, RGBID_E_ARG, "need n >= 1 and pyramid arrays");
@@ -248,8 +276,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     std::vector<size_t> warped_off(n, 0);
     for (int l = 0; l < L; ++l) {
         const int b = fullres ? l : 0;
-        char key[96];
-        snprintf(key, sizeof key, "w%d_h%d_l%d_m%d_f%d", A[0]->w[0], A[0]->h[0], l, P->warp, f16);
+        const std::string key = tune_key(n, A, l, P->warp, f16);
         auto it = c->tunes.find(key);
         tune[l] = it != c->tunes.end() ? it->second : default_tune(b);
         const int lpp = std::min(1 << (2 * b), 64), gpp = 64 / lpp;
@@ -441,9 +468,13 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             }
             it = c->graphs.emplace(key, std::make_pair(c->generation, ex)).first;
         }
+        if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
         HIPCHK(c, hipGraphLaunch(it->second.second, c->stream));
+        if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
     } else {
+        if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
         HIPCHK(c, enqueue(c->stream));
+        if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
     }
 
     // ---- results
@@ -461,6 +492,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                     c->prof_n[stp.level * 4 + k] += 1;
                 }
     }
+    if (launch_ms) HIPCHK(c, hipEventElapsedTime(launch_ms, c->tev[0], c->tev[1]));
     const PairState* res = static_cast<const PairState*>(c->h_down);
     for (int i = 0; i < n; ++i) {
         const PairState& s = res[i];
@@ -554,7 +586,8 @@ rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream)
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&c->tev[0]) != hipSuccess || hipEventCreate(&c->tev[1]) != hipSuccess) {
         delete c;
         return RGBID_E_DEVICE;
     }
@@ -577,6 +610,8 @@ void rgbid_destroy(rgbid_ctx* c)
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->h_down) hipHostFree(c->h_down);
     if (c->stage_done) hipEventDestroy(c->stage_done);
+    for (hipEvent_t e : c->tev)
+        if (e) hipEventDestroy(e);
     if (c->cap) hipStreamDestroy(c->cap);
     delete c;
 }
@@ -745,6 +780,95 @@ rgbid_status rgbid_normal_equations(rgbid_ctx* c, const rgbid_pyr* A, const rgbi
     return run_batch(c, 1, a, b, T, P, sched, 0, &o, out);
 }
 
+rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
+                            const rgbid_pyr* const* B, const rgbid_align_params* P, int reps,
+                            double* best_ms)
+{
+    if (!c) return RGBID_E_ARG;
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    if (n < 1 || !A || !B || reps < 1) return set_err(c, RGBID_E_ARG, "bad arguments");
+    for (int i = 0; i < n; ++i)
+        if (!A[i] || !B[i]) return set_err(c, RGBID_E_ARG, "NULL pyramid %d", i);
+    HIPCHK(c, hipSetDevice(c->device));
+    const int f16 = A[0]->f16;
+    const bool saved_prof = c->profiling;
+    c->profiling = false;
+    std::vector<rgbid_pose> o(n);
+    for (int l = 0; l < P->levels; ++l) {
+        const std::string key = tune_key(n, A, l, P->warp, f16);
+        const int b = P->warp == RGBID_WARP_FULLRES ? l : 0;
+        LevelTune best = default_tune(b);
+        float best_t = 1e30f;
+        for (int fused = 0; fused < 2; ++fused)
+            for (int waves : {2, 4, 8})
+                for (int tpw : {1, 2, 4, 8, 16})
+                    for (int remap = 0; remap < 2; ++remap) {
+                        LevelTune t;
+                        t.fused = fused;
+                        t.waves = waves;
+                        t.tiles_per_wave = tpw;
+                        t.xcd_remap = remap;
+                        c->tunes[key] = t;
+                        std::vector<Step> sched{Step{l, reps}};
+                        float ms = 0.0f;
+                        // first call captures the graph, second is timed
+                        rgbid_status st = run_batch(c, n, A, B, nullptr, P, sched, 0, o.data(),
+                                                    nullptr);
+                        if (st == RGBID_OK)
+                            st = run_batch(c, n, A, B, nullptr, P, sched, 0, o.data(), nullptr, &ms);
+                        if (st != RGBID_OK) {
+                            c->profiling = saved_prof;
+                            c->tunes[key] = best;
+                            return st;
+                        }
+                        if (ms < best_t) {
+                            best_t = ms;
+                            best = t;
+                        }
+                    }
+        c->tunes[key] = best;
+        if (best_ms) best_ms[l] = best_t / reps;
+    }
+    // drop the candidate graphs
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
+    c->graphs.clear();
+    c->profiling = saved_prof;
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_tune_save(const rgbid_ctx* c, const char* path)
+{
+    if (!c || !path) return RGBID_E_ARG;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return RGBID_E_ARG;
+    for (const auto& kv : c->tunes)
+        std::fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.fused, kv.second.waves,
+                     kv.second.tiles_per_wave, kv.second.xcd_remap);
+    std::fclose(f);
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_tune_load(rgbid_ctx* c, const char* path)
+{
+    if (!c || !path) return RGBID_E_ARG;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return set_err(c, RGBID_E_ARG, "cannot open %s", path);
+    char key[512];
+    LevelTune t;
+    int nread = 0;
+    while (std::fscanf(f, "%511s %d %d %d %d", key, &t.fused, &t.waves, &t.tiles_per_wave,
+                       &t.xcd_remap) == 5) {
+        if (t.waves < 1 || t.waves > 8 || t.tiles_per_wave < 1 || t.tiles_per_wave > 64) continue;
+        c->tunes[key] = t;
+        ++nread;
+    }
+    std::fclose(f);
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
+    c->graphs.clear();
+    return nread > 0 ? RGBID_OK : set_err(c, RGBID_E_ARG, "no tune entries in %s", path);
+}
+
 rgbid_status rgbid_keyframe_init(rgbid_ctx* c, const rgbid_camera* cam, const float* W_dev,
                                  size_t pitch_elems, rgbid_kf** out)
 {
@@ -871,6 +995,275 @@ void rgbid_keyframe_free(rgbid_kf* kf)
     hipDeviceSynchronize();
     hipFree(kf->base);
     delete kf;
+}
+
+}  // extern "C"
+
+// ====================================================================== pose maps, warm start
+
+namespace {
+
+void rot_exp(const double th[3], double R[9])
+{
+    const double n = std::sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    const double S[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+    double S2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += S[3 * i + k] * S[3 * k + j];
+            S2[3 * i + j] = acc;
+        }
+    const double a = n < 1e-8 ? 1.0 : std::sin(n) / n;
+    const double b = n < 1e-8 ? 0.5 : (1.0 - std::cos(n)) / (n * n);
+    for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + a * S[i] + b * S2[i];
+}
+
+const double kXiScale[6] = {0.15, 0.15, 0.15, 0.1745, 0.1745, 0.1745};
+
+rgbid_status net_reserve(rgbid_ctx* c, rgbid_net* net, int n)
+{
+    if (n <= net->cap) return RGBID_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (net->act_base) HIPCHK(c, hipFree(net->act_base));
+    net->act_base = nullptr;
+    net->cap = 0;
+    const int cap = std::max(n, 64);
+    size_t off[16], total = 0;
+    int k = 0;
+    auto add = [&](size_t bytes) { off[k++] = total; total = align_up(total + bytes, 256); };
+    for (int l = 0; l < 4; ++l) add((size_t)cap * kCnnCh[l + 1] * kCnnHs[l + 1] * kCnnWs[l + 1] * 4);
+    for (int l = 0; l < 4; ++l) add((size_t)cap * kCnnCh[l + 1] * kCnnHs[l + 1] * kCnnWs[l + 1] * 4);
+    add((size_t)cap * 128 * 4);
+    add((size_t)cap * 6 * 4);
+    add((size_t)cap * 6 * 4);
+    add((size_t)cap * 4);
+    add((size_t)cap * 6 * 4);
+    HIPCHK(c, hipMalloc(&net->act_base, total));
+    char* b = static_cast<char*>(net->act_base);
+    for (int l = 0; l < 4; ++l) net->buf.act[l] = reinterpret_cast<float*>(b + off[l]);
+    for (int l = 0; l < 4; ++l) net->buf.dz[l] = reinterpret_cast<float*>(b + off[4 + l]);
+    net->buf.pooled = reinterpret_cast<float*>(b + off[8]);
+    net->buf.out = reinterpret_cast<float*>(b + off[9]);
+    net->buf.dout = reinterpret_cast<float*>(b + off[10]);
+    net->buf.loss_n = reinterpret_cast<float*>(b + off[11]);
+    net->buf.target = reinterpret_cast<float*>(b + off[12]);
+    net->cap = cap;
+    return RGBID_OK;
+}
+
+rgbid_status net_targets(rgbid_ctx* c, rgbid_net* net, int n, const double* xi)
+{
+    char* stage;
+    rgbid_status st;
+    if ((st = stage_begin(c, (size_t)n * 6 * sizeof(float), &stage)) != RGBID_OK) return st;
+    float* t = reinterpret_cast<float*>(stage);
+    for (int i = 0; i < n * 6; ++i) t[i] = (float)(xi[i] / kXiScale[i % 6]);
+    HIPCHK(c, hipMemcpyAsync(net->buf.target, t, (size_t)n * 6 * sizeof(float),
+                             hipMemcpyHostToDevice, c->stream));
+    return stage_end(c);
+}
+
+rgbid_status net_loss(rgbid_ctx* c, rgbid_net* net, int n, double* loss)
+{
+    rgbid_status st;
+    if ((st = ensure_down(c, (size_t)n * sizeof(float))) != RGBID_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->h_down, net->buf.loss_n, (size_t)n * sizeof(float),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const float* l = static_cast<const float*>(c->h_down);
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += l[i];
+    *loss = s / n;
+    return RGBID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rgbid_pose_exp(const double xi[6], rgbid_pose* T)
+{
+    if (!xi || !T) return;
+    rot_exp(xi + 3, T->R);
+    for (int i = 0; i < 3; ++i) T->t[i] = xi[i];
+}
+
+void rgbid_pose_log(const rgbid_pose* T, double xi[6])
+{
+    if (!xi || !T) return;
+    const double* R = T->R;
+    double cth = (R[0] + R[4] + R[8] - 1.0) / 2.0;
+    cth = std::min(1.0, std::max(-1.0, cth));
+    const double n = std::acos(cth);
+    const double f = n < 1e-8 ? 0.5 : n / (2.0 * std::sin(n));
+    xi[0] = T->t[0];
+    xi[1] = T->t[1];
+    xi[2] = T->t[2];
+    xi[3] = f * (R[7] - R[5]);
+    xi[4] = f * (R[2] - R[6]);
+    xi[5] = f * (R[3] - R[1]);
+}
+
+size_t rgbid_warmstart_param_count(void) { return (size_t)kCnnParams; }
+
+rgbid_status rgbid_warmstart_create(rgbid_ctx* c, const float* params, rgbid_net** out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out || !params) return set_err(c, RGBID_E_ARG, "NULL parameters or output");
+    *out = nullptr;
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_net* net = new (std::nothrow) rgbid_net();
+    if (!net) return set_err(c, RGBID_E_NOMEM, "host allocation failed");
+    net->device = c->device;
+    const size_t P = kCnnParams, f = align_up(P * 4, 256);
+    const size_t total = 5 * f + align_up(P * 2, 256);
+    hipError_t e = hipMalloc(&net->base, total);
+    if (e != hipSuccess) {
+        delete net;
+        return set_err(c, RGBID_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
+    char* b = static_cast<char*>(net->base);
+    net->buf.w = reinterpret_cast<float*>(b);
+    net->buf.m = reinterpret_cast<float*>(b + f);
+    net->buf.v = reinterpret_cast<float*>(b + 2 * f);
+    net->buf.grad = reinterpret_cast<float*>(b + 3 * f);
+    net->buf.decay = reinterpret_cast<float*>(b + 4 * f);
+    net->buf.wbf = reinterpret_cast<__hip_bfloat16*>(b + 5 * f);
+    std::vector<float> decay(P, 0.0f);
+    for (int l = 0; l < 10; l += 2)
+        for (int i = kCnnOff[l]; i < kCnnOff[l + 1]; ++i) decay[i] = 1.0f;
+    e = hipMemcpy(net->buf.w, params, P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(net->buf.decay, decay.data(), P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(net->buf.m, 0, 2 * f, c->stream);
+    if (e == hipSuccess) e = cnn_refresh_bf16(c->stream, net->buf);
+    if (e != hipSuccess) {
+        hipFree(net->base);
+        delete net;
+        return set_err(c, RGBID_E_DEVICE, "warm-start init failed: %s", hipGetErrorString(e));
+    }
+    *out = net;
+    return RGBID_OK;
+}
+
+void rgbid_warmstart_free(rgbid_net* net)
+{
+    if (!net) return;
+    hipSetDevice(net->device);
+    hipDeviceSynchronize();
+    if (net->act_base) hipFree(net->act_base);
+    hipFree(net->base);
+    delete net;
+}
+
+rgbid_status rgbid_warmstart_get_params(rgbid_ctx* c, const rgbid_net* net, float* params)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!net || !params) return set_err(c, RGBID_E_ARG, "NULL network or output");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(params, net->buf.w, (size_t)kCnnParams * 4, hipMemcpyDeviceToHost));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_warmstart_input(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
+                                   const rgbid_pyr* const* B, float* x_dev)
+{
+    if (!c) return RGBID_E_ARG;
+    if (n < 1 || !A || !B || !x_dev) return set_err(c, RGBID_E_ARG, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    if ((st = ensure(c, c->frames, std::max(n * sizeof(CnnInput), sizeof(PyrFrame)))) != RGBID_OK)
+        return st;
+    char* stage;
+    if ((st = stage_begin(c, n * sizeof(CnnInput), &stage)) != RGBID_OK) return st;
+    CnnInput* in = reinterpret_cast<CnnInput*>(stage);
+    for (int i = 0; i < n; ++i) {
+        if (!A[i] || !B[i]) return set_err(c, RGBID_E_ARG, "NULL pyramid %d", i);
+        int la = -1, lb = -1;
+        for (int l = 0; l < A[i]->levels; ++l)
+            if (A[i]->w[l] == kCnnW && A[i]->h[l] == kCnnH) la = l;
+        for (int l = 0; l < B[i]->levels; ++l)
+            if (B[i]->w[l] == kCnnW && B[i]->h[l] == kCnnH) lb = l;
+        if (la < 0 || lb < 0) return set_err(c, RGBID_E_SHAPE, "pair %d has no 80x60 level", i);
+        in[i].A = A[i]->iw[la];
+        in[i].B = B[i]->iw[lb];
+        in[i].f16 = A[i]->f16;
+        if (B[i]->f16 != A[i]->f16) return set_err(c, RGBID_E_SHAPE, "pair %d mixes formats", i);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->frames.p, in, n * sizeof(CnnInput), hipMemcpyHostToDevice, c->stream));
+    if ((st = stage_end(c)) != RGBID_OK) return st;
+    HIPCHK(c, cnn_input(c->stream, static_cast<const CnnInput*>(c->frames.p), n, x_dev));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_warmstart_forward(rgbid_ctx* c, rgbid_net* net, int n, const float* x_dev,
+                                     double* xi_out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!net || n < 1 || !x_dev || !xi_out) return set_err(c, RGBID_E_ARG, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    if ((st = net_reserve(c, net, n)) != RGBID_OK) return st;
+    HIPCHK(c, cnn_forward(c->stream, net->buf, n, x_dev));
+    if ((st = ensure_down(c, (size_t)n * 6 * sizeof(float))) != RGBID_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->h_down, net->buf.out, (size_t)n * 6 * sizeof(float),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const float* o = static_cast<const float*>(c->h_down);
+    for (int i = 0; i < n * 6; ++i) xi_out[i] = (double)o[i] * kXiScale[i % 6];
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_warmstart_predict(rgbid_ctx* c, rgbid_net* net, int n,
+                                     const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                                     float* x_scratch, rgbid_pose* init_out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!init_out) return set_err(c, RGBID_E_ARG, "NULL output");
+    rgbid_status st;
+    if ((st = rgbid_warmstart_input(c, n, A, B, x_scratch)) != RGBID_OK) return st;
+    std::vector<double> xi((size_t)n * 6);
+    if ((st = rgbid_warmstart_forward(c, net, n, x_scratch, xi.data())) != RGBID_OK) return st;
+    for (int i = 0; i < n; ++i) rgbid_pose_exp(&xi[6 * i], &init_out[i]);
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_warmstart_gradient(rgbid_ctx* c, rgbid_net* net, int n, const float* x_dev,
+                                      const double* xi, double* loss, float* grad_host)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!net || n < 1 || !x_dev || !xi) return set_err(c, RGBID_E_ARG, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    if ((st = net_reserve(c, net, n)) != RGBID_OK) return st;
+    if ((st = net_targets(c, net, n, xi)) != RGBID_OK) return st;
+    HIPCHK(c, cnn_forward(c->stream, net->buf, n, x_dev));
+    HIPCHK(c, cnn_backward(c->stream, net->buf, n, x_dev, net->buf.target));
+    if (loss && (st = net_loss(c, net, n, loss)) != RGBID_OK) return st;
+    if (grad_host) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(grad_host, net->buf.grad, (size_t)kCnnParams * 4, hipMemcpyDeviceToHost));
+    }
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_warmstart_train_step(rgbid_ctx* c, rgbid_net* net, int n, const float* x_dev,
+                                        const double* xi, double lr, double wd, double* loss)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!net || n < 1 || !x_dev || !xi) return set_err(c, RGBID_E_ARG, "bad arguments");
+    if (!(lr > 0.0) || wd < 0.0) return set_err(c, RGBID_E_ARG, "lr must be > 0, wd >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    if ((st = net_reserve(c, net, n)) != RGBID_OK) return st;
+    if ((st = net_targets(c, net, n, xi)) != RGBID_OK) return st;
+    HIPCHK(c, cnn_forward(c->stream, net->buf, n, x_dev));
+    HIPCHK(c, cnn_backward(c->stream, net->buf, n, x_dev, net->buf.target));
+    net->step += 1;
+    HIPCHK(c, cnn_adamw(c->stream, net->buf, (float)lr, (float)wd, net->step));
+    if (loss && (st = net_loss(c, net, n, loss)) != RGBID_OK) return st;
+    return RGBID_OK;
 }
 
 }  // extern "C"

@@ -2,6 +2,7 @@
 // tables, per-pair state and the host launchers of each kernel family.
 #pragma once
 
+#include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -137,5 +138,47 @@ hipError_t launch_fill(hipStream_t s, float* p, int n, float v);
 // Dense copy of a pitched inverse-depth map with holes normalised to 0.
 hipError_t launch_copy_valid(hipStream_t s, const float* src, long long pitch, int w, int h,
                              float* dst);
+
+// ---------------------------------------------------------------- warm start
+
+constexpr int kCnnH = 60, kCnnW = 80;
+constexpr int kCnnCh[5] = {4, 32, 64, 128, 128};
+constexpr int kCnnHs[5] = {60, 30, 15, 8, 4};
+constexpr int kCnnWs[5] = {80, 40, 20, 10, 5};
+// parameter layout: w1 b1 w2 b2 w3 b3 w4 b4 wfc bfc (conv weights Co x Ci x 3 x 3)
+constexpr int kCnnOff[11] = {0,      1152,   1184,   19616,  19680, 93408,
+                             93536,  240992, 241120, 241888, 241894};
+constexpr int kCnnParams = 241894;
+
+// The 80x60 level of one pair's pyramids.
+struct CnnInput {
+    const void* A;     // interleaved (I, W) of A at the 80x60 level
+    const void* B;
+    int f16;
+    int pad;
+};
+
+struct CnnBuffers {
+    float* w;              // FP32 master parameters
+    float* m;              // AdamW moments
+    float* v;
+    float* grad;
+    float* decay;          // 1 for weights, 0 for biases
+    __hip_bfloat16* wbf;   // bf16 copy used by forward / backward
+    float* act[4];         // post-ReLU activations of the conv layers
+    float* dz[4];          // gradients w.r.t. the pre-activations
+    float* pooled;         // N x 128
+    float* out;            // N x 6 (normalised twist)
+    float* dout;
+    float* loss_n;
+    float* target;         // N x 6
+};
+
+hipError_t cnn_input(hipStream_t s, const CnnInput* in_dev, int n, float* x);
+hipError_t cnn_forward(hipStream_t s, const CnnBuffers& B, int N, const float* x);
+hipError_t cnn_backward(hipStream_t s, const CnnBuffers& B, int N, const float* x,
+                        const float* target);
+hipError_t cnn_adamw(hipStream_t s, const CnnBuffers& B, float lr, float wd, int step);
+hipError_t cnn_refresh_bf16(hipStream_t s, const CnnBuffers& B);
 
 }  // namespace rgbid

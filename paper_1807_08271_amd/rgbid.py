@@ -102,6 +102,24 @@ _SIGS = {
     "rgbid_keyframe_read": (C.c_int, [_P, _P, _P, _P]),
     "rgbid_keyframe_reset": (C.c_int, [_P, _P, _P, C.c_size_t]),
     "rgbid_keyframe_free": (None, [_P]),
+    "rgbid_pose_exp": (None, [C.POINTER(C.c_double), C.POINTER(rgbid_pose)]),
+    "rgbid_pose_log": (None, [C.POINTER(rgbid_pose), C.POINTER(C.c_double)]),
+    "rgbid_warmstart_param_count": (C.c_size_t, []),
+    "rgbid_warmstart_create": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(_P)]),
+    "rgbid_warmstart_free": (None, [_P]),
+    "rgbid_warmstart_get_params": (C.c_int, [_P, _P, C.POINTER(C.c_float)]),
+    "rgbid_warmstart_input": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P), _P]),
+    "rgbid_warmstart_forward": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double)]),
+    "rgbid_warmstart_predict": (C.c_int, [_P, _P, C.c_int, C.POINTER(_P), C.POINTER(_P), _P,
+                                          C.POINTER(rgbid_pose)]),
+    "rgbid_warmstart_gradient": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_float)]),
+    "rgbid_warmstart_train_step": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double), C.c_double,
+                                             C.c_double, C.POINTER(C.c_double)]),
+    "rgbid_autotune": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                 C.POINTER(rgbid_align_params), C.c_int, C.POINTER(C.c_double)]),
+    "rgbid_tune_save": (C.c_int, [_P, C.c_char_p]),
+    "rgbid_tune_load": (C.c_int, [_P, C.c_char_p]),
     "rgbid_set_profiling": (C.c_int, [_P, C.c_int]),
     "rgbid_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
 }
@@ -352,3 +370,120 @@ def rgbid_kernel_times(ctx):
 
 def rgbid_keyframe_free(kf):
     lib().rgbid_keyframe_free(kf)
+
+
+# ----------------------------------------------------------------- pose maps
+
+
+def rgbid_pose_exp(xi):
+    x = (C.c_double * 6)(*[float(v) for v in np.ravel(xi)])
+    p = rgbid_pose()
+    lib().rgbid_pose_exp(x, C.byref(p))
+    return pose_tuple(p)
+
+
+def rgbid_pose_log(R, t):
+    p = make_pose(R, t)
+    x = (C.c_double * 6)()
+    lib().rgbid_pose_log(C.byref(p), x)
+    return np.array(x[:])
+
+
+# ----------------------------------------------------------------- warm start
+
+
+def rgbid_warmstart_param_count() -> int:
+    return int(lib().rgbid_warmstart_param_count())
+
+
+def rgbid_warmstart_create(ctx, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != rgbid_warmstart_param_count():
+        raise ValueError("expected %d parameters" % rgbid_warmstart_param_count())
+    out = C.c_void_p()
+    _check(ctx, lib().rgbid_warmstart_create(ctx, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                             C.byref(out)))
+    return out
+
+
+def rgbid_warmstart_free(net):
+    lib().rgbid_warmstart_free(net)
+
+
+def rgbid_warmstart_get_params(ctx, net):
+    a = np.zeros(rgbid_warmstart_param_count(), dtype=np.float32)
+    _check(ctx, lib().rgbid_warmstart_get_params(ctx, net, a.ctypes.data_as(C.POINTER(C.c_float))))
+    return a
+
+
+def _dev(t, n):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+            or not t.is_contiguous() or t.numel() < n * 4 * 60 * 80:
+        raise TypeError("expected a contiguous float32 device tensor of n x 4 x 60 x 80")
+    return C.c_void_p(t.data_ptr())
+
+
+def rgbid_warmstart_input(ctx, As, Bs, x):
+    n = len(As)
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    _check(ctx, lib().rgbid_warmstart_input(ctx, n, a, b, _dev(x, n)))
+
+
+def rgbid_warmstart_forward(ctx, net, x, n):
+    xi = np.zeros(n * 6)
+    _check(ctx, lib().rgbid_warmstart_forward(ctx, net, int(n), _dev(x, n),
+                                              xi.ctypes.data_as(C.POINTER(C.c_double))))
+    return xi.reshape(n, 6)
+
+
+def rgbid_warmstart_predict(ctx, net, As, Bs, x_scratch):
+    n = len(As)
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    out = (rgbid_pose * n)()
+    _check(ctx, lib().rgbid_warmstart_predict(ctx, net, n, a, b, _dev(x_scratch, n), out))
+    return [pose_tuple(out[i]) for i in range(n)]
+
+
+def rgbid_warmstart_gradient(ctx, net, x, xi):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = xi.shape[0]
+    loss = C.c_double()
+    g = np.zeros(rgbid_warmstart_param_count(), dtype=np.float32)
+    _check(ctx, lib().rgbid_warmstart_gradient(ctx, net, n, _dev(x, n),
+                                               xi.ctypes.data_as(C.POINTER(C.c_double)),
+                                               C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float))))
+    return loss.value, g
+
+
+def rgbid_warmstart_train_step(ctx, net, x, xi, lr, wd=1e-4, want_loss=False):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = xi.shape[0]
+    loss = C.c_double()
+    _check(ctx, lib().rgbid_warmstart_train_step(ctx, net, n, _dev(x, n),
+                                                 xi.ctypes.data_as(C.POINTER(C.c_double)),
+                                                 float(lr), float(wd),
+                                                 C.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+# ----------------------------------------------------------------- autotuner
+
+
+def rgbid_autotune(ctx, As, Bs, params, reps=3):
+    n = len(As)
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    best = (C.c_double * 8)()
+    _check(ctx, lib().rgbid_autotune(ctx, n, a, b, C.byref(params), int(reps), best))
+    return list(best[:params.levels])
+
+
+def rgbid_tune_save(ctx, path):
+    _check(ctx, lib().rgbid_tune_save(ctx, path.encode()))
+
+
+def rgbid_tune_load(ctx, path):
+    _check(ctx, lib().rgbid_tune_load(ctx, path.encode()))

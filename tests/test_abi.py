@@ -28,3 +28,17 @@ def test_default_params():
     assert p.levels == 4 and list(p.iters)[:4] == [10] * 4
     assert p.weight == rgbid.RGBID_W_HUBER and abs(p.huber_k - 1.345) < 1e-15
     assert p.sample_max == 19200 and p.scale_iters == 20 and p.warp == rgbid.RGBID_WARP_FULLRES
+
+
+def test_pose_maps_host_functions():
+    # the decoupled exp / log of the library's host code against scipy
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+    from paper_1807_08271_amd import rgbid
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        xi = np.concatenate([rng.normal(size=3), rng.normal(size=3) * 0.5])
+        R, t = rgbid.rgbid_pose_exp(xi)
+        np.testing.assert_allclose(R, Rotation.from_rotvec(xi[3:]).as_matrix(), atol=1e-14)
+        np.testing.assert_array_equal(t, xi[:3])
+        np.testing.assert_allclose(rgbid.rgbid_pose_log(R, t), xi, atol=1e-12)
