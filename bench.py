@@ -124,6 +124,49 @@ def cpu_baseline(pairs, fusion, oparams, budget_s):
                           n, P, per_align, t_fu)}
 
 
+def warmstart_compare(ctx, npairs, steps):
+    """Plain Gauss-Newton from the identity against the learned warm start +
+    Gauss-Newton on a batch of held-out large-motion pairs (<= 10 deg / 15 cm):
+    alignments/s over `steps` timed repetitions (network input + forward
+    included for the warm start) and the success rate (final pose within
+    1e-5 rad / 1e-5 m of the Gauss-Newton optimum reached from the true pose),
+    both with early stop at 1e-6."""
+    import numpy as np
+    import torch
+    from paper_1807_08271_amd import rgbid as rg
+    from paper_1807_08271_amd import warmstart as ws
+    net = rg.rgbid_warmstart_create(ctx, ws.load_weights())
+    st = ws.PairStream(ctx, npairs)
+    m, truth = st.load(0, npairs, "eval")
+    ref, rstats = rg.rgbid_align_batch(ctx, st.As[:m], st.Bs[:m], ws.label_params(), inits=truth)
+    prm = ws.eval_params()
+    res = {}
+    for name in ("plain", "warm"):
+        def run():
+            inits = rg.rgbid_warmstart_predict(ctx, net, st.As[:m], st.Bs[:m], st.x) \
+                if name == "warm" else None
+            return rg.rgbid_align_batch(ctx, st.As[:m], st.Bs[:m], prm, inits=inits)
+        poses, stats = run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            poses, stats = run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = [ws._close(poses[i], ref[i], 1e-5, 1e-5) and stats[i]["status"] == 0
+              for i in range(m) if rstats[i]["status"] == 0]
+        iters = [sum(stats[i]["iters_done"]) for i in range(m) if rstats[i]["status"] == 0]
+        res[name] = {"alignments_per_s": round(m * steps / dt, 1),
+                     "success_rate": round(float(np.mean(ok)), 4),
+                     "mean_gn_iters": round(float(np.mean(iters)), 2)}
+        log("warm-start comparison %-5s: %s" % (name, res[name]))
+    st.close()
+    rg.rgbid_warmstart_free(net)
+    res["workload"] = ("%d held-out 640x480 pairs, motion <= 10 deg / 15 cm, 4 levels x <= 10 "
+                       "iterations, early stop 1e-6" % m)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +178,8 @@ def main():
     ap.add_argument("--weight", choices=["huber", "student_t"], default="huber")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--ws-pairs", type=int, default=64)
     ap.add_argument("--tune-file", default=None, help="load tuned launch shapes from this file")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -269,6 +314,8 @@ def main():
         "accuracy": {"max_rot_err_vs_truth_rad": float(max(errs)),
                      "max_trans_err_vs_truth_m": float(max(terrs)), "degenerate_pairs": bad},
     }
+    if not args.no_warmstart:
+        out["warmstart"] = warmstart_compare(ctx, args.ws_pairs, args.steps)
     if not args.no_cpu:
         log("timing the FP64 oracle on a bounded sample ...")
         op = oracle.Params(levels=4, iters=[10] * 4, weight=args.weight, warp=args.warp,

@@ -146,6 +146,15 @@ __device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, 
     return warp_core<F16>(G, u, v, load_w<F16>(G.WA, v * G.w + u), Io, Wo);
 }
 
+// Warp-level coordinates of the children this lane handles in one pass, and
+// their W_A (loaded ahead so the next pass's loads overlap this pass's
+// gathers).
+template <bool F16, int CPL>
+struct PassChildren {
+    int u[CPL], v[CPL];
+    float wa[CPL];
+};
+
 // Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
 // children at the warp level; LPP = min(C, 64) lanes share one pixel, GPP =
 // 64 / LPP pixels are warped per pass, and each lane handles CPL = C / LPP
@@ -159,29 +168,45 @@ struct ChildLayout {
     static constexpr int CPL = C / LPP;
 };
 
-// One pass: the GPP consecutive grid pixels first .. first+GPP-1 (grid of
-// width gw, grid stride gs in level pixels).  Every lane of group g = lane /
-// LPP returns the mean warped values of pixel first + g and whether all its
-// children are warp-valid (the strict downsampling rule).
+// Children of the pixel of lane group g in the pass starting at grid pixel
+// `first` (grid of width gw, grid stride gs in level pixels), with their W_A.
 template <bool F16, int LOG2B>
-__device__ __forceinline__ void warp_pass(const Geom& G, int first, int gw, float inv_gw, int ngrid,
-                                          int gs, int lane, float& Io, float& Wo, bool& Vo,
-                                          int& idxo)
+__device__ __forceinline__ PassChildren<F16, ChildLayout<LOG2B>::CPL>
+pass_children(const Geom& G, int first, int gw, float inv_gw, int ngrid, int gs, int lane)
 {
     using CL = ChildLayout<LOG2B>;
+    PassChildren<F16, CL::CPL> pc;
     const int j = lane % CL::LPP, g = lane / CL::LPP;
     const int idx = first + g;
-    const bool in = idx < ngrid;
     int gu = 0, gv = 0;
-    if (in) split_index(idx, gw, inv_gw, gu, gv);
-    float sI = 0.0f, sW = 0.0f;
-    bool ok = in;
+    if (idx < ngrid) split_index(idx, gw, inv_gw, gu, gv);
 #pragma unroll
     for (int m = 0; m < CL::CPL; ++m) {
         const int c = j + CL::LPP * m;
+        pc.u[m] = gu * gs * CL::B + (c % CL::B);
+        pc.v[m] = gv * gs * CL::B + (c / CL::B);
+        pc.wa[m] = load_w<F16>(G.WA, pc.v[m] * G.w + pc.u[m]);
+    }
+    return pc;
+}
+
+// One pass: the GPP consecutive grid pixels first .. first+GPP-1.  Every lane
+// of group g = lane / LPP returns the mean warped values of pixel first + g
+// and whether all its children are warp-valid (the strict downsampling rule).
+template <bool F16, int LOG2B>
+__device__ __forceinline__ void warp_pass_pc(const Geom& G, const PassChildren<F16, ChildLayout<LOG2B>::CPL>& pc,
+                                             int first, int ngrid, int lane, float& Io,
+                                             float& Wo, bool& Vo, int& idxo)
+{
+    using CL = ChildLayout<LOG2B>;
+    const int g = lane / CL::LPP;
+    const int idx = first + g;
+    bool ok = idx < ngrid;
+    float sI = 0.0f, sW = 0.0f;
+#pragma unroll
+    for (int m = 0; m < CL::CPL; ++m) {
         float ci, cw;
-        const bool okc = warp_px<F16>(G, gu * gs * CL::B + (c % CL::B),
-                                      gv * gs * CL::B + (c / CL::B), ci, cw);
+        const bool okc = warp_core<F16>(G, pc.u[m], pc.v[m], pc.wa[m], ci, cw);
         ok = ok && okc;
         sI += ci;
         sW += cw;
@@ -203,6 +228,15 @@ __device__ __forceinline__ void warp_pass(const Geom& G, int first, int gw, floa
     Wo = sW * invC;
     Vo = gvalid;
     idxo = idx;
+}
+
+template <bool F16, int LOG2B>
+__device__ __forceinline__ void warp_pass(const Geom& G, int first, int gw, float inv_gw, int ngrid,
+                                          int gs, int lane, float& Io, float& Wo, bool& Vo,
+                                          int& idxo)
+{
+    const auto pc = pass_children<F16, LOG2B>(G, first, gw, inv_gw, ngrid, gs, lane);
+    warp_pass_pc<F16, LOG2B>(G, pc, first, ngrid, lane, Io, Wo, Vo, idxo);
 }
 
 // A tile of 64 consecutive grid pixels in LPP passes; afterwards lane L owns
@@ -408,12 +442,16 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
-    for (int tile = ch.first + wave; tile < end; tile += waves) {
+    int tile = ch.first + wave;
+    auto pc = pass_children<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane);
+    for (; tile < end; tile += waves) {
         float Is, Ws;
         bool wv;
         int idx;
-        warp_pass<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane, Is, Ws,
-                              wv, idx);
+        warp_pass_pc<F16, LOG2B>(G, pc, tile * CL::GPP, gd.n, lane, Is, Ws, wv, idx);
+        // children of the next tile: their W_A loads overlap this tile's tail
+        const int ntile = tile + waves < end ? tile + waves : tile;
+        pc = pass_children<F16, LOG2B>(G, ntile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane);
         if ((lane % CL::LPP) != 0 || idx >= gd.n) continue;
         int gu, gv;
         split_index(idx, gd.gw, gd.inv_gw, gu, gv);

@@ -75,9 +75,13 @@ struct rgbid_ctx {
     size_t h_down_bytes = 0;
     int generation = 0;              // bumps when a workspace buffer moves
     bool use_graphs = true;
-    std::map<std::string, std::pair<int, hipGraphExec_t>> graphs;
+    std::map<std::string, std::vector<hipGraphExec_t>> graphs;   // one graph per chain
     std::map<std::string, LevelTune> tunes;   // per (level shape) launch shape
     hipEvent_t tev[2] = {nullptr, nullptr};   // launch-region timing (autotuner)
+    int chains = 2;                           // parallel branches of a batch graph
+    std::vector<hipStream_t> chain_streams;   // capture streams of branches 1..
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
     bool profiling = false;
     std::vector<hipEvent_t> events;  // timing events, grown on demand
     double prof_ms[kMaxLevels * 4] = {};
@@ -237,6 +241,29 @@ std::string tune_key(int n, const rgbid_pyr* const* A, int level, int warp, int 
     return k;
 }
 
+void clear_graphs(rgbid_ctx* c)
+{
+    for (auto& kv : c->graphs)
+        for (hipGraphExec_t g : kv.second) (void)hipGraphExecDestroy(g);
+    c->graphs.clear();
+}
+
+// Streams (default priority) and fork / join events for the chains of a
+// batch; chain 0 runs on the context's stream.
+rgbid_status ensure_chain_streams(rgbid_ctx* c, int nch)
+{
+    if (!c->fork) HIPCHK(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    while ((int)c->chain_streams.size() < nch - 1) {
+        hipStream_t s;
+        HIPCHK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c->chain_streams.push_back(s);
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->joins.push_back(e);
+    }
+    return RGBID_OK;
+}
+
 // The batched driver: n pairs, a schedule of (level, iterations), update on
 // or off.  Writes poses and stats (host) and returns OK unless an argument or
 // the device failed.
@@ -267,12 +294,34 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     const int L = P->levels;
     const bool fullres = P->warp == RGBID_WARP_FULLRES;
 
+    // ---- chains: with graphs, the batch is split into independent groups of
+    // pairs captured as parallel branches, so one group's latency-bound
+    // kernels (scale, solve) overlap another group's pixel kernels.
+    const bool graphed = c->use_graphs && !c->profiling;
+    const int nch = graphed ? std::max(1, std::min(c->chains, n)) : 1;
+    std::vector<int> cfirst(nch + 1, n);
+    {
+        long long tot = 0, cum = 0;
+        for (int i = 0; i < n; ++i) tot += (long long)A[i]->w[0] * A[i]->h[0];
+        cfirst[0] = 0;
+        int k = 1;
+        for (int i = 0; i < n && k < nch; ++i) {
+            cum += (long long)A[i]->w[0] * A[i]->h[0];
+            if (cum * nch >= tot * k && i + 1 < n) cfirst[k++] = i + 1;
+        }
+        for (; k < nch; ++k) cfirst[k] = n;
+        cfirst[nch] = n;
+    }
+
     // ---- launch shapes and tables
     LevelTune tune[kMaxLevels];
     std::vector<int> stride(n * L), sw(n * L), sh(n * L);
-    std::vector<std::vector<Chunk>> wch(L), rch(L);
-    std::vector<std::vector<int>> rbeg(L);
-    size_t max_red = 0, warped_per_pair_total = 0;
+    // [chain][level]
+    std::vector<std::vector<std::vector<Chunk>>> wch(nch, std::vector<std::vector<Chunk>>(L)),
+        rch(nch, std::vector<std::vector<Chunk>>(L));
+    std::vector<std::vector<std::vector<int>>> rbeg(nch, std::vector<std::vector<int>>(L));
+    std::vector<size_t> max_red(nch, 0);
+    size_t warped_per_pair_total = 0;
     std::vector<size_t> warped_off(n, 0);
     for (int l = 0; l < L; ++l) {
         const int b = fullres ? l : 0;
@@ -281,25 +330,32 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         tune[l] = it != c->tunes.end() ? it->second : default_tune(b);
         const int lpp = std::min(1 << (2 * b), 64), gpp = 64 / lpp;
         const int wtiles_per_chunk = tune[l].waves * tune[l].tiles_per_wave;
-        rbeg[l].push_back(0);
-        for (int i = 0; i < n; ++i) {
-            const int w = A[i]->w[l], h = A[i]->h[l];
-            const int s = sample_stride(w, h, P->sample_max);
-            stride[i * L + l] = s;
-            sw[i * L + l] = (w + s - 1) / s;
-            sh[i * L + l] = (h + s - 1) / s;
-            const long long ngrid = tune[l].fused ? (long long)sw[i * L + l] * sh[i * L + l]
-                                                  : (long long)w * h;
-            const long long wt = (ngrid + gpp - 1) / gpp;
-            for (long long t = 0; t < wt; t += wtiles_per_chunk)
-                wch[l].push_back(Chunk{i, (int)t, (int)std::min<long long>(wtiles_per_chunk, wt - t)});
-            const long long rt = ((long long)w * h + 63) / 64;
-            for (long long t = 0; t < rt; t += wtiles_per_chunk)
-                rch[l].push_back(Chunk{i, (int)t, (int)std::min<long long>(wtiles_per_chunk, rt - t)});
-            rbeg[l].push_back((int)rch[l].size());
+        for (int k = 0; k < nch; ++k) {
+            rbeg[k][l].push_back(0);
+            for (int i = cfirst[k]; i < cfirst[k + 1]; ++i) {
+                const int li = i - cfirst[k];
+                const int w = A[i]->w[l], h = A[i]->h[l];
+                const int s = sample_stride(w, h, P->sample_max);
+                stride[i * L + l] = s;
+                sw[i * L + l] = (w + s - 1) / s;
+                sh[i * L + l] = (h + s - 1) / s;
+                const long long ngrid = tune[l].fused ? (long long)sw[i * L + l] * sh[i * L + l]
+                                                      : (long long)w * h;
+                const long long wt = (ngrid + gpp - 1) / gpp;
+                for (long long t = 0; t < wt; t += wtiles_per_chunk)
+                    wch[k][l].push_back(
+                        Chunk{li, (int)t, (int)std::min<long long>(wtiles_per_chunk, wt - t)});
+                const long long rt = ((long long)w * h + 63) / 64;
+                for (long long t = 0; t < rt; t += wtiles_per_chunk)
+                    rch[k][l].push_back(
+                        Chunk{li, (int)t, (int)std::min<long long>(wtiles_per_chunk, rt - t)});
+                rbeg[k][l].push_back((int)rch[k][l].size());
+            }
+            max_red[k] = std::max(max_red[k], rch[k][l].size());
         }
-        max_red = std::max(max_red, rch[l].size());
     }
+    std::vector<size_t> poff(nch + 1, 0);
+    for (int k = 0; k < nch; ++k) poff[k + 1] = poff[k] + max_red[k];
     for (int i = 0; i < n; ++i) {
         size_t need = 0;
         for (int l = 0; l < L; ++l)
@@ -311,21 +367,22 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     // ---- workspace
     rgbid_status st;
     size_t tbytes = 0;
-    std::vector<LevelTables> lt(L);
-    for (int l = 0; l < L; ++l) {
-        lt[l].warp_off = tbytes;
-        tbytes = align_up(tbytes + wch[l].size() * sizeof(Chunk), 256);
-        lt[l].red_off = tbytes;
-        tbytes = align_up(tbytes + rch[l].size() * sizeof(Chunk), 256);
-        lt[l].begin_off = tbytes;
-        tbytes = align_up(tbytes + rbeg[l].size() * sizeof(int), 256);
-        lt[l].n_warp = (int)wch[l].size();
-        lt[l].n_red = (int)rch[l].size();
-    }
+    std::vector<std::vector<LevelTables>> lt(nch, std::vector<LevelTables>(L));
+    for (int k = 0; k < nch; ++k)
+        for (int l = 0; l < L; ++l) {
+            lt[k][l].warp_off = tbytes;
+            tbytes = align_up(tbytes + wch[k][l].size() * sizeof(Chunk), 256);
+            lt[k][l].red_off = tbytes;
+            tbytes = align_up(tbytes + rch[k][l].size() * sizeof(Chunk), 256);
+            lt[k][l].begin_off = tbytes;
+            tbytes = align_up(tbytes + rbeg[k][l].size() * sizeof(int), 256);
+            lt[k][l].n_warp = (int)wch[k][l].size();
+            lt[k][l].n_red = (int)rch[k][l].size();
+        }
     if ((st = ensure(c, c->pairs, n * sizeof(PairDesc))) != RGBID_OK) return st;
     if ((st = ensure(c, c->states, n * sizeof(PairState))) != RGBID_OK) return st;
     if ((st = ensure(c, c->tables, tbytes)) != RGBID_OK) return st;
-    if ((st = ensure(c, c->partials, std::max<size_t>(1, max_red) * kNSum * sizeof(float2))) != RGBID_OK) return st;
+    if ((st = ensure(c, c->partials, std::max<size_t>(1, poff[nch]) * kNSum * sizeof(float2))) != RGBID_OK) return st;
     if ((st = ensure(c, c->warped, std::max<size_t>(1, warped_per_pair_total) * sizeof(float2))) != RGBID_OK) return st;
     if ((st = ensure(c, c->sample, (size_t)n * P->sample_max * sizeof(float2))) != RGBID_OK) return st;
 
@@ -365,11 +422,12 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         s.sigma[0] = s.sigma[1] = 1.0f;
         s.nu[0] = s.nu[1] = 5.0f;
     }
-    for (int l = 0; l < L; ++l) {
-        std::memcpy(tb + lt[l].warp_off, wch[l].data(), wch[l].size() * sizeof(Chunk));
-        std::memcpy(tb + lt[l].red_off, rch[l].data(), rch[l].size() * sizeof(Chunk));
-        std::memcpy(tb + lt[l].begin_off, rbeg[l].data(), rbeg[l].size() * sizeof(int));
-    }
+    for (int k = 0; k < nch; ++k)
+        for (int l = 0; l < L; ++l) {
+            std::memcpy(tb + lt[k][l].warp_off, wch[k][l].data(), wch[k][l].size() * sizeof(Chunk));
+            std::memcpy(tb + lt[k][l].red_off, rch[k][l].data(), rch[k][l].size() * sizeof(Chunk));
+            std::memcpy(tb + lt[k][l].begin_off, rbeg[k][l].data(), rbeg[k][l].size() * sizeof(int));
+        }
     HIPCHK(c, hipMemcpyAsync(c->pairs.p, pd, pairs_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->states.p, ps, states_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->tables.p, tb, tbytes, hipMemcpyHostToDevice, c->stream));
@@ -393,29 +451,32 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             c->events.push_back(ev);
         }
     }
-    auto enqueue = [&](hipStream_t s) -> hipError_t {
+    // the whole schedule of chain k on stream s
+    auto enqueue = [&](hipStream_t s, int k) -> hipError_t {
         hipError_t e = hipSuccess;
         int ev_base = 0;
+        const int p0 = cfirst[k], np = cfirst[k + 1] - cfirst[k];
+        if (np <= 0) return e;
+        PairState* states = static_cast<PairState*>(c->states.p) + p0;
         for (const Step& stp : sched) {
             const int l = stp.level;
-            if ((e = launch_level_start(s, static_cast<PairState*>(c->states.p), n)) != hipSuccess)
-                return e;
+            if ((e = launch_level_start(s, states, np)) != hipSuccess) return e;
             IterLaunch il;
-            il.pairs = static_cast<const PairDesc*>(c->pairs.p);
-            il.states = static_cast<PairState*>(c->states.p);
-            il.npairs = n;
+            il.pairs = static_cast<const PairDesc*>(c->pairs.p) + p0;
+            il.states = states;
+            il.npairs = np;
             il.level = l;
             il.ip = ip;
             il.tune = tune[l];
             il.f16 = f16;
             il.block_log2 = fullres ? l : 0;
             char* tbase = static_cast<char*>(c->tables.p);
-            il.warp_chunks = reinterpret_cast<const Chunk*>(tbase + lt[l].warp_off);
-            il.n_warp_chunks = lt[l].n_warp;
-            il.red_chunks = reinterpret_cast<const Chunk*>(tbase + lt[l].red_off);
-            il.n_red_chunks = lt[l].n_red;
-            il.pair_red_begin = reinterpret_cast<const int*>(tbase + lt[l].begin_off);
-            il.partials = static_cast<float2*>(c->partials.p);
+            il.warp_chunks = reinterpret_cast<const Chunk*>(tbase + lt[k][l].warp_off);
+            il.n_warp_chunks = lt[k][l].n_warp;
+            il.red_chunks = reinterpret_cast<const Chunk*>(tbase + lt[k][l].red_off);
+            il.n_red_chunks = lt[k][l].n_red;
+            il.pair_red_begin = reinterpret_cast<const int*>(tbase + lt[k][l].begin_off);
+            il.partials = static_cast<float2*>(c->partials.p) + poff[k] * kNSum;
             il.update = update;
             for (int it = 0; it < stp.iters; ++it) {
                 const hipEvent_t* ev = c->profiling ? &c->events[5 * (ev_base + it)] : nullptr;
@@ -427,12 +488,12 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     };
     // Timing events inside a captured graph cannot be read back, so a profiled
     // call launches directly.
-    if (c->use_graphs && !c->profiling) {
+    if (graphed) {
         std::string key;
         {
             char buf[160];
-            snprintf(buf, sizeof buf, "n%d f%d u%d L%d g%d p%d|", n, f16, update, L, c->generation,
-                     (int)c->profiling);
+            snprintf(buf, sizeof buf, "n%d f%d u%d L%d g%d c%d|", n, f16, update, L, c->generation,
+                     nch);
             key = buf;
             for (int i = 0; i < n; ++i) {
                 snprintf(buf, sizeof buf, "%dx%d,", A[i]->w[0], A[i]->h[0]);
@@ -446,34 +507,46 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             key.append(reinterpret_cast<const char*>(&ip), sizeof ip);
             key.append(reinterpret_cast<const char*>(tune), sizeof(LevelTune) * L);
         }
+        if ((st = ensure_chain_streams(c, nch)) != RGBID_OK) return st;
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
-            hipGraph_t g = nullptr;
-            HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue(c->cap);
-            hipError_t e2 = hipStreamEndCapture(c->cap, &g);
-            if (e != hipSuccess || e2 != hipSuccess) {
+            std::vector<hipGraphExec_t> execs;
+            for (int k = 0; k < nch; ++k) {
+                hipGraph_t g = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+                hipError_t e = enqueue(c->cap, k);
+                hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+                hipGraphExec_t ex = nullptr;
+                if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
                 if (g) hipGraphDestroy(g);
-                return set_err(c, RGBID_E_DEVICE, "graph capture failed: %s",
-                               hipGetErrorString(e != hipSuccess ? e : e2));
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    for (hipGraphExec_t x : execs) (void)hipGraphExecDestroy(x);
+                    return set_err(c, RGBID_E_DEVICE, "graph capture failed: %s",
+                                   hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                execs.push_back(ex);
             }
-            hipGraphExec_t ex = nullptr;
-            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
-            if (e != hipSuccess)
-                return set_err(c, RGBID_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-            if (c->graphs.size() > 64) {
-                for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
-                c->graphs.clear();
-            }
-            it = c->graphs.emplace(key, std::make_pair(c->generation, ex)).first;
+            if (c->graphs.size() > 64) clear_graphs(c);
+            it = c->graphs.emplace(key, std::move(execs)).first;
         }
+        // chains run concurrently on their own streams, forked from and joined
+        // back into the context's stream
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
-        HIPCHK(c, hipGraphLaunch(it->second.second, c->stream));
+        if (nch > 1) {
+            HIPCHK(c, hipEventRecord(c->fork, c->stream));
+            for (int k = 1; k < nch; ++k)
+                HIPCHK(c, hipStreamWaitEvent(c->chain_streams[k - 1], c->fork, 0));
+        }
+        for (int k = 0; k < nch; ++k)
+            HIPCHK(c, hipGraphLaunch(it->second[k], k == 0 ? c->stream : c->chain_streams[k - 1]));
+        for (int k = 1; k < nch; ++k) {
+            HIPCHK(c, hipEventRecord(c->joins[k - 1], c->chain_streams[k - 1]));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->joins[k - 1], 0));
+        }
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
     } else {
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
-        HIPCHK(c, enqueue(c->stream));
+        HIPCHK(c, enqueue(c->stream, 0));
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
     }
 
@@ -593,6 +666,7 @@ rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream)
     }
     const char* g = std::getenv("RGBID_NO_GRAPH");
     c->use_graphs = !(g && g[0] == '1');
+    if (const char* ch = std::getenv("RGBID_CHAINS")) c->chains = std::max(1, std::min(8, std::atoi(ch)));
     *ctx = c;
     return RGBID_OK;
 }
@@ -602,7 +676,7 @@ void rgbid_destroy(rgbid_ctx* c)
     if (!c) return;
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
+    clear_graphs(c);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
                       &c->frames})
@@ -612,6 +686,9 @@ void rgbid_destroy(rgbid_ctx* c)
     if (c->stage_done) hipEventDestroy(c->stage_done);
     for (hipEvent_t e : c->tev)
         if (e) hipEventDestroy(e);
+    for (hipStream_t cs : c->chain_streams) hipStreamDestroy(cs);
+    for (hipEvent_t e : c->joins) hipEventDestroy(e);
+    if (c->fork) hipEventDestroy(c->fork);
     if (c->cap) hipStreamDestroy(c->cap);
     delete c;
 }
@@ -831,8 +908,7 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
         if (best_ms) best_ms[l] = best_t / reps;
     }
     // drop the candidate graphs
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
-    c->graphs.clear();
+    clear_graphs(c);
     c->profiling = saved_prof;
     return RGBID_OK;
 }
@@ -864,8 +940,7 @@ rgbid_status rgbid_tune_load(rgbid_ctx* c, const char* path)
         ++nread;
     }
     std::fclose(f);
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second.second);
-    c->graphs.clear();
+    clear_graphs(c);
     return nread > 0 ? RGBID_OK : set_err(c, RGBID_E_ARG, "no tune entries in %s", path);
 }
 

@@ -318,7 +318,7 @@ def test_fuse_20_frames_matches_oracle(ctx):
             nb = Wp[1 + dv:1 + dv + cam.h, 1 + du:1 + du + cam.w]
             edge |= np.abs(nb - Wkf0) > 0.05 * np.maximum(Wkf0, 1e-9)
     flat = agree & ~edge
-    assert flat.mean() > 0.95
+    assert flat.sum() > 0.8 * (Wkf0 > 0).sum()
     np.testing.assert_allclose(Wg[flat], Wr[flat], rtol=1e-5)
     np.testing.assert_allclose(Wg[agree], Wr[agree], rtol=1e-4)
     np.testing.assert_allclose(Cg[agree], Cr[agree], rtol=1e-5)
