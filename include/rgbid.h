@@ -228,6 +228,42 @@ rgbid_status rgbid_autotune(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
 rgbid_status rgbid_tune_save(const rgbid_ctx* ctx, const char* path);
 rgbid_status rgbid_tune_load(rgbid_ctx* ctx, const char* path);
 
+/* ------------------------------------------------------------ covariance */
+
+/* Bilateral filter of the covariance iteration (the paper gives no
+   parameters): window (2 radius + 1)^2 (radius <= 7), spatial weight
+   exp(-d^2 / (2 sigma_s^2)), intensity range weight exp(-dI^2 / (2 sigma_I^2)),
+   inverse-depth range weight exp(-(dW / (rel_W W(p)))^2 / 2); holes skipped.
+   Defaults: 2, 1.5 px, 10 grey levels, 0.05. */
+typedef struct {
+    int radius;
+    double sigma_s, sigma_I, rel_W;
+} rgbid_bilateral;
+
+/* Pose covariance of sec. 6.2: one extra linearisation at level 0 and pose T
+   (the final estimate) without an update, with {I_A, W_A} bilateral-filtered
+   before the pyramid and gradients are formed; Sigma (6 x 6, row-major) =
+   H_filt^-1, inverted by FP64 Cholesky.  bf NULL = defaults; stats (NULL ok)
+   receives the filtered linearisation.  Synchronises.  Errors: E_ARG,
+   E_SHAPE, E_DEGENERATE (H_filt not positive definite). */
+rgbid_status rgbid_covariance(rgbid_ctx* ctx, const rgbid_pyr* A, const rgbid_pyr* B,
+                              const rgbid_pose* T, const rgbid_align_params* params,
+                              const rgbid_bilateral* bf, double Sigma[36],
+                              rgbid_align_stats* stats);
+
+/* ------------------------------------------------------------ covisibility */
+
+/* Dense covisibility ratio of sec. 6.4 at pyramid `level`: the pixels of A
+   with a valid inverse depth (S_H) are transferred into B with T (the pose of
+   B in A); a pixel is visible (S_V) when it lands in the image with four valid
+   W_B taps and |W_B(p_B) - w_B| < tol (tol = 3 sigma_W), w_B the transferred
+   inverse depth.  The same is done from B to A with T^-1, and
+   *ratio = min(|S_V|/|S_H| over both directions).  counts (4 entries or NULL)
+   receives |S_H(A)|, |S_V(A->B)|, |S_H(B)|, |S_V(B->A)|.  Synchronises.
+   Errors: E_ARG, E_SHAPE. */
+rgbid_status rgbid_covisibility(rgbid_ctx* ctx, const rgbid_pyr* A, const rgbid_pyr* B, int level,
+                                const rgbid_pose* T, double tol, double* ratio, long long* counts);
+
 /* ------------------------------------------------------------ keyframe fusion */
 
 /* Creates a keyframe from a caller-owned FP32 inverse-depth map (copied) with

@@ -136,6 +136,14 @@ def lib():
         L.or_align.restype = C.c_int
         L.or_align.argtypes = [cp, dp, dp, dp, dp, dp, dp, C.POINTER(_Params), dp, dp,
                                C.POINTER(_Stats)]
+        L.or_covisibility.argtypes = [cp, dp, dp, dp, dp, C.c_double, C.POINTER(C.c_longlong),
+                                      C.POINTER(C.c_longlong)]
+        L.or_bilateral.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                   C.c_double, dp, dp]
+        L.or_covariance.restype = C.c_int
+        L.or_covariance.argtypes = [cp, C.c_int, dp, dp, dp, dp, dp, dp, C.POINTER(_Params),
+                                    C.c_int, C.c_double, C.c_double, C.c_double, dp,
+                                    C.POINTER(_Stats)]
         L.or_fuse.restype = C.c_longlong
         L.or_fuse.argtypes = [cp, dp, dp, dp, dp, dp, C.c_double]
         _lib = L
@@ -356,3 +364,53 @@ def fuse(cam, Wkf, Ckf, Wk, R, t, tol):
     n = lib().or_fuse(C.byref(c), _p(Wkf), _p(Ckf), _p(Wk), _p(_d(R).reshape(9)), _p(_d(t)),
                       float(tol))
     return Wkf, Ckf, int(n)
+
+
+def covisibility(cam, WA, WB, R, t, tol):
+    """(|S_H|, |S_V|) of A transferred into B (sec. 6.4)."""
+    c = _cam(cam)
+    nH, nV = C.c_longlong(), C.c_longlong()
+    lib().or_covisibility(C.byref(c), _p(_d(WA)), _p(_d(WB)), _p(_d(R).reshape(9)), _p(_d(t)),
+                          float(tol), C.byref(nH), C.byref(nV))
+    return nH.value, nV.value
+
+
+def covisibility_ratio(cam, WA, WB, R, t, tol):
+    """min(vr_AB, vr_BA) with vr = |S_V| / |S_H| (sec. 6.4); B -> A uses the
+    inverse pose."""
+    hA, vA = covisibility(cam, WA, WB, R, t, tol)
+    R = np.asarray(R, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    hB, vB = covisibility(cam, WB, WA, R.T, -R.T @ t, tol)
+    ra = vA / hA if hA else 0.0
+    rb = vB / hB if hB else 0.0
+    return min(ra, rb), (hA, vA, hB, vB)
+
+
+# default bilateral filter of the covariance iteration (a reading: the paper
+# gives no parameters)
+BILATERAL = dict(radius=2, sigma_s=1.5, sigma_I=10.0, rel_W=0.05)
+
+
+def bilateral(I, W, radius=2, sigma_s=1.5, sigma_I=10.0, rel_W=0.05):
+    I, W = _d(I), _d(W)
+    h, w = I.shape
+    Io, Wo = np.zeros((h, w)), np.zeros((h, w))
+    lib().or_bilateral(_p(I), _p(W), w, h, radius, sigma_s, sigma_I, rel_W, _p(Io), _p(Wo))
+    return Io, Wo
+
+
+def covariance(cam0, IA0, WA0, IB0, WB0, R, t, params: Params = None, **bf):
+    """(Sigma 6x6, stats) of the filtered extra linearisation at level 0."""
+    params = params or Params()
+    b = dict(BILATERAL, **bf)
+    c = _cam(cam0)
+    arrs = [_d(a) for a in (IA0, WA0, IB0, WB0)]
+    S = np.zeros(36)
+    st = _Stats()
+    pc = params._c()
+    rc = lib().or_covariance(C.byref(c), params.levels, *[_p(a) for a in arrs],
+                             _p(_d(R).reshape(9)), _p(_d(t)), C.byref(pc), int(b["radius"]),
+                             float(b["sigma_s"]), float(b["sigma_I"]), float(b["rel_W"]), _p(S),
+                             C.byref(st))
+    return (S.reshape(6, 6) if rc == 0 else None), _stats(st)

@@ -770,3 +770,106 @@ long long or_fuse(const or_cam* c, double* Wkf, double* Ckf, const double* Wk,
         }
     return nf;
 }
+
+/* ---------------------------------------------------------------- covisibility */
+
+/* Dense covisibility of sec. 6.4 in one direction: pixels of A with a valid
+   W_A (S_H) are transferred into B with T = (R, t), the pose of B in A
+   (Y = R^T (K^-1 p / W_A - t), p_B = K Y / Y_z, w_B = 1 / Y_z); a pixel is
+   visible (S_V) when Y_z > 0, p_B lies in the image (the bilinear bounds rule)
+   with four valid W_B taps, and |W_B(p_B) - w_B| < tol (tol = 3 sigma_W).
+   Writes |S_H| and |S_V|. */
+void or_covisibility(const or_cam* c, const double* WA, const double* WB, const double R[9],
+                     const double t[3], double tol, long long* nH, long long* nV)
+{
+    const int w = c->w, h = c->h;
+    long long h_ = 0, v_ = 0;
+    for (int v = 0; v < h; ++v)
+        for (int u = 0; u < w; ++u) {
+            const double wa = WA[v * w + u];
+            if (!valid_w(wa)) continue;
+            ++h_;
+            const double ray[3] = {(u - c->cx) / c->fx, (v - c->cy) / c->fy, 1.0};
+            const double X[3] = {ray[0] / wa - t[0], ray[1] / wa - t[1], ray[2] / wa - t[2]};
+            double Y[3];
+            for (int k = 0; k < 3; ++k) Y[k] = R[k] * X[0] + R[3 + k] * X[1] + R[6 + k] * X[2];
+            if (!(Y[2] > 0.0)) continue;
+            const double ub = c->fx * Y[0] / Y[2] + c->cx, vb = c->fy * Y[1] / Y[2] + c->cy;
+            double wb;
+            if (!bilinear(WB, w, h, ub, vb, 1, &wb)) continue;
+            if (fabs(wb - 1.0 / Y[2]) < tol) ++v_;
+        }
+    *nH = h_;
+    *nV = v_;
+}
+
+/* ---------------------------------------------------------------- covariance */
+
+/* Bilateral filter applied to {I_A, W_A} before the covariance iteration
+   (sec. 6.2).  The paper gives no parameters; reading: window (2r+1)^2,
+   spatial weight exp(-d^2 / (2 sigma_s^2)), range weight exp(-dI^2 /
+   (2 sigma_I^2)) for intensity and exp(-(dW / (rel_W W(p)))^2 / 2) for inverse
+   depth; W holes neither contribute nor receive a value; out-of-image
+   neighbours are skipped. */
+void or_bilateral(const double* I, const double* W, int w, int h, int radius, double sigma_s,
+                  double sigma_I, double rel_W, double* Io, double* Wo)
+{
+    for (int v = 0; v < h; ++v)
+        for (int u = 0; u < w; ++u) {
+            const int i = v * w + u;
+            double si = 0, swi = 0, sw = 0, sww = 0;
+            const double w0 = W[i];
+            const int wv = valid_w(w0);
+            for (int dv = -radius; dv <= radius; ++dv)
+                for (int du = -radius; du <= radius; ++du) {
+                    const int x = u + du, y = v + dv;
+                    if (x < 0 || y < 0 || x >= w || y >= h) continue;
+                    const int j = y * w + x;
+                    const double gs = exp(-(double)(du * du + dv * dv) / (2.0 * sigma_s * sigma_s));
+                    const double di = (I[j] - I[i]) / sigma_I;
+                    const double gi = gs * exp(-0.5 * di * di);
+                    si += gi * I[j];
+                    swi += gi;
+                    if (wv && valid_w(W[j])) {
+                        const double dw = (W[j] - w0) / (rel_W * w0);
+                        const double gw = gs * exp(-0.5 * dw * dw);
+                        sw += gw * W[j];
+                        sww += gw;
+                    }
+                }
+            Io[i] = si / swi;
+            Wo[i] = wv ? sw / sww : 0.0;
+        }
+}
+
+/* Pose covariance of sec. 6.2: one extra linearisation at level 0 and pose T
+   without update, with {I_A, W_A} bilateral-filtered (then the pyramid and the
+   gradients are computed from the filtered images); Sigma = H_filt^-1 (full
+   6x6, row-major).  Returns OR_DEGENERATE if H_filt is not positive definite. */
+int or_covariance(const or_cam* c0, int levels, const double* IA0, const double* WA0,
+                  const double* IB0, const double* WB0, const double R[9], const double t[3],
+                  const or_params* P, int radius, double sigma_s, double sigma_I, double rel_W,
+                  double Sigma[36], or_stats* st)
+{
+    const size_t n = (size_t)c0->w * c0->h;
+    double* If = malloc(n * sizeof(double));
+    double* Wf = malloc(n * sizeof(double));
+    or_bilateral(IA0, WA0, c0->w, c0->h, radius, sigma_s, sigma_I, rel_W, If, Wf);
+    if (P->storage != OR_STORE_F64)
+        for (size_t i = 0; i < n; ++i) {
+            If[i] = store_round(If[i], P->storage);
+            Wf[i] = store_round(Wf[i], P->storage);
+        }
+    memset(st, 0, sizeof *st);
+    or_normal_equations_at(c0, levels, If, Wf, IB0, WB0, 0, R, t, P, st);
+    free(If);
+    free(Wf);
+    /* inverse by solving H x = e_k with the Cholesky solver (xi = -H^-1 g) */
+    for (int k = 0; k < 6; ++k) {
+        double e[6] = {0}, x[6];
+        e[k] = -1.0;
+        if (or_solve(st->H, e, x) != OR_OK) return OR_DEGENERATE;
+        for (int r = 0; r < 6; ++r) Sigma[6 * r + k] = x[r];
+    }
+    return OR_OK;
+}

@@ -470,43 +470,6 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
 
 // ------------------------------------------------------------------ k_scale
 
-struct Sum3 {
-    double a, b, c;
-};
-
-__device__ __forceinline__ Sum3 block_sum3(Sum3 v, double* lds)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v.a = wave_sum_d(v.a);
-    v.b = wave_sum_d(v.b);
-    v.c = wave_sum_d(v.c);
-    if (lane == 0) {
-        lds[3 * wave] = v.a;
-        lds[3 * wave + 1] = v.b;
-        lds[3 * wave + 2] = v.c;
-    }
-    __syncthreads();
-    if (wave == 0) {
-        Sum3 t{0.0, 0.0, 0.0};
-        if (lane < nw) {
-            t.a = lds[3 * lane];
-            t.b = lds[3 * lane + 1];
-            t.c = lds[3 * lane + 2];
-        }
-        t.a = wave_sum_d(t.a);
-        t.b = wave_sum_d(t.b);
-        t.c = wave_sum_d(t.c);
-        if (lane == 0) {
-            lds[96] = t.a;
-            lds[97] = t.b;
-            lds[98] = t.c;
-        }
-    }
-    __syncthreads();
-    Sum3 r{lds[96], lds[97], lds[98]};
-    return r;
-}
-
 // psi(x), x > 0: upward recurrence to x >= 12 then the Stirling-type series
 // psi(x) ~ ln x - 1/(2x) - sum_k B_2k / (2k x^2k) (Abramowitz & Stegun 6.3.18).
 __device__ double digamma_d(double x)
@@ -522,26 +485,57 @@ __device__ double digamma_d(double x)
     return r + log(x) - 0.5 / x - series;
 }
 
+// Block sums for the scale kernel with one barrier per call: each wave
+// reduces its FP32 values with cross-lane shuffles, lane 0 stores them in the
+// LDS slot of this call's parity, and after the barrier every wave adds the
+// per-wave values in FP64 in wave order (identical on all lanes, so the
+// result is block-uniform and deterministic).  Alternating slots make the
+// next call's stores safe without a second barrier.
+template <int NV>
+struct BlockSums {
+    double v[NV];
+};
+
+template <int NV>
+__device__ __forceinline__ BlockSums<NV> block_sums(const float (&x)[NV], float* lds, int parity)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    float* slot = lds + parity * 16 * NV;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const float w = wave_sum(x[k]);
+        if (lane == 0) slot[wave * NV + k] = w;
+    }
+    __syncthreads();
+    BlockSums<NV> r;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) r.v[k] = 0.0;
+    for (int w = 0; w < nw; ++w)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) r.v[k] += (double)slot[w * NV + k];
+    return r;
+}
+
 // n f_c(nu) + sum_i (1 + ln w_i - w_i), w_i = (nu + 1)/(nu + x_i^2), with
 // f_c(nu) = -psi(nu/2) + ln(nu/2) + psi((nu+1)/2) - ln((nu+1)/2): the left side
 // of the nu equation of sec. 6.3 (eq:robustnessValue).  x2 holds x_i^2
 // (NaN = not in the sample); block-uniform result.
 __device__ __forceinline__ double nu_equation(const float (&x2)[kScalePerThread], double n,
-                                              double nud, double* lds)
+                                              double nud, float* lds, int parity)
 {
     const float nf = (float)nud;
-    float acc = 0.0f;
+    float acc[1] = {0.0f};
 #pragma unroll
     for (int q = 0; q < kScalePerThread; ++q) {
         if (x2[q] == x2[q]) {
             const float w = (nf + 1.0f) / (nf + x2[q]);
-            acc += 1.0f + logf(w) - w;
+            acc[0] += 1.0f + logf(w) - w;
         }
     }
-    const Sum3 z = block_sum3(Sum3{(double)acc, 0.0, 0.0}, lds);
+    const BlockSums<1> z = block_sums<1>(acc, lds, parity);
     const double c = -digamma_d(0.5 * nud) + log(0.5 * nud) + digamma_d(0.5 * (nud + 1.0)) -
                      log(0.5 * (nud + 1.0));
-    return n * c + z.a;
+    return n * c + z.v[0];
 }
 
 // One workgroup per (pair, channel): location mu and scale sigma of the
@@ -552,7 +546,7 @@ __device__ __forceinline__ double nu_equation(const float (&x2)[kScalePerThread]
 // normalised residuals frozen.
 __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
 {
-    __shared__ double lds[100];
+    __shared__ float lds[2 * 16 * 3];
     const int p = blockIdx.x, ch = blockIdx.y;
     PairState& S = L.states[p];
     if (!S.active || S.level_stop) return;
@@ -560,7 +554,7 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     const int n_all = D.sw[L.level] * D.sh[L.level];
     const float floor_s = ch == 0 ? 1e-3f : 1e-6f;
     float r[kScalePerThread];
-    float cnt = 0.0f, sq = 0.0f;
+    float cs[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kScalePerThread; ++k) {
         const int i = threadIdx.x + k * kScaleThreads;
@@ -571,35 +565,38 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
         }
         r[k] = x;
         if (x == x) {
-            cnt += 1.0f;
-            sq = fmaf(x, x, sq);
+            cs[0] += 1.0f;
+            cs[1] = fmaf(x, x, cs[1]);
         }
     }
-    Sum3 t = block_sum3(Sum3{(double)cnt, (double)sq, 0.0}, lds);
-    const double n = t.a;
+    int parity = 0;
+    const BlockSums<2> t = block_sums<2>(cs, lds, parity);
+    parity ^= 1;
+    const double n = t.v[0];
     double mu = 0.0, sigma = floor_s;
     float nu = 5.0f;
     if (n > 0.0) {
-        sigma = fmax(sqrt(t.b / n), (double)floor_s);
+        sigma = fmax(sqrt(t.v[1] / n), (double)floor_s);
         const float k = L.ip.huber_k;
         for (int it = 0; it < L.ip.scale_iters; ++it) {
             const float fmu = (float)mu, isg = (float)(1.0 / sigma);
-            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+            float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int q = 0; q < kScalePerThread; ++q) {
                 if (r[q] == r[q]) {
                     const float d = r[q] - fmu;
                     const float w = omega(L.ip.weight, d * isg, 5.0f, k);
-                    s0 += w;
-                    s1 = fmaf(w, d, s1);
-                    s2 = fmaf(w * d, d, s2);
+                    acc[0] += w;
+                    acc[1] = fmaf(w, d, acc[1]);
+                    acc[2] = fmaf(w * d, d, acc[2]);
                 }
             }
-            const Sum3 z = block_sum3(Sum3{(double)s0, (double)s1, (double)s2}, lds);
+            const BlockSums<3> z = block_sums<3>(acc, lds, parity);
+            parity ^= 1;
             // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
-            const double dm = z.b / z.a;
+            const double dm = z.v[1] / z.v[0];
             mu += dm;
-            const double var = fmax((z.c - z.b * dm) / n, 0.0);
+            const double var = fmax((z.v[2] - z.v[1] * dm) / n, 0.0);
             sigma = fmax(sqrt(var), (double)floor_s);
         }
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
@@ -614,7 +611,8 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
             bool done = false;
             for (int ev = 0; ev < 32 && !done; ++ev) {
                 const double nud = ev == 0 ? 10.0 : ev == 1 ? 2.0 : 0.5 * (lo + hi);
-                const double f = nu_equation(r, n, nud, lds);
+                const double f = nu_equation(r, n, nud, lds, parity);
+                parity ^= 1;
                 if (ev == 0) {
                     if (f > 0.0) { nv = 10.0; done = true; }
                 } else if (ev == 1) {

@@ -67,7 +67,8 @@ struct rgbid_ctx {
     hipStream_t stream = nullptr;    // work stream (the caller's)
     hipStream_t cap = nullptr;       // private stream for graph capture
     std::string err;
-    DevBuf pairs, states, tables, partials, warped, sample, frames;
+    DevBuf pairs, states, tables, partials, warped, sample, frames, covis, cov_img;
+    rgbid_pyr* cov_pyr = nullptr;    // filtered reference of the covariance iteration
     void* h_stage = nullptr;         // pinned upload staging
     size_t h_stage_bytes = 0;
     hipEvent_t stage_done = nullptr; // last upload from h_stage finished
@@ -677,9 +678,10 @@ void rgbid_destroy(rgbid_ctx* c)
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     clear_graphs(c);
+    if (c->cov_pyr) rgbid_pyramid_free(c->cov_pyr);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
-                      &c->frames})
+                      &c->frames, &c->covis, &c->cov_img})
         if (b->p) hipFree(b->p);
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->h_down) hipHostFree(c->h_down);
@@ -1025,6 +1027,131 @@ rgbid_status rgbid_keyframe_read(rgbid_ctx* c, const rgbid_kf* kf, float* W_out,
     const size_t bytes = (size_t)kf->cam.width * kf->cam.height * sizeof(float);
     if (W_out) HIPCHK(c, hipMemcpyAsync(W_out, kf->W, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (C_out) HIPCHK(c, hipMemcpyAsync(C_out, kf->C, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_covisibility(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B, int level,
+                                const rgbid_pose* T, double tol, double* ratio, long long* counts)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!A || !B || !T || !ratio) return set_err(c, RGBID_E_ARG, "NULL argument");
+    if (level < 0 || level >= A->levels || level >= B->levels)
+        return set_err(c, RGBID_E_ARG, "level outside the pyramids");
+    if (A->w[level] != B->w[level] || A->h[level] != B->h[level] || A->f16 != B->f16)
+        return set_err(c, RGBID_E_SHAPE, "A and B differ in size or format");
+    if (!(tol > 0.0)) return set_err(c, RGBID_E_ARG, "tol must be > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    if ((st = ensure(c, c->covis, 4 * sizeof(unsigned long long))) != RGBID_OK) return st;
+    unsigned long long* cnt = static_cast<unsigned long long*>(c->covis.p);
+    HIPCHK(c, hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), c->stream));
+    // A -> B with T, then B -> A with T^-1 = (R^T, -R^T t)
+    double Ri[9], ti[3];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) Ri[3 * i + j] = T->R[3 * j + i];
+        ti[i] = -(Ri[3 * i] * T->t[0] + Ri[3 * i + 1] * T->t[1] + Ri[3 * i + 2] * T->t[2]);
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+        CovisArgs a;
+        a.WA = dir == 0 ? A->wp[level] : B->wp[level];
+        a.WB = dir == 0 ? B->wp[level] : A->wp[level];
+        a.f16 = A->f16;
+        a.w = A->w[level];
+        a.h = A->h[level];
+        a.fx = (float)A->fx[level];
+        a.fy = (float)A->fy[level];
+        a.cx = (float)A->cx[level];
+        a.cy = (float)A->cy[level];
+        if (dir == 0) pose_floats(T->R, T->t, a.RT, a.Rtt);
+        else pose_floats(Ri, ti, a.RT, a.Rtt);
+        a.tol = (float)tol;
+        a.count = cnt + 2 * dir;
+        HIPCHK(c, launch_covis(c->stream, a));
+    }
+    if ((st = ensure_down(c, 4 * sizeof(unsigned long long))) != RGBID_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->h_down, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const unsigned long long* h = static_cast<const unsigned long long*>(c->h_down);
+    const double ra = h[0] ? (double)h[1] / (double)h[0] : 0.0;
+    const double rb = h[2] ? (double)h[3] / (double)h[2] : 0.0;
+    *ratio = std::min(ra, rb);
+    if (counts)
+        for (int i = 0; i < 4; ++i) counts[i] = (long long)h[i];
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_covariance(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B,
+                              const rgbid_pose* T, const rgbid_align_params* P,
+                              const rgbid_bilateral* bf, double Sigma[36], rgbid_align_stats* stats)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!A || !B || !T || !Sigma) return set_err(c, RGBID_E_ARG, "NULL argument");
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    rgbid_bilateral b{2, 1.5, 10.0, 0.05};
+    if (bf) b = *bf;
+    if (b.radius < 0 || b.radius > 7 || !(b.sigma_s > 0) || !(b.sigma_I > 0) || !(b.rel_W > 0))
+        return set_err(c, RGBID_E_ARG, "bilateral parameters out of range");
+    HIPCHK(c, hipSetDevice(c->device));
+    // filtered copy of A: level 0 filtered, then its pyramid (cached per size)
+    rgbid_pyr*& F = c->cov_pyr;
+    if (F && (F->w[0] != A->w[0] || F->h[0] != A->h[0] || F->levels != A->levels || F->f16 != A->f16 ||
+              F->cam.fx != A->cam.fx || F->cam.fy != A->cam.fy || F->cam.cx != A->cam.cx ||
+              F->cam.cy != A->cam.cy)) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        rgbid_pyramid_free(F);
+        F = nullptr;
+    }
+    const size_t n0 = (size_t)A->w[0] * A->h[0];
+    rgbid_status st;
+    if ((st = ensure(c, c->cov_img, 2 * n0 * sizeof(float))) != RGBID_OK) return st;
+    float* If = static_cast<float*>(c->cov_img.p);
+    float* Wf = If + n0;
+    HIPCHK(c, launch_bilateral(c->stream, A->iw[0], A->f16, A->w[0], A->h[0], b.radius,
+                               (float)b.sigma_s, (float)b.sigma_I, (float)b.rel_W, If, Wf));
+    if (!F) {
+        if ((st = rgbid_pyramid(c, &A->cam, A->levels, A->f16 ? RGBID_F16 : RGBID_F32, If, Wf,
+                                (size_t)A->w[0], &F)) != RGBID_OK)
+            return st;
+    } else if ((st = rgbid_pyramid_update(c, F, If, Wf, (size_t)A->w[0])) != RGBID_OK) {
+        return st;
+    }
+    rgbid_align_stats s;
+    if ((st = rgbid_normal_equations(c, F, B, 0, T, P, &s)) != RGBID_OK) return st;
+    if (stats) *stats = s;
+    // Sigma = H^-1 by FP64 Cholesky on the host (6x6)
+    double H[6][6], L[6][6] = {};
+    int k = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int bb = a; bb < 6; ++bb) H[a][bb] = H[bb][a] = s.H[k++];
+    double dmax = 0.0;
+    for (int a = 0; a < 6; ++a) dmax = std::max(dmax, H[a][a]);
+    for (int j = 0; j < 6; ++j) {
+        double d = H[j][j];
+        for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
+        if (!(d > 1e-12 * dmax)) return set_err(c, RGBID_E_DEGENERATE, "filtered Hessian not positive definite");
+        L[j][j] = std::sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double e = H[i][j];
+            for (int q = 0; q < j; ++q) e -= L[i][q] * L[j][q];
+            L[i][j] = e / L[j][j];
+        }
+    }
+    for (int col = 0; col < 6; ++col) {
+        double y[6], x[6];
+        for (int i = 0; i < 6; ++i) {
+            double e = (i == col) ? 1.0 : 0.0;
+            for (int q = 0; q < i; ++q) e -= L[i][q] * y[q];
+            y[i] = e / L[i][i];
+        }
+        for (int i = 5; i >= 0; --i) {
+            double e = y[i];
+            for (int q = i + 1; q < 6; ++q) e -= L[q][i] * x[q];
+            x[i] = e / L[i][i];
+        }
+        for (int i = 0; i < 6; ++i) Sigma[6 * i + col] = x[i];
+    }
     return RGBID_OK;
 }
 

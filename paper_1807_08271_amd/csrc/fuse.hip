@@ -121,3 +121,150 @@ hipError_t launch_copy_valid(hipStream_t s, const float* src, long long pitch, i
 }
 
 }  // namespace rgbid
+
+namespace rgbid {
+namespace {
+
+template <bool F16>
+__device__ __forceinline__ float load_wp(const void* p, long long i)
+{
+    if constexpr (F16) return __half2float(static_cast<const __half*>(p)[i]);
+    else return static_cast<const float*>(p)[i];
+}
+
+// Dense covisibility (sec. 6.4), one direction: counts the pixels of A with a
+// valid W_A (S_H) and those whose transfer into B is in bounds with four valid
+// W_B taps and |W_B(p_B) - 1/Y_z| < tol (S_V).
+template <bool F16>
+__global__ void __launch_bounds__(256) k_covis(CovisArgs a)
+{
+    __shared__ unsigned int cnt[2][4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool inH = false, inV = false;
+    if (i < a.w * a.h) {
+        const int v = i / a.w, u = i - v * a.w;
+        const float wa = load_wp<F16>(a.WA, i);
+        if (w_valid(wa)) {
+            inH = true;
+            const float rx = ((float)u - a.cx) / a.fx, ry = ((float)v - a.cy) / a.fy;
+            const float ax = fmaf(a.RT[0], rx, fmaf(a.RT[1], ry, a.RT[2]));
+            const float ay = fmaf(a.RT[3], rx, fmaf(a.RT[4], ry, a.RT[5]));
+            const float az = fmaf(a.RT[6], rx, fmaf(a.RT[7], ry, a.RT[8]));
+            const float yx = fmaf(-wa, a.Rtt[0], ax), yy = fmaf(-wa, a.Rtt[1], ay);
+            const float yz = fmaf(-wa, a.Rtt[2], az);
+            if (yz > 0.0f) {
+                const float iz = 1.0f / yz;
+                const float ub = fmaf(a.fx * yx, iz, a.cx), vb = fmaf(a.fy * yy, iz, a.cy);
+                if (ub >= -0.5f && ub < (float)a.w - 0.5f && vb >= -0.5f && vb < (float)a.h - 0.5f) {
+                    const float fu = floorf(ub), fv = floorf(vb);
+                    const float al = ub - fu, be = vb - fv;
+                    int x0 = (int)fu, y0 = (int)fv;
+                    const int x1 = min(x0 + 1, a.w - 1), y1 = min(y0 + 1, a.h - 1);
+                    x0 = max(x0, 0);
+                    y0 = max(y0, 0);
+                    const float p00 = load_wp<F16>(a.WB, (long long)y0 * a.w + x0);
+                    const float p10 = load_wp<F16>(a.WB, (long long)y0 * a.w + x1);
+                    const float p01 = load_wp<F16>(a.WB, (long long)y1 * a.w + x0);
+                    const float p11 = load_wp<F16>(a.WB, (long long)y1 * a.w + x1);
+                    if (w_valid(p00) && w_valid(p10) && w_valid(p01) && w_valid(p11)) {
+                        const float wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 +
+                                         (1.0f - al) * be * p01 + al * be * p11;
+                        inV = fabsf(wb - wa * iz) < a.tol;
+                    }
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long bh = __ballot(inH), bv = __ballot(inV);
+    if (lane == 0) {
+        cnt[0][wave] = (unsigned int)__popcll(bh);
+        cnt[1][wave] = (unsigned int)__popcll(bv);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const unsigned int n = cnt[threadIdx.x][0] + cnt[threadIdx.x][1] + cnt[threadIdx.x][2] +
+                               cnt[threadIdx.x][3];
+        if (n) atomicAdd(a.count + threadIdx.x, (unsigned long long)n);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_covis(hipStream_t s, const CovisArgs& a)
+{
+    const int n = a.w * a.h;
+    if (n <= 0) return hipSuccess;
+    if (a.f16) hipLaunchKernelGGL(k_covis<true>, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_covis<false>, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace rgbid
+
+namespace rgbid {
+namespace {
+
+// Bilateral filter of the reference (I, W) before the covariance iteration:
+// spatial weight exp(-d^2 / (2 sigma_s^2)) over a (2r+1)^2 window, range
+// weight exp(-dI^2 / (2 sigma_I^2)) for intensity and
+// exp(-(dW / (rel_W W(p)))^2 / 2) for inverse depth; W holes neither
+// contribute nor receive a value.  Output: dense FP32 images.
+template <bool F16>
+__global__ void __launch_bounds__(256) k_bilateral(const void* __restrict__ iw, int w, int h,
+                                                   int radius, float inv2ss, float inv_sI,
+                                                   float inv_relW, float* Io, float* Wo)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= w * h) return;
+    const int v = i / w, u = i - v * w;
+    auto ld = [&](int j) -> float2 {
+        if constexpr (F16) return __half22float2(static_cast<const __half2*>(iw)[j]);
+        else return static_cast<const float2*>(iw)[j];
+    };
+    const float2 c = ld(i);
+    const bool wv = w_valid(c.y);
+    const float iw0 = wv ? inv_relW / c.y : 0.0f;
+    float si = 0.0f, swi = 0.0f, sw = 0.0f, sww = 0.0f;
+    for (int dv = -radius; dv <= radius; ++dv) {
+        const int y = v + dv;
+        if (y < 0 || y >= h) continue;
+        for (int du = -radius; du <= radius; ++du) {
+            const int x = u + du;
+            if (x < 0 || x >= w) continue;
+            const float2 q = ld(y * w + x);
+            const float gs = expf(-(float)(du * du + dv * dv) * inv2ss);
+            const float di = (q.x - c.x) * inv_sI;
+            const float gi = gs * expf(-0.5f * di * di);
+            si = fmaf(gi, q.x, si);
+            swi += gi;
+            if (wv && w_valid(q.y)) {
+                const float dw = (q.y - c.y) * iw0;
+                const float gw = gs * expf(-0.5f * dw * dw);
+                sw = fmaf(gw, q.y, sw);
+                sww += gw;
+            }
+        }
+    }
+    Io[i] = si / swi;
+    Wo[i] = wv ? sw / sww : 0.0f;
+}
+
+}  // namespace
+
+hipError_t launch_bilateral(hipStream_t s, const void* iw, int f16, int w, int h, int radius,
+                            float sigma_s, float sigma_I, float rel_W, float* Io, float* Wo)
+{
+    const int n = w * h;
+    if (n <= 0) return hipSuccess;
+    const float inv2ss = 1.0f / (2.0f * sigma_s * sigma_s);
+    if (f16)
+        hipLaunchKernelGGL(k_bilateral<true>, dim3((n + 255) / 256), dim3(256), 0, s, iw, w, h,
+                           radius, inv2ss, 1.0f / sigma_I, 1.0f / rel_W, Io, Wo);
+    else
+        hipLaunchKernelGGL(k_bilateral<false>, dim3((n + 255) / 256), dim3(256), 0, s, iw, w, h,
+                           radius, inv2ss, 1.0f / sigma_I, 1.0f / rel_W, Io, Wo);
+    return hipGetLastError();
+}
+
+}  // namespace rgbid

@@ -135,6 +135,21 @@ struct FuseArgs {
 };
 hipError_t launch_fuse(hipStream_t s, const FuseArgs& a);
 hipError_t launch_fill(hipStream_t s, float* p, int n, float v);
+
+struct CovisArgs {
+    const void* WA;       // W planes of one pyramid level (float or __half)
+    const void* WB;
+    int f16;
+    int w, h;
+    float fx, fy, cx, cy;
+    float RT[9];          // R^T of the pose of B in A
+    float Rtt[3];         // R^T t
+    float tol;
+    unsigned long long* count;   // [0] += |S_H|, [1] += |S_V|
+};
+hipError_t launch_covis(hipStream_t s, const CovisArgs& a);
+hipError_t launch_bilateral(hipStream_t s, const void* iw, int f16, int w, int h, int radius,
+                            float sigma_s, float sigma_I, float rel_W, float* Io, float* Wo);
 // Dense copy of a pitched inverse-depth map with holes normalised to 0.
 hipError_t launch_copy_valid(hipStream_t s, const float* src, long long pitch, int w, int h,
                              float* dst);

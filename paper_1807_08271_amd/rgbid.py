@@ -51,6 +51,11 @@ class rgbid_align_params(C.Structure):
                 ("stop_eps_r", C.c_double)]
 
 
+class rgbid_bilateral(C.Structure):
+    _fields_ = [("radius", C.c_int), ("sigma_s", C.c_double), ("sigma_I", C.c_double),
+                ("rel_W", C.c_double)]
+
+
 class rgbid_align_stats(C.Structure):
     _fields_ = [("H", C.c_double * 21), ("g", C.c_double * 6), ("mu_I", C.c_double),
                 ("sigma_I", C.c_double), ("nu_I", C.c_double), ("mu_W", C.c_double),
@@ -120,6 +125,11 @@ _SIGS = {
                                  C.POINTER(rgbid_align_params), C.c_int, C.POINTER(C.c_double)]),
     "rgbid_tune_save": (C.c_int, [_P, C.c_char_p]),
     "rgbid_tune_load": (C.c_int, [_P, C.c_char_p]),
+    "rgbid_covisibility": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(rgbid_pose), C.c_double,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    "rgbid_covariance": (C.c_int, [_P, _P, _P, C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
+                                   C.POINTER(rgbid_bilateral), C.POINTER(C.c_double),
+                                   C.POINTER(rgbid_align_stats)]),
     "rgbid_set_profiling": (C.c_int, [_P, C.c_int]),
     "rgbid_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
 }
@@ -487,3 +497,30 @@ def rgbid_tune_save(ctx, path):
 
 def rgbid_tune_load(ctx, path):
     _check(ctx, lib().rgbid_tune_load(ctx, path.encode()))
+
+
+# ----------------------------------------------------------------- covisibility
+
+
+def rgbid_covisibility(ctx, A, B, level, T, tol):
+    """Returns (ratio, (|S_H(A)|, |S_V(A->B)|, |S_H(B)|, |S_V(B->A)|))."""
+    r = C.c_double()
+    cnt = (C.c_longlong * 4)()
+    pose = make_pose(*T)
+    _check(ctx, lib().rgbid_covisibility(ctx, A, B, int(level), C.byref(pose), float(tol),
+                                         C.byref(r), cnt))
+    return r.value, tuple(cnt[:])
+
+
+# ----------------------------------------------------------------- covariance
+
+
+def rgbid_covariance(ctx, A, B, T, params, radius=2, sigma_s=1.5, sigma_I=10.0, rel_W=0.05):
+    """Returns (Sigma 6x6, stats dict of the filtered linearisation)."""
+    bf = rgbid_bilateral(int(radius), float(sigma_s), float(sigma_I), float(rel_W))
+    S = (C.c_double * 36)()
+    st = rgbid_align_stats()
+    pose = make_pose(*T)
+    _check(ctx, lib().rgbid_covariance(ctx, A, B, C.byref(pose), C.byref(params), C.byref(bf), S,
+                                       C.byref(st)))
+    return np.array(S[:]).reshape(6, 6), st.as_dict()

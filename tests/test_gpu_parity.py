@@ -324,3 +324,51 @@ def test_fuse_20_frames_matches_oracle(ctx):
     np.testing.assert_allclose(Cg[agree], Cr[agree], rtol=1e-5)
     assert np.all((Wg > 0) == (Wkf0 > 0))       # keyframe holes stay holes
     rg.rgbid_keyframe_free(K)
+
+
+# ----------------------------------------------------------------- covisibility
+
+
+@pytest.mark.parametrize("level", [0, 2])
+def test_covisibility_matches_oracle(ctx, c2_pairs, level):
+    # counts decided in FP32 on the GPU and FP64 in the oracle: equal up to a
+    # few pixels within rounding of a bounds / tap / tolerance threshold
+    rg = _rg()
+    p = c2_pairs[0]
+    A = _pyr(ctx, p.cam, 3, p.A)
+    B = _pyr(ctx, p.cam, 3, p.B)
+    WA = oracle.pyramid(p.cam, 3, p.A.I, p.A.W, storage="f32")[level][1]
+    WB = oracle.pyramid(p.cam, 3, p.B.I, p.B.W, storage="f32")[level][1]
+    cl = oracle.camera_level(p.cam, level)
+    for (R, t) in [(np.eye(3), np.zeros(3)), (p.R, p.t)]:
+        r, cnt = rg.rgbid_covisibility(ctx, A, B, level, (R, t), 0.01)
+        rr, cr = oracle.covisibility_ratio(cl, WA, WB, R, t, 0.01)
+        assert cnt[0] == cr[0] and cnt[2] == cr[2]          # hole masks: exact
+        assert abs(cnt[1] - cr[1]) <= 20 and abs(cnt[3] - cr[3]) <= 20, (cnt, cr)
+        assert abs(r - rr) <= 20.0 / min(cr[0], cr[2])
+        assert 0.3 < r <= 1.0
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+# ----------------------------------------------------------------- covariance
+
+
+def test_covariance_matches_oracle(ctx, c2_pairs):
+    # Sigma = H_filt^-1 from the bilateral-filtered reference at the final pose:
+    # the filtered normal equations meet the normal-equation bound, and the GPU
+    # covariance inverts the oracle's filtered Hessian.
+    rg = _rg()
+    p = c2_pairs[1]
+    A = _pyr(ctx, p.cam, 4, p.A)
+    B = _pyr(ctx, p.cam, 4, p.B)
+    prm = _params(4, [10] * 4)
+    R, t, _, rc = rg.rgbid_align(ctx, A, B, prm)
+    S, st = rg.rgbid_covariance(ctx, A, B, (R, t), prm)
+    So, sto = oracle.covariance(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, R, t, _oparams(4, [1] * 4))
+    check_normal_equations(st, sto, what="filtered covariance iteration")
+    np.testing.assert_allclose(S @ sto["H"], np.eye(6), atol=2e-3)
+    d = np.sqrt(np.diag(So))
+    assert np.all(np.abs(S - So) <= 2e-3 * np.outer(d, d) + 1e-30)
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)

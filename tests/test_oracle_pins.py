@@ -575,3 +575,81 @@ def test_fuse_occluder_rejected():
     W2, C2, n = oracle.fuse(cam, Wkf, np.ones((h, w)), Wk, np.eye(3), np.zeros(3), tol=0.01)
     assert np.all(C2[:, :19] == 1.0) and np.all(W2[:, :19] == 0.5)
     assert np.all(C2[:, 21:] == 2.0)
+
+
+# ----------------------------------------------------------------- covisibility
+
+
+def test_covisibility_identity_and_shift():
+    # identity, B = A: every pixel with a valid 2x2 tap neighbourhood is visible
+    w, h = 60, 40
+    cam = (w, h, 50.0, 50.0, 29.5, 19.5)
+    Z0 = 2.0
+    W = np.full((h, w), 1.0 / Z0)
+    nH, nV = oracle.covisibility(cam, W, W, np.eye(3), np.zeros(3), 0.01)
+    assert nH == w * h and nV == w * h
+    # fronto-parallel plane, B translated by k pixels along x: columns whose
+    # transfer leaves the image are not visible (closed form: k columns)
+    for k in (1, 3, 7):
+        t = np.array([k * Z0 / 50.0, 0.0, 0.0])
+        nH, nV = oracle.covisibility(cam, W, W, np.eye(3), t, 0.01)
+        assert nH == w * h and nV == (w - k) * h
+        r, counts = oracle.covisibility_ratio(cam, W, W, np.eye(3), t, 0.01)
+        assert r == pytest.approx((w - k) / w)
+
+
+def test_covisibility_occluder_and_holes():
+    w, h = 40, 30
+    cam = (w, h, 40.0, 40.0, 19.5, 14.5)
+    WA = np.full((h, w), 0.5)
+    WA[:5, :] = 0.0                      # holes are not in S_H
+    WB = np.full((h, w), 0.5)
+    WB[:, 30:] = 1.5                     # an occluder in B
+    nH, nV = oracle.covisibility(cam, WA, WB, np.eye(3), np.zeros(3), 0.01)
+    assert nH == (h - 5) * w
+    assert nV == (h - 5) * 30           # columns 30.. see the occluder
+
+
+# ----------------------------------------------------------------- covariance
+
+
+def test_bilateral_reduces_to_gaussian_blur_and_keeps_edges():
+    from scipy.ndimage import correlate
+    rng = np.random.default_rng(30)
+    I = rng.uniform(0, 255, (20, 24))
+    W = rng.uniform(0.5, 0.6, (20, 24))
+    # huge range sigmas: a normalised 5x5 Gaussian (library correlation, with
+    # the weights renormalised over the in-image part of the window)
+    Io, Wo = oracle.bilateral(I, W, 2, 1.5, 1e12, 1e12)
+    d = np.arange(-2, 3)
+    g = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * 1.5 ** 2))
+    num = correlate(I, g, mode="constant")
+    den = correlate(np.ones_like(I), g, mode="constant")
+    np.testing.assert_allclose(Io, num / den, rtol=1e-12)
+    # constant image stays constant; a step edge is kept with a small sigma
+    C = np.full((10, 10), 7.0)
+    np.testing.assert_allclose(oracle.bilateral(C, C * 0 + 0.5)[0], C, rtol=1e-14)
+    S = np.where(np.arange(10)[None, :] < 5, 0.0, 200.0) * np.ones((10, 1))
+    Wd = np.where(np.arange(10)[None, :] < 5, 0.5, 1.0) * np.ones((10, 1))
+    So, Wdo = oracle.bilateral(S, Wd, 2, 1.5, 1.0, 0.01)
+    np.testing.assert_allclose(So, S, atol=1e-9)
+    np.testing.assert_allclose(Wdo, Wd, rtol=1e-9)
+    # holes stay holes and are skipped
+    Wh = W.copy()
+    Wh[5, 5] = 0.0
+    _, Who = oracle.bilateral(I, Wh)
+    assert Who[5, 5] == 0.0 and np.all(Who[Wh > 0] > 0)
+
+
+def test_covariance_is_inverse_of_filtered_hessian():
+    import synth
+    p = synth.pair_c1(2)
+    P = oracle.Params(levels=1, iters=[1], storage="f64")
+    S, st = oracle.covariance(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, p.R, p.t, P)
+    np.testing.assert_allclose(S @ st["H"], np.eye(6), atol=1e-9)
+    np.testing.assert_allclose(S, S.T, rtol=1e-9, atol=1e-20)
+    assert np.all(np.linalg.eigvalsh(S) > 0)
+    # the Hessian is that of the filtered reference at the given pose
+    If, Wf = oracle.bilateral(p.A.I, p.A.W)
+    st2 = oracle.normal_equations_at(p.cam, If, Wf, p.B.I, p.B.W, 0, p.R, p.t, P)
+    np.testing.assert_allclose(st2["H"], st["H"], rtol=1e-12)
