@@ -295,6 +295,76 @@ rgbid_status rgbid_keyframe_read(rgbid_ctx* ctx, const rgbid_kf* kf, float* W_ou
 
 void rgbid_keyframe_free(rgbid_kf* kf);
 
+/* ------------------------------------------------------------ tracking front-end */
+
+/* Frame-to-reference tracking of an RGB-D sequence with keyframe fusion
+   (sec. 7.1, sec. 7.2).  Every frame k is aligned to the current reference
+   frame from the constant-velocity guess T_rf^{k-1} T_{k-2}^{k-1}; the
+   odometry constraint T_{k-1}^k and, if requested, its covariance (pose
+   covariance of sec. 6.2 propagated as in the appendix on covariance
+   composition) are formed; the dense covisibility ratio (sec. 6.4, at
+   pyramid level covis_level, tol = tol_sigmas * sigma_W of that alignment)
+   against the keyframe decides whether frame k starts a new keyframe
+   (ratio < kf_threshold) or is fused into it; after a keyframe switch the
+   frames recorded with the previous keyframe (at most `buffer`, most recent
+   first) are fused into the new one, one per incoming frame; the ratio
+   against the reference frame decides whether frame k becomes the next
+   reference frame (ratio < rf_threshold).  Covariances are over the left
+   perturbation (dt, dtheta): t -> t + dt, R -> exp(dtheta) R. */
+typedef struct {
+    rgbid_align_params align;  /* alignment of each frame to the reference */
+    double rf_threshold;       /* reference-frame switch (default 0.8; above kf_threshold) */
+    double kf_threshold;       /* keyframe switch (default 0.7) */
+    int covis_level;           /* pyramid level of the covisibility ratios (default 2) */
+    double tol_sigmas;         /* occlusion tolerance in sigma_W (default 3) */
+    int buffer;                /* pre-keyframe frame buffer, 0..64 (default 8) */
+    int covariance;            /* 1: pose and odometry covariances (default 1) */
+} rgbid_tracker_params;
+
+typedef struct {
+    long long frame;           /* k, counted from 0 */
+    rgbid_pose T_w_k;          /* pose of frame k in frame 0 */
+    rgbid_pose T_rf_k;         /* pose of frame k in its reference frame */
+    rgbid_pose T_prev_k;       /* odometry constraint: pose of frame k in frame k-1 */
+    double Sigma_rf_k[36];     /* covariance of T_rf_k, row-major (0 if not requested) */
+    double Sigma_odo[36];      /* covariance of T_prev_k (0 if not requested) */
+    double covis_rf, covis_kf; /* covisibility ratios with the reference frame and keyframe */
+    int rf_switched;           /* frame k is the reference frame of frame k+1 */
+    int kf_switched;           /* frame k started a new keyframe */
+    int cov_status;            /* rgbid_status of the covariance iteration */
+    long long n_fused;         /* keyframe pixels fused from frame k */
+    long long n_fused_buffer;  /* keyframe pixels fused from a buffered frame */
+    rgbid_align_stats stats;   /* alignment of frame k (zeros for frame 0) */
+} rgbid_track_result;
+
+typedef struct rgbid_tracker rgbid_tracker;
+
+/* Fills p with the defaults listed above (align = rgbid_default_params). */
+void rgbid_tracker_default_params(rgbid_tracker_params* p);
+
+/* Creates a tracker for frames of camera `cam`, with pyramids of `levels`
+   levels in `storage` format (levels >= align.levels, > covis_level).  The
+   tracker owns its pyramids (three), the keyframe and `2 buffer + 1` FP32
+   inverse-depth maps.  Errors: E_ARG, E_NOMEM. */
+rgbid_status rgbid_tracker_create(rgbid_ctx* ctx, const rgbid_camera* cam, int levels,
+                                  rgbid_format storage, const rgbid_tracker_params* params,
+                                  rgbid_tracker** out);
+
+/* Tracks the next frame (caller-owned FP32 device images, copied): frame 0
+   initialises the reference frame and the keyframe.  A degenerate alignment
+   keeps the guess and is reported in out->stats.status; a degenerate
+   covariance iteration sets cov_status and zero covariances.  Synchronises.
+   Errors: E_ARG, E_DEVICE. */
+rgbid_status rgbid_track(rgbid_ctx* ctx, rgbid_tracker* trk, const float* I_dev,
+                         const float* W_dev, size_t pitch_elems, rgbid_track_result* out);
+
+/* The tracker's active keyframe (owned by the tracker; read it with
+   rgbid_keyframe_read). */
+const rgbid_kf* rgbid_tracker_keyframe(const rgbid_tracker* trk);
+
+/* Releases the tracker (synchronises the device).  NULL is ignored. */
+void rgbid_tracker_free(rgbid_tracker* trk);
+
 /* ------------------------------------------------------------ pose maps */
 
 /* Decoupled exponential and logarithm of sec. 3: exp(xi) = (Rot(theta), v) for

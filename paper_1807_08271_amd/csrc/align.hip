@@ -26,25 +26,74 @@ namespace {
 
 __device__ __forceinline__ bool w_valid(float w) { return w > 0.0f && w < INFINITY; }
 
-template <bool F16>
-__device__ __forceinline__ float2 load_iw(const void* p, int i)
+// Image and workspace pointers reach the kernels through tables in memory, so
+// the compiler cannot tell they are global; these casts let it emit global
+// (not flat) loads and stores, which do not hold up scalar loads.
+#define RGBID_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const RGBID_GLOBAL T* gconst(const void* p)
 {
-    if constexpr (F16) return __half22float2(static_cast<const __half2*>(p)[i]);
-    else return static_cast<const float2*>(p)[i];
+    return (const RGBID_GLOBAL T*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ RGBID_GLOBAL T* gmut(void* p)
+{
+    return (RGBID_GLOBAL T*)p;
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+// Element i of a global array given a 32-bit element index: the byte offset
+// is formed in 32 bits (every image is far below 4 GiB), so the load takes
+// the uniform base from scalar registers and a 32-bit lane offset.
+template <typename T>
+__device__ __forceinline__ T ld_at(const void* base, unsigned i)
+{
+    const unsigned off = i * (unsigned)sizeof(T);
+    return *(const RGBID_GLOBAL T*)((const RGBID_GLOBAL char*)base + off);
 }
 
 template <bool F16>
-__device__ __forceinline__ float load_w(const void* p, int i)
+__device__ __forceinline__ float2 load_iw(const void* p, unsigned i)
 {
-    if constexpr (F16) return __half2float(static_cast<const __half*>(p)[i]);
-    else return static_cast<const float*>(p)[i];
+    if constexpr (F16) {
+        const h2v h = ld_at<h2v>(p, i);
+        return make_float2((float)h.x, (float)h.y);
+    } else {
+        const f2v f = ld_at<f2v>(p, i);
+        return make_float2(f.x, f.y);
+    }
+}
+
+template <bool F16>
+__device__ __forceinline__ float load_w(const void* p, unsigned i)
+{
+    if constexpr (F16) return (float)ld_at<_Float16>(p, i);
+    else return ld_at<float>(p, i);
+}
+
+__device__ __forceinline__ float2 load_f2(const void* p, size_t i)
+{
+    const f2v f = gconst<f2v>(p)[i];
+    return make_float2(f.x, f.y);
+}
+
+__device__ __forceinline__ void store_f2(void* p, size_t i, float a, float b)
+{
+    f2v v;
+    v.x = a;
+    v.y = b;
+    gmut<f2v>(p)[i] = v;
 }
 
 // Row / column of raster index idx in a grid of width gw (idx < 2^24).
 __device__ __forceinline__ void split_index(int idx, int gw, float inv_gw, int& gu, int& gv)
 {
     int v = (int)((float)idx * inv_gw);
-    int u = idx - v * gw;
+    int u = idx - (int)__umul24((unsigned)v, (unsigned)gw);
     if (u < 0) { u += gw; --v; }
     else if (u >= gw) { u -= gw; ++v; }
     gu = u;
@@ -120,14 +169,16 @@ __device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa,
     vb = ok ? vb : 0.0f;
     const float fu = floorf(ub), fv = floorf(vb);
     const float a = ub - fu, b = vb - fv;
-    int x0 = (int)fu, y0 = (int)fv;
-    const int x1 = min(x0 + 1, G.w - 1), y1 = min(y0 + 1, G.h - 1);
-    x0 = max(x0, 0);
-    y0 = max(y0, 0);
-    const float2 p00 = load_iw<F16>(G.Biw, y0 * G.w + x0);
-    const float2 p10 = load_iw<F16>(G.Biw, y0 * G.w + x1);
-    const float2 p01 = load_iw<F16>(G.Biw, y1 * G.w + x0);
-    const float2 p11 = load_iw<F16>(G.Biw, y1 * G.w + x1);
+    // taps: x0 = floor(u_B) (>= -1 in bounds), clamped to the image
+    const int xf = (int)fu, yf = (int)fv;
+    const unsigned x0 = (unsigned)max(xf, 0), y0 = (unsigned)max(yf, 0);
+    const unsigned dx = xf + 1 <= G.w - 1 && xf >= 0 ? 1u : 0u;
+    const unsigned dy = yf + 1 <= G.h - 1 && yf >= 0 ? (unsigned)G.w : 0u;
+    const unsigned i00 = __umul24(y0, (unsigned)G.w) + x0;
+    const float2 p00 = load_iw<F16>(G.Biw, i00);
+    const float2 p10 = load_iw<F16>(G.Biw, i00 + dx);
+    const float2 p01 = load_iw<F16>(G.Biw, i00 + dy);
+    const float2 p11 = load_iw<F16>(G.Biw, i00 + dy + dx);
     ok = ok && w_valid(p00.y) && w_valid(p10.y) && w_valid(p01.y) && w_valid(p11.y);
     const float c00 = (1.0f - a) * (1.0f - b), c10 = a * (1.0f - b);
     const float c01 = (1.0f - a) * b, c11 = a * b;
@@ -143,7 +194,7 @@ __device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa,
 template <bool F16>
 __device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, float& Wo)
 {
-    return warp_core<F16>(G, u, v, load_w<F16>(G.WA, v * G.w + u), Io, Wo);
+    return warp_core<F16>(G, u, v, load_w<F16>(G.WA, __umul24(v, G.w) + u), Io, Wo);
 }
 
 // Warp-level coordinates of the children this lane handles in one pass, and
@@ -156,16 +207,18 @@ struct PassChildren {
 };
 
 // Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
-// children at the warp level; LPP = min(C, 64) lanes share one pixel, GPP =
-// 64 / LPP pixels are warped per pass, and each lane handles CPL = C / LPP
-// children.
+// children at the warp level; each lane warps CPL = min(C, 4) of them (four
+// independent load chains per lane), LPP = C / CPL lanes share one pixel and
+// combine their sums with cross-lane shuffles, and GPP = 64 / LPP pixels are
+// warped per pass.
 template <int LOG2B>
 struct ChildLayout {
     static constexpr int B = 1 << LOG2B;
     static constexpr int C = B * B;
-    static constexpr int LPP = C < 64 ? C : 64;
-    static constexpr int GPP = 64 / LPP;
-    static constexpr int CPL = C / LPP;
+    static constexpr int CPL = C < 4 ? C : 4;   // children per lane
+    static constexpr int LPP = C / CPL;         // lanes per pixel
+    static constexpr int GPP = 64 / LPP;        // pixels per pass
+    static_assert(LPP <= 64, "at most 64 lanes per level pixel");
 };
 
 // Children of the pixel of lane group g in the pass starting at grid pixel
@@ -183,9 +236,9 @@ pass_children(const Geom& G, int first, int gw, float inv_gw, int ngrid, int gs,
 #pragma unroll
     for (int m = 0; m < CL::CPL; ++m) {
         const int c = j + CL::LPP * m;
-        pc.u[m] = gu * gs * CL::B + (c % CL::B);
-        pc.v[m] = gv * gs * CL::B + (c / CL::B);
-        pc.wa[m] = load_w<F16>(G.WA, pc.v[m] * G.w + pc.u[m]);
+        pc.u[m] = __umul24(gu, gs * CL::B) + (c % CL::B);
+        pc.v[m] = __umul24(gv, gs * CL::B) + (c / CL::B);
+        pc.wa[m] = load_w<F16>(G.WA, __umul24(pc.v[m], G.w) + pc.u[m]);
     }
     return pc;
 }
@@ -291,7 +344,7 @@ struct Nbrs {
 template <bool F16>
 __device__ __forceinline__ Nbrs load_nbrs(const LevelView& A, int u, int v)
 {
-    const int i = v * A.w + u;
+    const int i = (int)__umul24(v, A.w) + u;
     Nbrs n;
     n.l = load_iw<F16>(A.iw, u > 0 ? i - 1 : i);
     n.r = load_iw<F16>(A.iw, u < A.w - 1 ? i + 1 : i);
@@ -344,7 +397,7 @@ template <bool F16, bool JAC>
 __device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float ify, int u, int v,
                                             float Is, float Ws, bool wv, Terms& T)
 {
-    const float2 c = load_iw<F16>(A.iw, v * A.w + u);
+    const float2 c = load_iw<F16>(A.iw, __umul24(v, A.w) + u);
     const Nbrs n = load_nbrs<F16>(A, u, v);
     terms_core<JAC>(A, ifx, ify, u, v, c, n, Is, Ws, wv, T);
 }
@@ -434,11 +487,13 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
     const int l = L.level;
     const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
     const Geom G = make_geom(S, D.A[wl], D.B[wl]);
-    const LevelView& A = D.A[l];
+    const LevelView A = D.A[l];
     const float ifx = 1.0f / A.fx, ify = 1.0f / A.fy;
     const bool fused = L.tune.fused;
     const GridDim gd = fused ? sample_grid(D, l) : level_grid(A);
     const int s = D.stride[l], sw = D.sw[l];
+    void* const warped = D.warped;
+    void* const sample = D.sample;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
@@ -456,15 +511,15 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
         int gu, gv;
         split_index(idx, gd.gw, gd.inv_gw, gu, gv);
         const int u = gu * gd.gs, v = gv * gd.gs;
-        if (!fused) D.warped[idx] = make_float2(Is, wv ? Ws : 0.0f);
+        if (!fused) store_f2(warped, idx, Is, wv ? Ws : 0.0f);
         int sidx;
         if (fused) sidx = idx;
         else if ((u % s) == 0 && (v % s) == 0) sidx = (v / s) * sw + u / s;
         else continue;
         Terms T;
         pixel_terms<F16, false>(A, ifx, ify, u, v, Is, Ws, wv, T);
-        D.sample[sidx] = make_float2(T.vI ? T.rI : __int_as_float(0x7fc00000),
-                                     T.vW ? T.rW : __int_as_float(0x7fc00000));
+        store_f2(sample, sidx, T.vI ? T.rI : __int_as_float(0x7fc00000),
+                 T.vW ? T.rW : __int_as_float(0x7fc00000));
     }
 }
 
@@ -560,7 +615,7 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
         const int i = threadIdx.x + k * kScaleThreads;
         float x = __int_as_float(0x7fc00000);
         if (i < n_all) {
-            const float2 e = D.sample[i];
+            const float2 e = load_f2(D.sample, i);
             x = ch == 0 ? e.x : e.y;
         }
         r[k] = x;
@@ -646,9 +701,10 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     if (!S.active || S.level_stop) return;
     const PairDesc& D = L.pairs[ch.pair];
     const int l = L.level;
-    const LevelView& A = D.A[l];
+    const LevelView A = D.A[l];
     const float ifx = 1.0f / A.fx, ify = 1.0f / A.fy;
     const GridDim gd = level_grid(A);
+    const void* const warped = D.warped;
 
     const int kind = L.ip.weight;
     const float kh = L.ip.huber_k;
@@ -718,7 +774,7 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             } else {
                 idx = tile * 64 + lane;
                 const int ic = idx < gd.n ? idx : 0;
-                const float2 e = D.warped[ic];
+                const float2 e = load_f2(warped, ic);
                 Is = e.x;
                 Ws = e.y;
                 wv = Ws > 0.0f && idx < gd.n;
@@ -755,7 +811,7 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             lo += (hi - (s - bp)) + (x - bp);
             hi = s;
         }
-        L.partials[(size_t)ci * kNSum + threadIdx.x] = make_float2(hi, lo);
+        store_f2(L.partials, (size_t)ci * kNSum + threadIdx.x, hi, lo);
     }
 }
 
@@ -801,9 +857,11 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
 #pragma unroll
     for (int k = 0; k < kNSum; ++k) s[k] = 0.0;
     for (int c = beg + lane; c < end; c += 64) {
-        const float2* P = L.partials + (size_t)c * kNSum;
 #pragma unroll
-        for (int k = 0; k < kNSum; ++k) s[k] += (double)P[k].x + (double)P[k].y;
+        for (int k = 0; k < kNSum; ++k) {
+            const float2 q = load_f2(L.partials, (size_t)c * kNSum + k);
+            s[k] += (double)q.x + (double)q.y;
+        }
     }
 #pragma unroll
     for (int k = 0; k < kNSum; ++k) s[k] = wave_sum_d(s[k]);

@@ -1469,3 +1469,348 @@ rgbid_status rgbid_warmstart_train_step(rgbid_ctx* c, rgbid_net* net, int n, con
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ tracking front-end
+// Sequence-level policy of sec. 7.1 / 7.2 on top of the calls above: the
+// per-pixel work is the alignment, covisibility, covariance and fusion
+// kernels; this part only keeps poses (FP64, host) and chooses which frames
+// are the reference frame and the keyframe.
+
+struct rgbid_tracker {
+    int device = 0;
+    rgbid_camera cam{};
+    int levels = 0;
+    rgbid_format storage = RGBID_F32;
+    rgbid_tracker_params p{};
+    rgbid_pyr* slot[3] = {nullptr, nullptr, nullptr};   // frame pyramids
+    int rf = -1, kfs = -1;        // slots of the reference frame and of the keyframe's frame
+    rgbid_kf* kf = nullptr;
+    float* maps = nullptr;        // 2 * buffer dense FP32 inverse-depth maps
+    std::vector<int> free_maps;
+    struct Rec {
+        int map;
+        rgbid_pose T_w;
+        double tol;
+    };
+    std::vector<Rec> recorded;    // frames of the active keyframe, oldest first
+    std::vector<Rec> pending;     // frames of the previous keyframe, next to fuse first
+    rgbid_pose T_w_rf{}, T_w_kf{}, T_rf_prev{}, T_prev2_prev{};
+    double S_rf_prev[36] = {};
+    long long k = -1;
+};
+
+namespace {
+
+rgbid_pose pose_identity()
+{
+    rgbid_pose T{};
+    T.R[0] = T.R[4] = T.R[8] = 1.0;
+    return T;
+}
+
+// a * b (T_A^C = T_A^B T_B^C)
+rgbid_pose pose_mul(const rgbid_pose& a, const rgbid_pose& b)
+{
+    rgbid_pose c{};
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < 3; ++q) s += a.R[3 * i + q] * b.R[3 * q + j];
+            c.R[3 * i + j] = s;
+        }
+        double s = a.t[i];
+        for (int q = 0; q < 3; ++q) s += a.R[3 * i + q] * b.t[q];
+        c.t[i] = s;
+    }
+    return c;
+}
+
+rgbid_pose pose_inv(const rgbid_pose& a)
+{
+    rgbid_pose c{};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c.R[3 * i + j] = a.R[3 * j + i];
+    for (int i = 0; i < 3; ++i)
+        c.t[i] = -(c.R[3 * i] * a.t[0] + c.R[3 * i + 1] * a.t[1] + c.R[3 * i + 2] * a.t[2]);
+    return c;
+}
+
+// out = J S J^T for 6x6 row-major matrices (out may not alias S)
+void sandwich_add(const double J[36], const double S[36], double out[36])
+{
+    double JS[36];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < 6; ++q) s += J[6 * i + q] * S[6 * q + j];
+            JS[6 * i + j] = s;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < 6; ++q) s += JS[6 * i + q] * J[6 * j + q];
+            out[6 * i + j] += s;
+        }
+}
+
+// [v]x written into the 3x3 block at (r, c) of a 6x6 row-major matrix, scaled
+void put_skew(double M[36], int r, int c, const double v[3], double s)
+{
+    M[6 * r + c + 1] += -s * v[2];
+    M[6 * r + c + 2] += s * v[1];
+    M[6 * (r + 1) + c] += s * v[2];
+    M[6 * (r + 1) + c + 2] += -s * v[0];
+    M[6 * (r + 2) + c] += -s * v[1];
+    M[6 * (r + 2) + c + 1] += s * v[0];
+}
+
+// The alignment's step xi = (v, theta) updates T <- exp(xi)^-1 T (sec. 6.2);
+// to first order that is the left perturbation dtheta = -theta,
+// dt = -v + [t]x theta, so Sigma_left = M Sigma_xi M^T.
+void xi_cov_to_left(const rgbid_pose& T, const double Sxi[36], double out[36])
+{
+    double M[36] = {};
+    for (int i = 0; i < 3; ++i) {
+        M[6 * i + i] = -1.0;
+        M[6 * (i + 3) + i + 3] = -1.0;
+    }
+    put_skew(M, 0, 3, T.t, 1.0);
+    std::memset(out, 0, 36 * sizeof(double));
+    sandwich_add(M, Sxi, out);
+}
+
+// Covariance of T_A^B = (T_W^A)^-1 T_W^B from left-perturbation covariances
+// of T_W^A and T_W^B (appendix on covariance propagation):
+//   J_A = -[[R_A^T, R_A^T [t_A - t_B]x], [0, R_A^T]],  J_B = diag(R_A^T, R_A^T).
+void relative_covariance(const rgbid_pose& Twa, const double Sa[36], const rgbid_pose& Twb,
+                         const double Sb[36], double out[36])
+{
+    double Ja[36] = {}, Jb[36] = {};
+    double RaT[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) RaT[3 * i + j] = Twa.R[3 * j + i];
+    const double d[3] = {Twa.t[0] - Twb.t[0], Twa.t[1] - Twb.t[1], Twa.t[2] - Twb.t[2]};
+    // R_A^T [d]x, column by column: (R_A^T [d]x)_{ij} = sum_q RaT_iq [d]x_qj
+    double K[9] = {0.0, -d[2], d[1], d[2], 0.0, -d[0], -d[1], d[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < 3; ++q) s += RaT[3 * i + q] * K[3 * q + j];
+            Ja[6 * i + j] = -RaT[3 * i + j];
+            Ja[6 * i + j + 3] = -s;
+            Ja[6 * (i + 3) + j + 3] = -RaT[3 * i + j];
+            Jb[6 * i + j] = RaT[3 * i + j];
+            Jb[6 * (i + 3) + j + 3] = RaT[3 * i + j];
+        }
+    std::memset(out, 0, 36 * sizeof(double));
+    sandwich_add(Ja, Sa, out);
+    sandwich_add(Jb, Sb, out);
+}
+
+int take_map(rgbid_tracker* t)
+{
+    const int m = t->free_maps.back();
+    t->free_maps.pop_back();
+    return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rgbid_tracker_default_params(rgbid_tracker_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    rgbid_default_params(&p->align);
+    p->rf_threshold = 0.8;
+    p->kf_threshold = 0.7;
+    p->covis_level = 2;
+    p->tol_sigmas = 3.0;
+    p->buffer = 8;
+    p->covariance = 1;
+}
+
+void rgbid_tracker_free(rgbid_tracker* t)
+{
+    if (!t) return;
+    hipSetDevice(t->device);
+    hipDeviceSynchronize();
+    for (auto* s : t->slot)
+        if (s) rgbid_pyramid_free(s);
+    if (t->kf) rgbid_keyframe_free(t->kf);
+    if (t->maps) hipFree(t->maps);
+    delete t;
+}
+
+rgbid_status rgbid_tracker_create(rgbid_ctx* c, const rgbid_camera* cam, int levels,
+                                  rgbid_format storage, const rgbid_tracker_params* P,
+                                  rgbid_tracker** out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out) return set_err(c, RGBID_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cam || !P) return set_err(c, RGBID_E_ARG, "NULL camera or parameters");
+    std::string why;
+    if (!params_ok(&P->align, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    if (levels < P->align.levels || levels > kMaxLevels)
+        return set_err(c, RGBID_E_ARG, "levels must lie in [align.levels, 8]");
+    if (P->covis_level < 0 || P->covis_level >= levels)
+        return set_err(c, RGBID_E_ARG, "covis_level outside the pyramid");
+    if (!(P->rf_threshold >= 0.0 && P->rf_threshold <= 1.0 && P->kf_threshold >= 0.0 &&
+          P->kf_threshold <= 1.0))
+        return set_err(c, RGBID_E_ARG, "thresholds must lie in [0, 1]");
+    if (!(P->tol_sigmas > 0.0)) return set_err(c, RGBID_E_ARG, "tol_sigmas must be > 0");
+    if (P->buffer < 0 || P->buffer > 64) return set_err(c, RGBID_E_ARG, "buffer outside 0..64");
+    if (storage != RGBID_F32 && storage != RGBID_F16) return set_err(c, RGBID_E_ARG, "unknown storage");
+    if (cam->width < 1 || cam->height < 1 || !(cam->fx > 0 && cam->fy > 0))
+        return set_err(c, RGBID_E_ARG, "bad camera");
+    if ((cam->width >> (levels - 1)) < 1 || (cam->height >> (levels - 1)) < 1)
+        return set_err(c, RGBID_E_ARG, "level %d would be empty", levels - 1);
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_tracker* t = new (std::nothrow) rgbid_tracker();
+    if (!t) return set_err(c, RGBID_E_NOMEM, "host allocation failed");
+    t->device = c->device;
+    t->cam = *cam;
+    t->levels = levels;
+    t->storage = storage;
+    t->p = *P;
+    if (P->buffer > 0) {
+        const size_t np = (size_t)cam->width * cam->height;
+        hipError_t e = hipMalloc(&t->maps, 2 * (size_t)P->buffer * np * sizeof(float));
+        if (e != hipSuccess) {
+            delete t;
+            return set_err(c, RGBID_E_NOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+        }
+        for (int m = 2 * P->buffer - 1; m >= 0; --m) t->free_maps.push_back(m);
+    }
+    *out = t;
+    return RGBID_OK;
+}
+
+const rgbid_kf* rgbid_tracker_keyframe(const rgbid_tracker* t) { return t ? t->kf : nullptr; }
+
+rgbid_status rgbid_track(rgbid_ctx* c, rgbid_tracker* t, const float* I_dev, const float* W_dev,
+                         size_t pitch_elems, rgbid_track_result* out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!t || !I_dev || !W_dev || !out) return set_err(c, RGBID_E_ARG, "NULL argument");
+    if (t->device != c->device) return set_err(c, RGBID_E_ARG, "tracker on another device");
+    if (pitch_elems < (size_t)t->cam.width) return set_err(c, RGBID_E_ARG, "pitch < width");
+    HIPCHK(c, hipSetDevice(c->device));
+    const rgbid_tracker_params& P = t->p;
+    std::memset(out, 0, sizeof(*out));
+    rgbid_status st;
+    // a pyramid slot that is neither the reference frame nor the keyframe's
+    int s = 0;
+    while (s == t->rf || s == t->kfs) ++s;
+    if (!t->slot[s]) {
+        if ((st = rgbid_pyramid(c, &t->cam, t->levels, t->storage, I_dev, W_dev, pitch_elems,
+                                &t->slot[s])) != RGBID_OK)
+            return st;
+    } else if ((st = rgbid_pyramid_update(c, t->slot[s], I_dev, W_dev, pitch_elems)) != RGBID_OK) {
+        return st;
+    }
+    const long long k = t->k + 1;
+    out->frame = k;
+    const rgbid_pose I = pose_identity();
+    if (k == 0) {
+        if (t->kf) {
+            if ((st = rgbid_keyframe_reset(c, t->kf, W_dev, pitch_elems)) != RGBID_OK) return st;
+        } else if ((st = rgbid_keyframe_init(c, &t->cam, W_dev, pitch_elems, &t->kf)) != RGBID_OK) {
+            return st;
+        }
+        t->rf = t->kfs = s;
+        t->T_w_rf = t->T_w_kf = t->T_rf_prev = t->T_prev2_prev = I;
+        std::memset(t->S_rf_prev, 0, sizeof(t->S_rf_prev));
+        out->T_w_k = out->T_rf_k = out->T_prev_k = I;
+        out->covis_rf = out->covis_kf = 1.0;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        t->k = k;
+        return RGBID_OK;
+    }
+    // constant-velocity guess (sec. 7.1) and the alignment to the reference
+    const rgbid_pose init = pose_mul(t->T_rf_prev, t->T_prev2_prev);
+    rgbid_pose T_rf_k;
+    const rgbid_pyr* const A1[1] = {t->slot[t->rf]};
+    const rgbid_pyr* const B1[1] = {t->slot[s]};
+    if ((st = rgbid_align_batch(c, 1, A1, B1, &init, &P.align, &T_rf_k, &out->stats)) != RGBID_OK)
+        return st;
+    const double tol = std::max(P.tol_sigmas * out->stats.sigma_W, 1e-12);
+    double S_rf_k[36] = {};
+    if (P.covariance) {
+        double Sxi[36];
+        st = rgbid_covariance(c, t->slot[t->rf], t->slot[s], &T_rf_k, &P.align, nullptr, Sxi, nullptr);
+        if (st == RGBID_OK) {
+            xi_cov_to_left(T_rf_k, Sxi, S_rf_k);
+            relative_covariance(t->T_rf_prev, t->S_rf_prev, T_rf_k, S_rf_k, out->Sigma_odo);
+            std::memcpy(out->Sigma_rf_k, S_rf_k, sizeof(S_rf_k));
+        } else if (st != RGBID_E_DEGENERATE) {
+            return st;
+        }
+        out->cov_status = st;
+    }
+    const rgbid_pose T_prev_k = pose_mul(pose_inv(t->T_rf_prev), T_rf_k);
+    const rgbid_pose T_w_k = pose_mul(t->T_w_rf, T_rf_k);
+    // keyframe (sec. 7.2): switch, or fuse this frame and one buffered frame
+    const rgbid_pose T_kf_k = pose_mul(pose_inv(t->T_w_kf), T_w_k);
+    if ((st = rgbid_covisibility(c, t->slot[t->kfs], t->slot[s], P.covis_level, &T_kf_k, tol,
+                                 &out->covis_kf, nullptr)) != RGBID_OK)
+        return st;
+    if (out->covis_kf < P.kf_threshold) {
+        out->kf_switched = 1;
+        t->kfs = s;
+        t->T_w_kf = T_w_k;
+        if ((st = rgbid_keyframe_reset(c, t->kf, W_dev, pitch_elems)) != RGBID_OK) return st;
+        for (const auto& r : t->pending) t->free_maps.push_back(r.map);
+        t->pending.assign(t->recorded.rbegin(), t->recorded.rend());
+        t->recorded.clear();
+    } else {
+        if ((st = rgbid_fuse(c, t->kf, W_dev, pitch_elems, &T_kf_k, tol, &out->n_fused)) != RGBID_OK)
+            return st;
+        if (!t->pending.empty()) {
+            const auto r = t->pending.front();
+            t->pending.erase(t->pending.begin());
+            const rgbid_pose T_kf_j = pose_mul(pose_inv(t->T_w_kf), r.T_w);
+            const size_t np = (size_t)t->cam.width * t->cam.height;
+            if ((st = rgbid_fuse(c, t->kf, t->maps + (size_t)r.map * np, (size_t)t->cam.width,
+                                 &T_kf_j, r.tol, &out->n_fused_buffer)) != RGBID_OK)
+                return st;
+            t->free_maps.push_back(r.map);
+        }
+    }
+    if (P.buffer > 0) {
+        if ((int)t->recorded.size() == P.buffer) {
+            t->free_maps.push_back(t->recorded.front().map);
+            t->recorded.erase(t->recorded.begin());
+        }
+        const int m = take_map(t);
+        const size_t np = (size_t)t->cam.width * t->cam.height;
+        HIPCHK(c, launch_copy_valid(c->stream, W_dev, (long long)pitch_elems, t->cam.width,
+                                    t->cam.height, t->maps + (size_t)m * np));
+        t->recorded.push_back(rgbid_tracker::Rec{m, T_w_k, tol});
+    }
+    // reference frame (sec. 7.1 with the covisibility criterion of sec. 7.2)
+    if ((st = rgbid_covisibility(c, t->slot[t->rf], t->slot[s], P.covis_level, &T_rf_k, tol,
+                                 &out->covis_rf, nullptr)) != RGBID_OK)
+        return st;
+    out->T_w_k = T_w_k;
+    out->T_rf_k = T_rf_k;
+    out->T_prev_k = T_prev_k;
+    t->T_prev2_prev = T_prev_k;
+    if (out->covis_rf < P.rf_threshold) {
+        out->rf_switched = 1;
+        t->rf = s;
+        t->T_w_rf = T_w_k;
+        t->T_rf_prev = I;
+        std::memset(t->S_rf_prev, 0, sizeof(t->S_rf_prev));
+    } else {
+        t->T_rf_prev = T_rf_k;
+        std::memcpy(t->S_rf_prev, S_rf_k, sizeof(S_rf_k));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    t->k = k;
+    return RGBID_OK;
+}
+
+}  // extern "C"

@@ -76,6 +76,31 @@ class rgbid_align_stats(C.Structure):
                     iters_done=list(self.iters_done[:]), status=self.status)
 
 
+class rgbid_tracker_params(C.Structure):
+    _fields_ = [("align", rgbid_align_params), ("rf_threshold", C.c_double),
+                ("kf_threshold", C.c_double), ("covis_level", C.c_int),
+                ("tol_sigmas", C.c_double), ("buffer", C.c_int), ("covariance", C.c_int)]
+
+
+class rgbid_track_result(C.Structure):
+    _fields_ = [("frame", C.c_longlong), ("T_w_k", rgbid_pose), ("T_rf_k", rgbid_pose),
+                ("T_prev_k", rgbid_pose), ("Sigma_rf_k", C.c_double * 36),
+                ("Sigma_odo", C.c_double * 36), ("covis_rf", C.c_double),
+                ("covis_kf", C.c_double), ("rf_switched", C.c_int), ("kf_switched", C.c_int),
+                ("cov_status", C.c_int), ("n_fused", C.c_longlong),
+                ("n_fused_buffer", C.c_longlong), ("stats", rgbid_align_stats)]
+
+    def as_dict(self):
+        return dict(k=self.frame, T_w_k=pose_tuple(self.T_w_k), T_rf_k=pose_tuple(self.T_rf_k),
+                    T_prev_k=pose_tuple(self.T_prev_k),
+                    S_rf_k=np.array(self.Sigma_rf_k[:]).reshape(6, 6),
+                    S_odo=np.array(self.Sigma_odo[:]).reshape(6, 6), covis_rf=self.covis_rf,
+                    covis_kf=self.covis_kf, rf_switched=bool(self.rf_switched),
+                    kf_switched=bool(self.kf_switched), cov_status=self.cov_status,
+                    n_fused=self.n_fused, n_fused_buffer=self.n_fused_buffer,
+                    stats=self.stats.as_dict())
+
+
 _lib = None
 
 # Every exported entry point with (restype, argtypes).
@@ -130,6 +155,12 @@ _SIGS = {
     "rgbid_covariance": (C.c_int, [_P, _P, _P, C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
                                    C.POINTER(rgbid_bilateral), C.POINTER(C.c_double),
                                    C.POINTER(rgbid_align_stats)]),
+    "rgbid_tracker_default_params": (None, [C.POINTER(rgbid_tracker_params)]),
+    "rgbid_tracker_create": (C.c_int, [_P, C.POINTER(rgbid_camera), C.c_int, C.c_int,
+                                       C.POINTER(rgbid_tracker_params), C.POINTER(_P)]),
+    "rgbid_track": (C.c_int, [_P, _P, _P, _P, C.c_size_t, C.POINTER(rgbid_track_result)]),
+    "rgbid_tracker_keyframe": (_P, [_P]),
+    "rgbid_tracker_free": (None, [_P]),
     "rgbid_set_profiling": (C.c_int, [_P, C.c_int]),
     "rgbid_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
 }
@@ -524,3 +555,43 @@ def rgbid_covariance(ctx, A, B, T, params, radius=2, sigma_s=1.5, sigma_I=10.0, 
     _check(ctx, lib().rgbid_covariance(ctx, A, B, C.byref(pose), C.byref(params), C.byref(bf), S,
                                        C.byref(st)))
     return np.array(S[:]).reshape(6, 6), st.as_dict()
+
+
+# ----------------------------------------------------------------- tracking front-end
+
+
+def rgbid_tracker_default_params(align=None, **overrides) -> rgbid_tracker_params:
+    p = rgbid_tracker_params()
+    lib().rgbid_tracker_default_params(C.byref(p))
+    if align is not None:
+        p.align = align
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def rgbid_tracker_create(ctx, cam, levels: int, storage: int, params: rgbid_tracker_params):
+    out = C.c_void_p()
+    c = _cam(cam)
+    _check(ctx, lib().rgbid_tracker_create(ctx, C.byref(c), int(levels), int(storage),
+                                           C.byref(params), C.byref(out)))
+    return out
+
+
+def rgbid_track(ctx, trk, I, W):
+    """Tracks the next frame; returns the result as a dict (poses as (R, t))."""
+    pI, pitch = _img(I)
+    pW, pitchW = _img(W)
+    if pitch != pitchW:
+        raise ValueError("I and W need the same row pitch")
+    res = rgbid_track_result()
+    _check(ctx, lib().rgbid_track(ctx, trk, pI, pW, pitch, C.byref(res)))
+    return res.as_dict()
+
+
+def rgbid_tracker_keyframe(trk):
+    return C.c_void_p(lib().rgbid_tracker_keyframe(trk))
+
+
+def rgbid_tracker_free(trk):
+    lib().rgbid_tracker_free(trk)

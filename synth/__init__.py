@@ -10,12 +10,13 @@ from .scene import (Camera, Scene, Frame, Pair, planes3_scene, room_scene,
                     closed_room_scene, render, make_frame, random_motion,
                     compose, invert, relative, pair_c1, pair_c2, walk_c3,
                     batch_c4, pair_warm, keyframe_sequence, camera_640,
-                    camera_160, camera_320, camera_1280, to_fp16_grid)
+                    camera_160, camera_320, camera_1280, to_fp16_grid,
+                    track_sequence)
 
 __all__ = [
     "Camera", "Scene", "Frame", "Pair", "planes3_scene", "room_scene",
     "closed_room_scene", "render", "make_frame", "random_motion", "compose",
     "invert", "relative", "pair_c1", "pair_c2", "walk_c3", "batch_c4",
     "pair_warm", "keyframe_sequence", "camera_640", "camera_160",
-    "camera_320", "camera_1280", "to_fp16_grid",
+    "camera_320", "camera_1280", "to_fp16_grid", "track_sequence",
 ]

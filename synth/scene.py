@@ -476,3 +476,26 @@ def walk_c3(n_frames: int = 300, seed: int = 0, cam: Camera = None, ss: int = 2,
                   hole_frac=0.0, ss=ss, device=device)
         frames = [make_frame(scene, cam, p, rng, **kw) for p in poses]
     return cam, scene, poses, frames
+
+
+def track_sequence(n_frames: int, step_deg: float, step_m: float, seed: int = 0,
+                   cam: Camera = None, ss: int = 2, device="cpu", noise: bool = True,
+                   axis=(0.0, 1.0, 0.0)):
+    """Constant-velocity sequence in the room scene: every step turns the
+    camera by step_deg about `axis` (camera coordinates) and moves it step_m
+    along its own x axis, so the view drifts steadily away from the first
+    frame.  Returns (cam, poses, frames) with poses camera-to-world."""
+    cam = cam or camera_160()
+    rng = _seed(5, seed)
+    scene = room_scene(9500 + seed)
+    step = (Rotation.from_rotvec(np.radians(step_deg) * np.asarray(axis, float)).as_matrix(),
+            np.array([step_m, 0.0, 0.0]))
+    pose = (_pitch_down(10.0), np.array([-0.3, 0.0, 0.0]))
+    kw = dict(sigma_I=2.0 if noise else 0.0, sigma_W="quadratic",
+              sigma_W_coef=1.5e-3 if noise else 0.0, hole_frac=0.0, ss=ss, device=device)
+    poses, frames = [], []
+    for _ in range(n_frames):
+        poses.append(pose)
+        frames.append(make_frame(scene, cam, pose, rng, **kw))
+        pose = compose(pose, step)
+    return cam, poses, frames

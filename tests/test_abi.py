@@ -42,3 +42,11 @@ def test_pose_maps_host_functions():
         np.testing.assert_allclose(R, Rotation.from_rotvec(xi[3:]).as_matrix(), atol=1e-14)
         np.testing.assert_array_equal(t, xi[:3])
         np.testing.assert_allclose(rgbid.rgbid_pose_log(R, t), xi, atol=1e-12)
+
+
+def test_tracker_default_params():
+    from paper_1807_08271_amd import rgbid
+    p = rgbid.rgbid_tracker_default_params()
+    assert p.align.levels == 4 and p.align.weight == rgbid.RGBID_W_HUBER
+    assert p.rf_threshold == 0.8 and p.kf_threshold == 0.7
+    assert p.covis_level == 2 and p.tol_sigmas == 3.0 and p.buffer == 8 and p.covariance == 1

@@ -1,0 +1,101 @@
+"""Tracking front-end (sec. 7.1, sec. 7.2) on the GPU against the front-end
+oracle: a constant-velocity 320x240 sequence that forces several reference
+frame and keyframe switches.
+
+Per frame, while every earlier switch decision agreed: the same decisions
+(unless the oracle's ratio lies within rounding of the threshold, after which
+the two histories may legitimately part and the comparison stops), poses
+within 1e-5 rad / m per alignment in the chain, covisibility ratios within a
+few pixels, covariances within 5e-3 of their scale, fused-pixel counts within
+a few threshold flips.  The final keyframe is compared pixel by pixel."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import frontend as fe
+from _parity import rot_err, upload
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 2e-3   # ratios this close to a threshold may decide either way
+
+
+def _near(x, thr):
+    return abs(x - thr) <= MARGIN
+
+
+def test_tracker_matches_oracle(ctx):
+    from paper_1807_08271_amd import rgbid as rg
+    import torch
+    cam, poses, frames = synth.track_sequence(12, 3.0, 0.04, seed=4, cam=synth.camera_320())
+    align = rg.rgbid_default_params(levels=3, iters=[8, 8, 8])
+    tp = rg.rgbid_tracker_default_params(align=align, rf_threshold=0.85, kf_threshold=0.7,
+                                         covis_level=1, buffer=4, covariance=1)
+    trk = rg.rgbid_tracker_create(ctx, cam, 3, rg.RGBID_F32, tp)
+    op = fe.TrackerParams(align=oracle.Params(levels=3, iters=[8, 8, 8], storage="f32"),
+                          rf_threshold=0.85, kf_threshold=0.7, covis_level=1, buffer=4,
+                          covariance=True)
+    otrk = fe.Tracker(cam, op)
+    chain = 1            # alignments composed into T_w_k so far
+    compared = dict(rf=0, kf=0, frames=0)
+    agreed = True
+    for k, f in enumerate(frames):
+        I, W = upload(f.I, f.W)
+        g = rg.rgbid_track(ctx, trk, I, W)
+        o = otrk.track(f.I, f.W)
+        if k == 0:
+            continue
+        assert g["stats"]["status"] == 0 and o["status"] == 0
+        # alignment against the same reference from the same guess
+        assert rot_err(g["T_rf_k"][0], o["T_rf_k"][0]) <= 1e-5, k
+        assert np.linalg.norm(g["T_rf_k"][1] - o["T_rf_k"][1]) <= 1e-5, k
+        assert rot_err(g["T_w_k"][0], o["T_w_k"][0]) <= 1e-5 * chain, k
+        assert np.linalg.norm(g["T_w_k"][1] - o["T_w_k"][1]) <= 1e-5 * chain, k
+        assert abs(g["covis_rf"] - o["covis_rf"]) <= 1e-3, (k, g["covis_rf"], o["covis_rf"])
+        assert abs(g["covis_kf"] - o["covis_kf"]) <= 1e-3, (k, g["covis_kf"], o["covis_kf"])
+        assert g["cov_status"] == 0
+        for key in ("S_rf_k", "S_odo"):
+            d = np.sqrt(np.diag(o[key]))
+            assert np.all(np.abs(g[key] - o[key]) <= 5e-3 * np.outer(d, d)), (k, key)
+        n_ref = max(o["n_fused"], 1)
+        assert abs(g["n_fused"] - o["n_fused"]) <= 20 + 1e-3 * n_ref, (k, g["n_fused"], o["n_fused"])
+        assert abs(g["n_fused_buffer"] - o["n_fused_buffer"]) <= 20 + 1e-3 * max(o["n_fused_buffer"], 1)
+        compared["frames"] += 1
+        near = _near(o["covis_kf"], op.kf_threshold) or _near(o["covis_rf"], op.rf_threshold)
+        if not near:
+            assert g["kf_switched"] == o["kf_switched"], k
+            assert g["rf_switched"] == o["rf_switched"], k
+        if g["kf_switched"] != o["kf_switched"] or g["rf_switched"] != o["rf_switched"]:
+            agreed = False
+            break
+        compared["rf"] += int(o["rf_switched"])
+        compared["kf"] += int(o["kf_switched"])
+        if o["rf_switched"]:
+            chain += 1
+    assert compared["frames"] >= 6 and compared["rf"] >= 1 and compared["kf"] >= 1, compared
+    if agreed:
+        h, w = frames[0].W.shape
+        Wg, Cg = rg.rgbid_keyframe_read(ctx, rg.rgbid_tracker_keyframe(trk), (h, w))
+        torch.cuda.synchronize()
+        Wg, Cg = Wg.cpu().numpy(), Cg.cpu().numpy()
+        valid = otrk.Wkf > 0
+        assert np.array_equal(valid, Wg > 0)
+        rel = np.abs(Wg[valid] - otrk.Wkf[valid]) / otrk.Wkf[valid]
+        assert np.median(rel) <= 1e-6 and np.mean(rel > 1e-4) <= 0.01, (np.median(rel), rel.max())
+        assert np.mean(np.abs(Cg[valid] - otrk.Ckf[valid]) > 1e-3 * otrk.Ckf[valid]) <= 0.01
+    rg.rgbid_tracker_free(trk)
+
+
+def test_tracker_arguments(ctx):
+    from paper_1807_08271_amd import rgbid as rg
+    cam = synth.camera_160()
+    tp = rg.rgbid_tracker_default_params(covis_level=5)
+    with pytest.raises(rg.RgbidError):
+        rg.rgbid_tracker_create(ctx, cam, 4, rg.RGBID_F32, tp)
+    tp = rg.rgbid_tracker_default_params(buffer=65)
+    with pytest.raises(rg.RgbidError):
+        rg.rgbid_tracker_create(ctx, cam, 4, rg.RGBID_F32, tp)
+    tp = rg.rgbid_tracker_default_params()
+    with pytest.raises(rg.RgbidError):
+        rg.rgbid_tracker_create(ctx, cam, 3, rg.RGBID_F32, tp)   # fewer levels than align
