@@ -295,6 +295,63 @@ rgbid_status rgbid_keyframe_read(rgbid_ctx* ctx, const rgbid_kf* kf, float* W_ou
 
 void rgbid_keyframe_free(rgbid_kf* kf);
 
+/* ------------------------------------------------------------ sensor input path */
+
+/* A camera with Brown distortion (sec. 4.1, eq. proj_dist): k = (k1, k2, k3,
+   k4, k5), radial k1, k2, k5 and tangential k3, k4; cam is the pinhole part. */
+typedef struct {
+    rgbid_camera cam;
+    double k[5];
+} rgbid_lens;
+
+/* Calibration of an RGB-D sensor (sec. 4.1, 4.2).  Raw depth Z_m (m) is
+   corrected as W_d(p) = beta1 / Z_m(p - p0) + beta0 (p0 = (p0x, p0y),
+   (4, 4) for the sensor of the paper), then, if spatial != 0,
+   W_u(p) = D1(p) W_d(p) + D0(p) with D_i(p) = q_i0 + q_i1 r^2 + q_i2 r^4 +
+   q_i3 r^6 + q_i4 m_x + q_i5 m_y + q_i6 m_x m_y + q_i7 m_x^2 m_y +
+   q_i8 m_x m_y^2, m = K_depth^-1 p (all nine listed terms are used).  T_dc is
+   the pose of the colour camera in the depth camera (T_D^C). */
+typedef struct {
+    rgbid_lens color, depth;
+    double beta0, beta1;
+    int p0x, p0y;
+    int spatial;
+    double q0[9], q1[9];
+    rgbid_pose T_dc;
+} rgbid_sensor;
+
+/* Undistortion by inverse warping (sec. 5.1): dst(p) = src(K h(K^-1 p)),
+   bilinear, on the lens's own grid (dst dense, width x height, caller-owned
+   device memory).  is_depth: src is an inverse-depth map, a sample needs
+   four valid taps and holes are 0.  Unmapped pixels are 0.  Does not
+   synchronise.  Errors: E_ARG. */
+rgbid_status rgbid_undistort(rgbid_ctx* ctx, const rgbid_lens* lens, const float* src,
+                             size_t pitch_elems, int is_depth, float* dst);
+
+/* Forward registration (sec. 5.2) of the undistorted inverse-depth map W_A
+   of camera A into camera B with T = T_A^B (X_A = R X_B + t): first the
+   translation alone, each pixel's footprint square (side 1/(1 - W t_z),
+   centred on the translated position) written to the intermediate frame
+   with an atomic maximum of the inverse depth (pixels whose centres lie in
+   the half-open square); then the rotation as an inverse warp with nearest
+   neighbour, W_B(p) = W_Bt(p_t) (R K_B^-1 p)_z.  WB: dense B-sized
+   caller-owned device buffer, holes 0.  Does not synchronise.  Errors:
+   E_ARG, E_NOMEM. */
+rgbid_status rgbid_register(rgbid_ctx* ctx, const rgbid_camera* camA, const float* WA,
+                            size_t pitch_elems, const rgbid_camera* camB, const rgbid_pose* T,
+                            float* WB);
+
+/* Input path of one RGB-D frame: depth correction of Z_raw on the depth
+   grid, undistortion through the depth lens, registration into the colour
+   camera with T_dc, and undistortion of the colour image I_raw (grey
+   levels, colour grid).  I_out, W_out: dense colour-sized caller-owned
+   device buffers, ready for rgbid_pyramid.  The corrected and undistorted
+   depth maps are formed inside the registration kernel and never stored.
+   Does not synchronise.  Errors: E_ARG, E_NOMEM. */
+rgbid_status rgbid_preprocess(rgbid_ctx* ctx, const rgbid_sensor* sensor, const float* I_raw,
+                              size_t pitch_I, const float* Z_raw, size_t pitch_Z, float* I_out,
+                              float* W_out);
+
 /* ------------------------------------------------------------ tracking front-end */
 
 /* Frame-to-reference tracking of an RGB-D sequence with keyframe fusion

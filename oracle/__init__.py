@@ -146,6 +146,14 @@ def lib():
                                     C.POINTER(_Stats)]
         L.or_fuse.restype = C.c_longlong
         L.or_fuse.argtypes = [cp, dp, dp, dp, dp, dp, C.c_double]
+        L.or_distort.argtypes = [dp, C.c_double, C.c_double, dp, dp]
+        L.or_undistort.argtypes = [cp, dp, dp, C.c_int, dp]
+        L.or_depth_correct.argtypes = [cp, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                       dp, dp, dp]
+        L.or_register_translate.argtypes = [cp, dp, dp, dp]
+        L.or_register_rotate.argtypes = [cp, dp, cp, dp, dp]
+        L.or_preprocess.argtypes = [cp, dp, cp, dp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                    C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -414,3 +422,79 @@ def covariance(cam0, IA0, WA0, IB0, WB0, R, t, params: Params = None, **bf):
                              float(b["sigma_s"]), float(b["sigma_I"]), float(b["rel_W"]), _p(S),
                              C.byref(st))
     return (S.reshape(6, 6) if rc == 0 else None), _stats(st)
+
+
+# --------------------------------------------------------------------------
+# sensor input path (sec. 4.1, 4.2, 5.1, 5.2)
+
+
+@dataclass
+class Sensor:
+    """Calibration of an RGB-D sensor: colour and depth pinhole cameras with
+    Brown distortion k = (k1..k5), depth correction (beta0, beta1, p0 and the
+    nine-term polynomials q0, q1 of D0, D1), and T_D^C, the pose of the colour
+    camera in the depth camera."""
+    color: tuple
+    depth: tuple
+    k_color: tuple = (0.0,) * 5
+    k_depth: tuple = (0.0,) * 5
+    beta0: float = 0.0
+    beta1: float = 1.0
+    p0: tuple = (4, 4)
+    spatial: bool = False
+    q0: tuple = (0.0,) * 9
+    q1: tuple = (1.0,) + (0.0,) * 8
+    R_dc: np.ndarray = field(default_factory=lambda: np.eye(3))
+    t_dc: np.ndarray = field(default_factory=lambda: np.zeros(3))
+
+
+def distort(k, x, y):
+    xd, yd = C.c_double(), C.c_double()
+    lib().or_distort(_p(_d(k)), float(x), float(y), C.byref(xd), C.byref(yd))
+    return xd.value, yd.value
+
+
+def undistort(cam, k, src, is_depth):
+    c = _cam(cam)
+    out = np.zeros((c.h, c.w))
+    lib().or_undistort(C.byref(c), _p(_d(k)), _p(_d(src)), int(is_depth), _p(out))
+    return out
+
+
+def depth_correct(cam, Z, beta0=0.0, beta1=1.0, p0=(4, 4), spatial=False, q0=(0.0,) * 9,
+                  q1=(1.0,) + (0.0,) * 8):
+    c = _cam(cam)
+    out = np.zeros((c.h, c.w))
+    lib().or_depth_correct(C.byref(c), _p(_d(Z)), float(beta0), float(beta1), int(p0[0]),
+                           int(p0[1]), int(spatial), _p(_d(q0)), _p(_d(q1)), _p(out))
+    return out
+
+
+def register_translate(camA, WA, t):
+    c = _cam(camA)
+    out = np.zeros((c.h, c.w))
+    lib().or_register_translate(C.byref(c), _p(_d(WA)), _p(_d(t)), _p(out))
+    return out
+
+
+def register_rotate(camA, WBt, camB, R):
+    ca, cb = _cam(camA), _cam(camB)
+    out = np.zeros((cb.h, cb.w))
+    lib().or_register_rotate(C.byref(ca), _p(_d(WBt)), C.byref(cb), _p(_d(R).reshape(9)), _p(out))
+    return out
+
+
+def register(camA, WA, camB, R, t):
+    """Forward registration of W_A into camera B with T_A^B = (R, t)."""
+    return register_rotate(camA, register_translate(camA, WA, t), camB, R)
+
+
+def preprocess(s: Sensor, I_raw, Z_raw):
+    cc, cd = _cam(s.color), _cam(s.depth)
+    Io = np.zeros((cc.h, cc.w))
+    Wo = np.zeros((cc.h, cc.w))
+    lib().or_preprocess(C.byref(cc), _p(_d(s.k_color)), C.byref(cd), _p(_d(s.k_depth)),
+                        float(s.beta0), float(s.beta1), int(s.p0[0]), int(s.p0[1]),
+                        int(s.spatial), _p(_d(s.q0)), _p(_d(s.q1)), _p(_d(s.R_dc).reshape(9)),
+                        _p(_d(s.t_dc)), _p(_d(I_raw)), _p(_d(Z_raw)), _p(Io), _p(Wo))
+    return Io, Wo

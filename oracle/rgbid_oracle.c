@@ -873,3 +873,160 @@ int or_covariance(const or_cam* c0, int levels, const double* IA0, const double*
     }
     return OR_OK;
 }
+
+/* ---------------------------------------------------------------- sensor input path */
+
+/* Brown distortion h of eq:proj_dist on the normalised plane, k = (k1..k5):
+     r^2 = x^2 + y^2,  rad = k1 r^2 + k2 r^4 + k5 r^6,
+     x_d = (1 + rad) x + 2 k3 x y + k4 (r^2 + 2 x^2),
+     y_d = (1 + rad) y + 2 k4 x y + k3 (r^2 + 2 y^2),
+   and the third coordinate stays 1. */
+void or_distort(const double k[5], double x, double y, double* xd, double* yd)
+{
+    const double r2 = x * x + y * y;
+    const double rad = k[0] * r2 + k[1] * r2 * r2 + k[4] * r2 * r2 * r2;
+    *xd = (1.0 + rad) * x + 2.0 * k[2] * x * y + k[3] * (r2 + 2.0 * x * x);
+    *yd = (1.0 + rad) * y + 2.0 * k[3] * x * y + k[2] * (r2 + 2.0 * y * y);
+}
+
+/* Inverse warping for undistortion (sec. 5.1): dst(p) = src(K h(K^-1 p)) by
+   bilinear interpolation.  Reading: the bounds rule and clamped taps of the
+   alignment's sampler; a depth image (is_depth) needs four valid taps, and an
+   unmapped pixel is 0 (a hole for depth). */
+void or_undistort(const or_cam* c, const double k[5], const double* src, int is_depth,
+                  double* dst)
+{
+    for (int v = 0; v < c->h; ++v)
+        for (int u = 0; u < c->w; ++u) {
+            double xd, yd, val = 0.0;
+            const double mx = (u - c->cx) / c->fx, my = (v - c->cy) / c->fy;
+            or_distort(k, mx, my, &xd, &yd);
+            /* K h(m) = p + f (h(m) - m): exact at zero distortion */
+            const double x = u + c->fx * (xd - mx), y = v + c->fy * (yd - my);
+            if (!bilinear(src, c->w, c->h, x, y, is_depth, &val)) val = 0.0;
+            if (is_depth && !valid_w(val)) val = 0.0;
+            dst[v * c->w + u] = val;
+        }
+}
+
+/* Spatially varying factor / offset of eq:depth_spatial_correction at pixel
+   (u, v): a polynomial in m = K^-1 p with nine coefficients q0..q8 (the text
+   announces eight parameters but lists nine terms; all nine are used). */
+static double depth_poly(const double q[9], double mx, double my)
+{
+    const double r2 = mx * mx + my * my;
+    return q[0] + q[1] * r2 + q[2] * r2 * r2 + q[3] * r2 * r2 * r2 + q[4] * mx + q[5] * my +
+           q[6] * mx * my + q[7] * mx * mx * my + q[8] * mx * my * my;
+}
+
+/* Depth correction of sec. 4.1 on the raw depth image Z_m (metres):
+     W_d(p) = beta1 W_m(p - p0) + beta0,  W_m = 1 / Z_m   (eq:depth_linear_correction)
+     W_u(p) = D1(p) W_d(p) + D0(p)                        (eq:depth_spatial_correction)
+   Holes (Z_m <= 0 or non-finite, p - p0 outside the image, W_u <= 0) are 0. */
+void or_depth_correct(const or_cam* c, const double* Zm, double beta0, double beta1, int p0x,
+                      int p0y, int spatial, const double q0[9], const double q1[9], double* Wu)
+{
+    for (int v = 0; v < c->h; ++v)
+        for (int u = 0; u < c->w; ++u) {
+            const int us = u - p0x, vs = v - p0y;
+            double out = 0.0;
+            if (us >= 0 && us < c->w && vs >= 0 && vs < c->h) {
+                const double Z = Zm[vs * c->w + us];
+                if (Z > 0.0 && isfinite(Z)) {
+                    double W = beta1 * (1.0 / Z) + beta0;
+                    if (spatial) {
+                        const double mx = (u - c->cx) / c->fx, my = (v - c->cy) / c->fy;
+                        W = depth_poly(q1, mx, my) * W + depth_poly(q0, mx, my);
+                    }
+                    out = valid_w(W) ? W : 0.0;
+                }
+            }
+            Wu[v * c->w + u] = out;
+        }
+}
+
+/* Forward registration, step 1 (sec. 5.2, eq:register_trans): W_A of camera
+   cA is moved by the translation t = t_A^B alone into the intermediate frame
+   B_t (camera cA, same size).  With t~ = K_A t and den = 1 - W t~_z (> 0),
+     w_t = W / den,  p_t = (p - W t~) / den,
+   and the pixel's footprint, a square of side 1/den centred on p_t, is
+   written to every pixel of B_t whose centre lies inside it (half-open on the
+   high side, so that the identity maps each pixel to itself), keeping the
+   greatest inverse depth.  Unwritten pixels are 0. */
+void or_register_translate(const or_cam* cA, const double* WA, const double t[3], double* WBt)
+{
+    const int n = cA->w * cA->h;
+    for (int i = 0; i < n; ++i) WBt[i] = 0.0;
+    const double tx = cA->fx * t[0] + cA->cx * t[2];
+    const double ty = cA->fy * t[1] + cA->cy * t[2];
+    const double tz = t[2];
+    for (int v = 0; v < cA->h; ++v)
+        for (int u = 0; u < cA->w; ++u) {
+            const double W = WA[v * cA->w + u];
+            if (!valid_w(W)) continue;
+            const double den = 1.0 - W * tz;
+            if (!(den > 0.0)) continue;
+            const double wt = W / den;
+            const double x = (u - W * tx) / den, y = (v - W * ty) / den;
+            const double half = 0.5 / den;
+            const double qx0 = ceil(x - half), qx1 = ceil(x + half) - 1.0;
+            const double qy0 = ceil(y - half), qy1 = ceil(y + half) - 1.0;
+            for (double qy = fmax(qy0, 0.0); qy <= fmin(qy1, cA->h - 1.0); qy += 1.0)
+                for (double qx = fmax(qx0, 0.0); qx <= fmin(qx1, cA->w - 1.0); qx += 1.0) {
+                    double* d = &WBt[(int)qy * cA->w + (int)qx];
+                    if (wt > *d) *d = wt;
+                }
+        }
+}
+
+/* Forward registration, step 2 (sec. 5.2): the remaining rotation as an
+   inverse warp into camera cB.  With R~_AB = K_A R K_B^-1 (R = R_A^B),
+   d = R~_AB p, p_t = (d_x, d_y) / d_z, W_Bt taken at the nearest pixel
+   (floor(x + 0.5)), W_B(p) = W_Bt(p_t) d_z.  Holes: d_z <= 0, p_t outside
+   the image, or a hole of W_Bt. */
+void or_register_rotate(const or_cam* cA, const double* WBt, const or_cam* cB, const double R[9],
+                        double* WB)
+{
+    for (int v = 0; v < cB->h; ++v)
+        for (int u = 0; u < cB->w; ++u) {
+            const double m[3] = {(u - cB->cx) / cB->fx, (v - cB->cy) / cB->fy, 1.0};
+            double r[3];
+            for (int i = 0; i < 3; ++i) r[i] = R[3 * i] * m[0] + R[3 * i + 1] * m[1] + R[3 * i + 2] * m[2];
+            double out = 0.0;
+            if (r[2] > 0.0) {
+                const double x = (cA->fx * r[0] + cA->cx * r[2]) / r[2];
+                const double y = (cA->fy * r[1] + cA->cy * r[2]) / r[2];
+                const double qx = floor(x + 0.5), qy = floor(y + 0.5);
+                if (qx >= 0 && qx <= cA->w - 1 && qy >= 0 && qy <= cA->h - 1) {
+                    const double wt = WBt[(int)qy * cA->w + (int)qx];
+                    if (valid_w(wt)) out = wt * r[2];
+                }
+            }
+            WB[v * cB->w + u] = valid_w(out) ? out : 0.0;
+        }
+}
+
+/* Input path of one RGB-D frame (sec. 4.1, 4.2, 5.1, 5.2) in the paper's
+   order: depth correction and spatial correction on the raw depth grid,
+   undistortion of the corrected inverse depth (depth lens) and of the
+   intensity (colour lens), then forward registration of the inverse depth
+   into the colour camera with T_D^C (pose of the colour camera in the depth
+   camera).  Outputs are on the colour camera's grid. */
+void or_preprocess(const or_cam* cc, const double kc[5], const or_cam* cd, const double kd[5],
+                   double beta0, double beta1, int p0x, int p0y, int spatial, const double q0[9],
+                   const double q1[9], const double R_dc[9], const double t_dc[3],
+                   const double* I_raw, const double* Z_raw, double* I_out, double* W_out)
+{
+    const size_t nd = (size_t)cd->w * cd->h;
+    double* Wu = malloc(nd * sizeof(double));
+    double* Wund = malloc(nd * sizeof(double));
+    double* Wt = malloc(nd * sizeof(double));
+    or_depth_correct(cd, Z_raw, beta0, beta1, p0x, p0y, spatial, q0, q1, Wu);
+    or_undistort(cd, kd, Wu, 1, Wund);
+    or_register_translate(cd, Wund, t_dc, Wt);
+    or_register_rotate(cd, Wt, cc, R_dc, W_out);
+    or_undistort(cc, kc, I_raw, 0, I_out);
+    free(Wu);
+    free(Wund);
+    free(Wt);
+}

@@ -17,7 +17,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librgbid.so")
 ARCH = os.environ.get("RGBID_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "pyramid.hip", "align.hip", "fuse.hip", "cnn.hip"]
+SOURCES = ["api.hip", "pyramid.hip", "align.hip", "fuse.hip", "cnn.hip", "sensor.hip"]
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

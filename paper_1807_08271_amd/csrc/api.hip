@@ -67,7 +67,7 @@ struct rgbid_ctx {
     hipStream_t stream = nullptr;    // work stream (the caller's)
     hipStream_t cap = nullptr;       // private stream for graph capture
     std::string err;
-    DevBuf pairs, states, tables, partials, warped, sample, frames, covis, cov_img;
+    DevBuf pairs, states, tables, partials, warped, sample, frames, covis, cov_img, reg;
     rgbid_pyr* cov_pyr = nullptr;    // filtered reference of the covariance iteration
     void* h_stage = nullptr;         // pinned upload staging
     size_t h_stage_bytes = 0;
@@ -681,7 +681,7 @@ void rgbid_destroy(rgbid_ctx* c)
     if (c->cov_pyr) rgbid_pyramid_free(c->cov_pyr);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
-                      &c->frames, &c->covis, &c->cov_img})
+                      &c->frames, &c->covis, &c->cov_img, &c->reg})
         if (b->p) hipFree(b->p);
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->h_down) hipHostFree(c->h_down);
@@ -1465,6 +1465,120 @@ rgbid_status rgbid_warmstart_train_step(rgbid_ctx* c, rgbid_net* net, int n, con
     net->step += 1;
     HIPCHK(c, cnn_adamw(c->stream, net->buf, (float)lr, (float)wd, net->step));
     if (loss && (st = net_loss(c, net, n, loss)) != RGBID_OK) return st;
+    return RGBID_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ sensor input path
+
+namespace {
+
+bool camera_ok(const rgbid_camera* c)
+{
+    return c && c->width > 0 && c->height > 0 && (long long)c->width * c->height < (1ll << 24) &&
+           c->fx > 0 && c->fy > 0 && std::isfinite(c->cx) && std::isfinite(c->cy);
+}
+
+LensF lens_f(const rgbid_camera& c, const double* k)
+{
+    LensF L;
+    L.w = c.width;
+    L.h = c.height;
+    L.fx = (float)c.fx;
+    L.fy = (float)c.fy;
+    L.cx = (float)c.cx;
+    L.cy = (float)c.cy;
+    for (int i = 0; i < 5; ++i) L.k[i] = k ? (float)k[i] : 0.0f;
+    return L;
+}
+
+void reg_pose(RegisterArgs& a, const rgbid_camera& camA, const rgbid_pose& T)
+{
+    a.tx = (float)(camA.fx * T.t[0] + camA.cx * T.t[2]);
+    a.ty = (float)(camA.fy * T.t[1] + camA.cy * T.t[2]);
+    a.tz = (float)T.t[2];
+    for (int i = 0; i < 9; ++i) a.R.m[i] = (float)T.R[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+rgbid_status rgbid_undistort(rgbid_ctx* c, const rgbid_lens* lens, const float* src,
+                             size_t pitch_elems, int is_depth, float* dst)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!lens || !src || !dst) return set_err(c, RGBID_E_ARG, "NULL argument");
+    if (!camera_ok(&lens->cam)) return set_err(c, RGBID_E_ARG, "bad camera");
+    if (pitch_elems < (size_t)lens->cam.width) return set_err(c, RGBID_E_ARG, "pitch < width");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_undistort(c->stream, src, (long long)pitch_elems, lens_f(lens->cam, lens->k),
+                               is_depth ? 1 : 0, dst));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_register(rgbid_ctx* c, const rgbid_camera* camA, const float* WA,
+                            size_t pitch_elems, const rgbid_camera* camB, const rgbid_pose* T,
+                            float* WB)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!WA || !WB || !T) return set_err(c, RGBID_E_ARG, "NULL argument");
+    if (!camera_ok(camA) || !camera_ok(camB)) return set_err(c, RGBID_E_ARG, "bad camera");
+    if (pitch_elems < (size_t)camA->width) return set_err(c, RGBID_E_ARG, "pitch < width");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    if ((st = ensure(c, c->reg, (size_t)camA->width * camA->height * 4)) != RGBID_OK) return st;
+    RegisterArgs a{};
+    a.src = WA;
+    a.pitch = (long long)pitch_elems;
+    a.raw = 0;
+    a.A = lens_f(*camA, nullptr);
+    a.B = lens_f(*camB, nullptr);
+    reg_pose(a, *camA, *T);
+    a.Wt = static_cast<unsigned*>(c->reg.p);
+    a.Wout = WB;
+    HIPCHK(c, launch_register(c->stream, a));
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_preprocess(rgbid_ctx* c, const rgbid_sensor* S, const float* I_raw,
+                              size_t pitch_I, const float* Z_raw, size_t pitch_Z, float* I_out,
+                              float* W_out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!S || !I_raw || !Z_raw || !I_out || !W_out) return set_err(c, RGBID_E_ARG, "NULL argument");
+    if (!camera_ok(&S->color.cam) || !camera_ok(&S->depth.cam)) return set_err(c, RGBID_E_ARG, "bad camera");
+    if (pitch_I < (size_t)S->color.cam.width || pitch_Z < (size_t)S->depth.cam.width)
+        return set_err(c, RGBID_E_ARG, "pitch < width");
+    if (!std::isfinite(S->beta0) || !std::isfinite(S->beta1))
+        return set_err(c, RGBID_E_ARG, "non-finite depth correction");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    const rgbid_camera& cd = S->depth.cam;
+    if ((st = ensure(c, c->reg, (size_t)cd.width * cd.height * 4)) != RGBID_OK) return st;
+    RegisterArgs a{};
+    a.src = Z_raw;
+    a.pitch = (long long)pitch_Z;
+    a.raw = 1;
+    a.A = lens_f(cd, S->depth.k);
+    a.B = lens_f(S->color.cam, S->color.k);
+    a.D.beta0 = (float)S->beta0;
+    a.D.beta1 = (float)S->beta1;
+    a.D.p0x = S->p0x;
+    a.D.p0y = S->p0y;
+    a.D.spatial = S->spatial ? 1 : 0;
+    for (int i = 0; i < 9; ++i) {
+        a.D.q0[i] = (float)S->q0[i];
+        a.D.q1[i] = (float)S->q1[i];
+    }
+    reg_pose(a, cd, S->T_dc);
+    a.Wt = static_cast<unsigned*>(c->reg.p);
+    a.Wout = W_out;
+    a.Iraw = I_raw;
+    a.pitchI = (long long)pitch_I;
+    a.Iout = I_out;
+    HIPCHK(c, launch_register(c->stream, a));
     return RGBID_OK;
 }
 

@@ -154,6 +154,49 @@ hipError_t launch_bilateral(hipStream_t s, const void* iw, int f16, int w, int h
 hipError_t launch_copy_valid(hipStream_t s, const float* src, long long pitch, int w, int h,
                              float* dst);
 
+// ---------------------------------------------------------------- sensor input path
+
+// A lens on the device: pinhole part and Brown distortion k1..k5.
+struct LensF {
+    int w, h;
+    float fx, fy, cx, cy;
+    float k[5];
+};
+
+// Depth correction: beta0, beta1, the correlation-window shift and the two
+// nine-term polynomials (q0: offset D0, q1: factor D1).
+struct DepthCorrF {
+    float beta0, beta1;
+    int p0x, p0y;
+    int spatial;
+    float q0[9], q1[9];
+};
+
+struct RotF {
+    float m[9];
+};
+
+// Forward registration of camera A's inverse depth into camera B with
+// T_A^B; raw = 1 reads raw depth and applies the correction and A's lens.
+struct RegisterArgs {
+    const float* src;
+    long long pitch;
+    int raw;
+    LensF A, B;
+    DepthCorrF D;
+    float tx, ty, tz;       // K_A t
+    RotF R;                 // R_A^B
+    unsigned* Wt;           // intermediate frame B_t (A's grid), as float bits
+    float* Wout;            // B's grid, dense
+    const float* Iraw;      // optional colour image to undistort on B's grid
+    long long pitchI;
+    float* Iout;
+};
+
+hipError_t launch_undistort(hipStream_t s, const float* src, long long pitch, const LensF& L,
+                            int is_depth, float* dst);
+hipError_t launch_register(hipStream_t s, const RegisterArgs& a);
+
 // ---------------------------------------------------------------- warm start
 
 constexpr int kCnnH = 60, kCnnW = 80;

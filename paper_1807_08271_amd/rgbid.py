@@ -76,6 +76,16 @@ class rgbid_align_stats(C.Structure):
                     iters_done=list(self.iters_done[:]), status=self.status)
 
 
+class rgbid_lens(C.Structure):
+    _fields_ = [("cam", rgbid_camera), ("k", C.c_double * 5)]
+
+
+class rgbid_sensor(C.Structure):
+    _fields_ = [("color", rgbid_lens), ("depth", rgbid_lens), ("beta0", C.c_double),
+                ("beta1", C.c_double), ("p0x", C.c_int), ("p0y", C.c_int), ("spatial", C.c_int),
+                ("q0", C.c_double * 9), ("q1", C.c_double * 9), ("T_dc", rgbid_pose)]
+
+
 class rgbid_tracker_params(C.Structure):
     _fields_ = [("align", rgbid_align_params), ("rf_threshold", C.c_double),
                 ("kf_threshold", C.c_double), ("covis_level", C.c_int),
@@ -155,6 +165,11 @@ _SIGS = {
     "rgbid_covariance": (C.c_int, [_P, _P, _P, C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
                                    C.POINTER(rgbid_bilateral), C.POINTER(C.c_double),
                                    C.POINTER(rgbid_align_stats)]),
+    "rgbid_undistort": (C.c_int, [_P, C.POINTER(rgbid_lens), _P, C.c_size_t, C.c_int, _P]),
+    "rgbid_register": (C.c_int, [_P, C.POINTER(rgbid_camera), _P, C.c_size_t,
+                                 C.POINTER(rgbid_camera), C.POINTER(rgbid_pose), _P]),
+    "rgbid_preprocess": (C.c_int, [_P, C.POINTER(rgbid_sensor), _P, C.c_size_t, _P, C.c_size_t,
+                                   _P, _P]),
     "rgbid_tracker_default_params": (None, [C.POINTER(rgbid_tracker_params)]),
     "rgbid_tracker_create": (C.c_int, [_P, C.POINTER(rgbid_camera), C.c_int, C.c_int,
                                        C.POINTER(rgbid_tracker_params), C.POINTER(_P)]),
@@ -595,3 +610,64 @@ def rgbid_tracker_keyframe(trk):
 
 def rgbid_tracker_free(trk):
     lib().rgbid_tracker_free(trk)
+
+
+# ----------------------------------------------------------------- sensor input path
+
+
+def make_lens(cam, k=None) -> rgbid_lens:
+    L = rgbid_lens()
+    L.cam = _cam(cam)
+    for i, v in enumerate(k if k is not None else [0.0] * 5):
+        L.k[i] = float(v)
+    return L
+
+
+def make_sensor(color, depth, k_color=None, k_depth=None, beta0=0.0, beta1=1.0, p0=(4, 4),
+                spatial=False, q0=None, q1=None, R_dc=None, t_dc=None) -> rgbid_sensor:
+    S = rgbid_sensor()
+    S.color = make_lens(color, k_color)
+    S.depth = make_lens(depth, k_depth)
+    S.beta0, S.beta1 = float(beta0), float(beta1)
+    S.p0x, S.p0y = int(p0[0]), int(p0[1])
+    S.spatial = int(bool(spatial))
+    q0 = q0 if q0 is not None else [0.0] * 9
+    q1 = q1 if q1 is not None else [1.0] + [0.0] * 8
+    for i in range(9):
+        S.q0[i], S.q1[i] = float(q0[i]), float(q1[i])
+    S.T_dc = make_pose(R_dc, t_dc)
+    return S
+
+
+def _out(h, w, device=None):
+    import torch
+    return torch.empty((h, w), dtype=torch.float32, device=device or "cuda")
+
+
+def rgbid_undistort(ctx, lens: rgbid_lens, src, is_depth: bool, out=None):
+    p, pitch = _img(src)
+    out = out if out is not None else _out(lens.cam.height, lens.cam.width, src.device)
+    _check(ctx, lib().rgbid_undistort(ctx, C.byref(lens), p, pitch, int(is_depth),
+                                      C.c_void_p(out.data_ptr())))
+    return out
+
+
+def rgbid_register(ctx, camA, WA, camB, T, out=None):
+    p, pitch = _img(WA)
+    ca, cb = _cam(camA), _cam(camB)
+    out = out if out is not None else _out(cb.height, cb.width, WA.device)
+    pose = make_pose(*T)
+    _check(ctx, lib().rgbid_register(ctx, C.byref(ca), p, pitch, C.byref(cb), C.byref(pose),
+                                     C.c_void_p(out.data_ptr())))
+    return out
+
+
+def rgbid_preprocess(ctx, sensor: rgbid_sensor, I_raw, Z_raw, I_out=None, W_out=None):
+    pI, pitchI = _img(I_raw)
+    pZ, pitchZ = _img(Z_raw)
+    h, w = sensor.color.cam.height, sensor.color.cam.width
+    I_out = I_out if I_out is not None else _out(h, w, I_raw.device)
+    W_out = W_out if W_out is not None else _out(h, w, I_raw.device)
+    _check(ctx, lib().rgbid_preprocess(ctx, C.byref(sensor), pI, pitchI, pZ, pitchZ,
+                                       C.c_void_p(I_out.data_ptr()), C.c_void_p(W_out.data_ptr())))
+    return I_out, W_out

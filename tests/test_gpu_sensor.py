@@ -1,0 +1,133 @@
+"""Sensor input path on the GPU against the oracle (sec. 4.1, 4.2, 5.1, 5.2):
+undistortion of intensity and inverse depth, forward registration, and the
+whole fused path from raw depth to a registered inverse-depth map, at
+640x480 on rendered room frames.
+
+The kernels decide sample bounds, tap validity, footprint coverage and the
+nearest neighbour in FP32; the oracle in FP64.  Where such a decision flips
+the value may legitimately differ by the local gradient, so each comparison
+states the share of pixels that must agree to the FP32 tolerance (intensity
+5e-3 grey levels, inverse depth 1e-5 relative) and bounds the rest."""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+K_COLOR = [0.12, -0.25, 0.0015, -0.001, 0.1]
+K_DEPTH = [-0.08, 0.15, -0.001, 0.0008, -0.05]
+
+
+def _frame(seed=3):
+    cam = synth.camera_640()
+    scene = synth.room_scene(7000 + seed)
+    pose = (Rotation.from_euler("x", -10, degrees=True).as_matrix(), np.zeros(3))
+    Z, I = synth.render(scene, cam, pose, ss=1)
+    Z = np.where(np.isfinite(Z) & (Z > 0.5) & (Z < 5.0), Z, 0.0)
+    return cam, I, Z
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _agree(got, want, rel=None, abs_=None, share=0.995):
+    both = (got != 0) & (want != 0)
+    mask_flip = np.mean((got != 0) != (want != 0))
+    assert mask_flip <= 1 - share, mask_flip
+    d = np.abs(got[both] - want[both])
+    tol = (rel * np.abs(want[both])) if rel is not None else abs_
+    ok = d <= tol
+    assert ok.mean() >= share, (ok.mean(), d.max())
+    return ok.mean(), mask_flip
+
+
+def test_undistort_matches_oracle(ctx):
+    from paper_1807_08271_amd import rgbid as rg
+    cam, I, Z = _frame()
+    W = np.where(Z > 0, 1.0 / np.where(Z > 0, Z, 1.0), 0.0).astype(np.float32)
+    I = I.astype(np.float32)
+    L = rg.make_lens(cam, K_COLOR)
+    gI = rg.rgbid_undistort(ctx, L, _t(I), False).cpu().numpy()
+    oI = oracle.undistort(cam, K_COLOR, I, False)
+    _agree(gI, oI, abs_=5e-3, share=0.999)
+    L = rg.make_lens(cam, K_DEPTH)
+    gW = rg.rgbid_undistort(ctx, L, _t(W), True).cpu().numpy()
+    oW = oracle.undistort(cam, K_DEPTH, W, True)
+    _agree(gW, oW, rel=1e-5, share=0.999)
+
+
+@pytest.mark.parametrize("motion", [((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
+                                    ((0.01, -0.02, 0.015), (0.05, -0.02, 0.04)),
+                                    ((0.0, 0.004, 0.0), (0.025, 0.0, 0.0))])
+def test_register_matches_oracle(ctx, motion):
+    from paper_1807_08271_amd import rgbid as rg
+    cam, _, Z = _frame(4)
+    W = np.where(Z > 0, 1.0 / np.where(Z > 0, Z, 1.0), 0.0).astype(np.float32)
+    R = Rotation.from_rotvec(motion[0]).as_matrix()
+    t = np.array(motion[1])
+    camB = synth.Camera(640, 480, 520.0, 522.0, 321.0, 238.0)
+    got = rg.rgbid_register(ctx, cam, _t(W), camB, (R, t)).cpu().numpy()
+    want = oracle.register(cam, W, camB, R, t)
+    _agree(got, want, rel=1e-5, share=0.995)
+
+
+def test_register_identity_is_a_copy(ctx):
+    from paper_1807_08271_amd import rgbid as rg
+    cam, _, Z = _frame(5)
+    W = np.where(Z > 0, 1.0 / np.where(Z > 0, Z, 1.0), 0.0).astype(np.float32)
+    got = rg.rgbid_register(ctx, cam, _t(W), cam, (np.eye(3), np.zeros(3))).cpu().numpy()
+    np.testing.assert_array_equal(got, W)
+
+
+def test_preprocess_matches_oracle(ctx):
+    from paper_1807_08271_amd import rgbid as rg
+    cam, I, Z = _frame(6)
+    depth = synth.Camera(640, 480, 575.8, 575.8, 319.5, 239.5)
+    R_dc = Rotation.from_rotvec([0.002, -0.003, 0.001]).as_matrix()
+    t_dc = np.array([0.025, 0.001, -0.002])
+    q0 = [1e-3, 2e-3, -1e-3, 5e-4, 1e-3, -2e-3, 1e-3, 5e-4, -5e-4]
+    q1 = [1.01, -0.02, 0.01, 0.005, 0.01, -0.01, 0.005, 0.002, -0.002]
+    kw = dict(k_color=K_COLOR, k_depth=K_DEPTH, beta0=0.002, beta1=0.995, p0=(4, 4),
+              spatial=True, q0=q0, q1=q1)
+    S = rg.make_sensor(cam, depth, R_dc=R_dc, t_dc=t_dc, **kw)
+    gI, gW = rg.rgbid_preprocess(ctx, S, _t(I), _t(Z))
+    gI, gW = gI.cpu().numpy(), gW.cpu().numpy()
+    so = oracle.Sensor(color=cam.as_tuple(), depth=depth.as_tuple(), R_dc=R_dc, t_dc=t_dc, **kw)
+    oI, oW = oracle.preprocess(so, I.astype(np.float32), Z.astype(np.float32))
+    _agree(gI, oI, abs_=5e-3, share=0.999)
+    _agree(gW, oW, rel=1e-5, share=0.99)
+    assert (gW > 0).mean() > 0.7
+
+
+def test_preprocess_identity_sensor(ctx):
+    # same camera, no distortion, identity correction and extrinsics: the
+    # output is 1/Z and the input intensity
+    from paper_1807_08271_amd import rgbid as rg
+    cam, I, Z = _frame(7)
+    S = rg.make_sensor(cam, cam, p0=(0, 0))
+    gI, gW = rg.rgbid_preprocess(ctx, S, _t(I), _t(Z))
+    gI, gW = gI.cpu().numpy(), gW.cpu().numpy()
+    Zf = Z.astype(np.float32)
+    W = np.where(Zf > 0, np.float32(1.0) / np.where(Zf > 0, Zf, np.float32(1.0)), 0.0)
+    # the sampler needs the whole 2x2 tap block valid (taps clamped at the border)
+    v = W > 0
+    vx = np.concatenate([v[:, 1:], v[:, -1:]], axis=1)
+    vy = np.concatenate([v[1:], v[-1:]], axis=0)
+    vxy = np.concatenate([vx[1:], vx[-1:]], axis=0)
+    want = np.where(v & vx & vy & vxy, W, 0.0)
+    np.testing.assert_array_equal(gW, want)
+    np.testing.assert_array_equal(gI, I.astype(np.float32))
+
+
+def test_sensor_arguments(ctx):
+    from paper_1807_08271_amd import rgbid as rg
+    cam, I, Z = _frame(8)
+    S = rg.make_sensor(cam, cam)
+    S.depth.cam.fx = -1.0
+    with pytest.raises(rg.RgbidError):
+        rg.rgbid_preprocess(ctx, S, _t(I), _t(Z))
