@@ -215,10 +215,10 @@ template <int LOG2B>
 struct ChildLayout {
     static constexpr int B = 1 << LOG2B;
     static constexpr int C = B * B;
-    static constexpr int CPL = C < 4 ? C : 4;   // children per lane
-    static constexpr int LPP = C / CPL;         // lanes per pixel
-    static constexpr int GPP = 64 / LPP;        // pixels per pass
-    static_assert(LPP <= 64, "at most 64 lanes per level pixel");
+    static constexpr int CPL = warp_children_per_lane(LOG2B);   // children per lane
+    static constexpr int LPP = warp_lanes_per_pixel(LOG2B);     // lanes per pixel
+    static constexpr int GPP = warp_pixels_per_pass(LOG2B);     // pixels per pass
+    static_assert(CPL * LPP == C && LPP <= 64, "at most 64 lanes per level pixel");
 };
 
 // Children of the pixel of lane group g in the pass starting at grid pixel

@@ -329,7 +329,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         const std::string key = tune_key(n, A, l, P->warp, f16);
         auto it = c->tunes.find(key);
         tune[l] = it != c->tunes.end() ? it->second : default_tune(b);
-        const int lpp = std::min(1 << (2 * b), 64), gpp = 64 / lpp;
+        const int gpp = warp_pixels_per_pass(b);
         const int wtiles_per_chunk = tune[l].waves * tune[l].tiles_per_wave;
         for (int k = 0; k < nch; ++k) {
             rbeg[k][l].push_back(0);

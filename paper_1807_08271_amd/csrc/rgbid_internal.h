@@ -20,6 +20,14 @@ constexpr int kScaleThreads = 1024;
 constexpr int kScalePerThread = 24;   // sample_max <= 24576
 constexpr int kMaxSample = kScaleThreads * kScalePerThread;
 
+// Lane layout of the full-resolution warp for level pixels with
+// C = 4^log2b children: each lane warps min(C, 4) children, C / min(C, 4)
+// lanes share a level pixel, and a 64-lane pass covers 64 / that pixels.
+// Host launch tables and kernels both use these.
+constexpr int warp_children_per_lane(int log2b) { return log2b == 0 ? 1 : 4; }
+constexpr int warp_lanes_per_pixel(int log2b) { return (1 << (2 * log2b)) / warp_children_per_lane(log2b); }
+constexpr int warp_pixels_per_pass(int log2b) { return 64 / warp_lanes_per_pixel(log2b); }
+
 // One pyramid level as the kernels see it.
 struct LevelView {
     const void* iw;   // interleaved (I, W): float2 or __half2, w*h, dense rows
