@@ -13,8 +13,10 @@ Kinect-like camera fx = fy = 525, cx = 319.5, cy = 239.5):
 value = aligned pairs per second over the timed steps (inputs already in HBM).
 
 Also reported: the roofline of the dominant kernel (algorithmic bytes per
-launch / HIP-event-timed average launch duration, against 8 TB/s), and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+launch / HIP-event-timed average launch duration, against 8 TB/s; and, where
+a counter summary of the current kernel sources is committed, its measured
+HBM bytes and its VALU issue rate against the chip's), and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 
 python bench.py [--steps K] [--warmup W] [--pairs P] [--storage f32|f16]
                 [--warp fullres|per_level] [--no-cpu]
@@ -22,7 +24,6 @@ python bench.py [--steps K] [--warmup W] [--pairs P] [--storage f32|f16]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -60,28 +61,28 @@ def algorithmic_bytes(level, kernel, npairs, w0, h0, f16, warp_fullres, fused):
     return None
 
 
-def source_sha():
-    h = hashlib.sha256()
-    for f in ("align.hip", "rgbid_internal.h"):
-        with open(os.path.join(ROOT, "paper_1807_08271_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
+# (one FP32 operation per lane and cycle; packed FP32 is disabled in the build)
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 
 
-def load_traffic(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def counter_summary():
+    """The machine-readable block of the committed rocprofv3 counter summary
+    of this workload, if it was taken on the current kernel sources."""
+    from paper_1807_08271_amd.build import source_sha
+    path = os.path.join(ROOT, "profiles", "rgbid_counters_64x640x480_fullres_f32.md")
     if not os.path.exists(path):
         return None
+    txt = open(path).read()
+    i = txt.find("```json")
+    if i < 0:
+        return None
+    j = txt.find("```", i + 7)
     try:
-        d = json.load(open(path))
+        d = json.loads(txt[i + 7:j])
     except ValueError:
         return None
-    if d.get("source_sha") != source_sha():
-        return None
-    ent = d.get("kernels", {}).get(kernel_key)
-    return ent.get("hbm_bytes_per_launch") if ent else None
+    return d if d.get("source_sha") == source_sha() else None
 
 
 def make_inputs(npairs, device):
@@ -250,6 +251,16 @@ def main():
         rg.rgbid_tune_save(ctx, os.path.join(ROOT, "gpurun_out", "tune_%s_%s.txt" % (
             args.storage, args.warp)))
 
+    # launch shape per level (fused warp + reduction or not), as tuned
+    tune_txt = os.path.join("/tmp", "rgbid_bench_tune_%d.txt" % os.getpid())
+    rg.rgbid_tune_save(ctx, tune_txt)
+    fused_level = {}
+    for line in open(tune_txt):
+        f = line.split()
+        if len(f) == 5 and f[0].endswith("x%d" % args.pairs):
+            fused_level[int(f[0].split("_")[0][1:])] = f[1] == "1"
+    os.remove(tune_txt)
+
     def step():
         rg.rgbid_pyramid_update_batch(ctx, all_pyr, all_I, all_W)
         poses, stats = rg.rgbid_align_batch(ctx, As, Bs, params)
@@ -285,7 +296,7 @@ def main():
     fullres = args.warp == "fullres"
     rows = []
     for (lvl, kname), (ms, nl) in sorted(kt.items()):
-        fused = (lvl == 0 or not fullres) if kname in ("warp", "reduce") else False
+        fused = fused_level.get(lvl, lvl == 0) if kname in ("warp", "reduce") else False
         b = algorithmic_bytes(lvl, kname, args.pairs, cam.w, cam.h, f16, fullres, fused)
         avg_us = 1e3 * ms / nl
         rows.append((ms, lvl, kname, avg_us, b))
@@ -295,12 +306,28 @@ def main():
     dom = max((r for r in rows if r[4] is not None), key=lambda r: r[0])
     _, lvl, kname, avg_us, b = dom
     achieved = b / (avg_us * 1e-6) / 1e9
-    key = "%s_l%d" % (kname, lvl)
-    traffic = load_traffic(key)
+    cs = counter_summary()
+    ent = (cs or {}).get("kernels", {}).get("%s_l%d" % (kname, lvl))
+    traffic = ent["hbm_bytes_per_launch"] if ent else None
     roofline = {"bound": "hbm", "kernel": "k_%s level %d" % (kname, lvl),
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": b, "avg_launch_us": round(avg_us, 2)}
+    roofline["hbm_GBs"] = round(achieved, 1)
+    if traffic:
+        roofline["measured_GBs"] = round(traffic / (avg_us * 1e-6) / 1e9, 1)
+    if ent and ent.get("valu_insts_per_launch"):
+        # executed wave instructions x 64 lanes / live duration, against the
+        # VALU issue peak: when this is the larger fraction the kernel is
+        # bound by arithmetic issue, not by HBM
+        gops = ent["valu_insts_per_launch"] * 64 / (avg_us * 1e-6) / 1e9
+        alu = {"achieved": round(gops, 1), "peak": VALU_PEAK_GOPS, "unit": "G lane-ops/s",
+               "frac": round(gops / VALU_PEAK_GOPS, 4)}
+        roofline["valu"] = alu
+        if alu["frac"] > roofline["frac"]:
+            roofline.update({"bound": "alu", "achieved": alu["achieved"], "peak": alu["peak"],
+                             "unit": alu["unit"], "frac": alu["frac"],
+                             "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)})
 
     value = args.pairs * args.steps / dt
     out = {

@@ -5,6 +5,7 @@ Usage: python -m paper_1807_08271_amd.build   (or build() from Python)
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -22,6 +23,17 @@ SOURCES = ["api.hip", "pyramid.hip", "align.hip", "fuse.hip", "cnn.hip", "sensor
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
+
+
+def source_sha(files=("align.hip", "api.hip", "rgbid_internal.h")) -> str:
+    """Hash of the sources that decide what the alignment kernels do per
+    launch (kernel code, shared layouts, launch tables): counter summaries
+    taken on other sources are not reused."""
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _compile(src: str) -> str:

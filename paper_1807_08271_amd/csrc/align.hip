@@ -402,13 +402,25 @@ __device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float
     terms_core<JAC>(A, ifx, ify, u, v, c, n, Is, Ws, wv, T);
 }
 
+// Robust weight of a normalised residual x: Huber min(1, k/|x|) or Student-t
+// (nu + 1)/(nu + x^2) (sec. 6.3).  Both branches of the Huber rule are
+// evaluated and selected, so the weight costs no divergent branch.
+template <int KIND>
+__device__ __forceinline__ float omega_k(float x, float nu, float k)
+{
+    if constexpr (KIND == RGBID_W_HUBER) {
+        const float ax = fabsf(x);
+        const float h = k * rcp(ax);
+        return ax <= k ? 1.0f : h;
+    } else {
+        return (nu + 1.0f) * rcp(fmaf(x, x, nu));
+    }
+}
+
 __device__ __forceinline__ float omega(int kind, float x, float nu, float k)
 {
-    if (kind == RGBID_W_HUBER) {
-        const float ax = fabsf(x);
-        return ax <= k ? 1.0f : k * rcp(ax);
-    }
-    return (nu + 1.0f) * rcp(fmaf(x, x, nu));
+    return kind == RGBID_W_HUBER ? omega_k<RGBID_W_HUBER>(x, nu, k)
+                                 : omega_k<RGBID_W_STUDENT_T>(x, nu, k);
 }
 
 __device__ __forceinline__ void accum(float* acc, const float* J, float w, float r)
@@ -579,18 +591,51 @@ __device__ __forceinline__ double nu_equation(const float (&x2)[kScalePerThread]
                                               double nud, float* lds, int parity)
 {
     const float nf = (float)nud;
-    float acc[1] = {0.0f};
+    float part[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int q = 0; q < kScalePerThread; ++q) {
-        if (x2[q] == x2[q]) {
-            const float w = (nf + 1.0f) / (nf + x2[q]);
-            acc[0] += 1.0f + logf(w) - w;
-        }
+        // a padding entry (NaN) takes w = 1, whose term 1 + ln 1 - 1 is 0
+        const float w = x2[q] == x2[q] ? (nf + 1.0f) / (nf + x2[q]) : 1.0f;
+        part[q & 1] += 1.0f + logf(w) - w;
     }
+    float acc[1] = {part[0] + part[1]};
     const BlockSums<1> z = block_sums<1>(acc, lds, parity);
     const double c = -digamma_d(0.5 * nud) + log(0.5 * nud) + digamma_d(0.5 * (nud + 1.0)) -
                      log(0.5 * (nud + 1.0));
     return n * c + z.v[0];
+}
+
+// The location / scale fixed point with nu = 5 (Student-t) or the Huber
+// threshold k: every step sums w, w d and w d^2 (d = r - mu, weights from
+// the previous estimate) over the block and moves mu by S1/S0, sigma^2 to
+// (S2 - S1^2/S0)/n.  Branch-free per element (padding entries get w = 0);
+// two partial sums per lane in a fixed order.
+template <int KIND>
+__device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThread], double n,
+                                                  float floor_s, float k, int iters, float* lds,
+                                                  int& parity, double& mu, double& sigma)
+{
+    for (int it = 0; it < iters; ++it) {
+        const float fmu = (float)mu, isg = (float)(1.0 / sigma);
+        float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < kScalePerThread; ++q) {
+            const bool ok = r[q] == r[q];
+            const float d = ok ? r[q] - fmu : 0.0f;
+            const float w = ok ? omega_k<KIND>(d * isg, 5.0f, k) : 0.0f;
+            s0[q & 1] += w;
+            s1[q & 1] = fmaf(w, d, s1[q & 1]);
+            s2[q & 1] = fmaf(w * d, d, s2[q & 1]);
+        }
+        float acc[3] = {s0[0] + s0[1], s1[0] + s1[1], s2[0] + s2[1]};
+        const BlockSums<3> z = block_sums<3>(acc, lds, parity);
+        parity ^= 1;
+        // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
+        const double dm = z.v[1] / z.v[0];
+        mu += dm;
+        const double var = fmax((z.v[2] - z.v[1] * dm) / n, 0.0);
+        sigma = fmax(sqrt(var), (double)floor_s);
+    }
 }
 
 // One workgroup per (pair, channel): location mu and scale sigma of the
@@ -632,28 +677,12 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     float nu = 5.0f;
     if (n > 0.0) {
         sigma = fmax(sqrt(t.v[1] / n), (double)floor_s);
-        const float k = L.ip.huber_k;
-        for (int it = 0; it < L.ip.scale_iters; ++it) {
-            const float fmu = (float)mu, isg = (float)(1.0 / sigma);
-            float acc[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int q = 0; q < kScalePerThread; ++q) {
-                if (r[q] == r[q]) {
-                    const float d = r[q] - fmu;
-                    const float w = omega(L.ip.weight, d * isg, 5.0f, k);
-                    acc[0] += w;
-                    acc[1] = fmaf(w, d, acc[1]);
-                    acc[2] = fmaf(w * d, d, acc[2]);
-                }
-            }
-            const BlockSums<3> z = block_sums<3>(acc, lds, parity);
-            parity ^= 1;
-            // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
-            const double dm = z.v[1] / z.v[0];
-            mu += dm;
-            const double var = fmax((z.v[2] - z.v[1] * dm) / n, 0.0);
-            sigma = fmax(sqrt(var), (double)floor_s);
-        }
+        if (L.ip.weight == RGBID_W_HUBER)
+            scale_fixed_point<RGBID_W_HUBER>(r, n, floor_s, L.ip.huber_k, L.ip.scale_iters, lds,
+                                             parity, mu, sigma);
+        else
+            scale_fixed_point<RGBID_W_STUDENT_T>(r, n, floor_s, L.ip.huber_k, L.ip.scale_iters, lds,
+                                                 parity, mu, sigma);
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
             const float fmu = (float)mu, isg = (float)(1.0 / sigma);
 #pragma unroll
