@@ -484,6 +484,42 @@ __device__ __forceinline__ GridDim sample_grid(const PairDesc& D, int l)
 
 // ------------------------------------------------------------------ k_warp
 
+// Reference values a pass's group leader needs for its pixel's sample
+// residuals: A's (I, W) at the pixel and its four neighbours (for the
+// validity of the inverse-depth gradient).  Loaded one pass ahead, together
+// with that pass's children, so the residual step has no dependent load.
+struct SampleRef {
+    int idx, sidx;      // grid index, sample index (-1: not a sample pixel)
+    int u, v;           // level coordinates
+    float2 c;
+    Nbrs n;
+};
+
+template <bool F16, int LOG2B>
+__device__ __forceinline__ SampleRef sample_ref(const LevelView& A, const GridDim& gd, int first,
+                                                int lane, bool fused, int s, int sw)
+{
+    using CL = ChildLayout<LOG2B>;
+    SampleRef r;
+    r.idx = first + lane / CL::LPP;
+    r.sidx = -1;
+    r.u = r.v = 0;
+    r.c = make_float2(0.0f, 0.0f);
+    r.n.l = r.n.r = r.n.t = r.n.b = r.c;
+    if ((lane % CL::LPP) != 0 || r.idx >= gd.n) return r;
+    int gu, gv;
+    split_index(r.idx, gd.gw, gd.inv_gw, gu, gv);
+    r.u = gu * gd.gs;
+    r.v = gv * gd.gs;
+    if (fused) r.sidx = r.idx;
+    else if ((r.u % s) == 0 && (r.v % s) == 0) r.sidx = (r.v / s) * sw + r.u / s;
+    if (r.sidx >= 0) {
+        r.c = load_iw<F16>(A.iw, __umul24(r.v, A.w) + r.u);
+        r.n = load_nbrs<F16>(A, r.u, r.v);
+    }
+    return r;
+}
+
 // Tiles of this kernel are single passes of GPP grid pixels.  The group
 // leader of each pixel stores the warped values (store mode) and, for sample
 // pixels, the two residuals (NaN = not defined).
@@ -511,26 +547,24 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
     const int end = ch.first + ch.count;
     int tile = ch.first + wave;
     auto pc = pass_children<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane);
+    SampleRef sr = sample_ref<F16, LOG2B>(A, gd, tile * CL::GPP, lane, fused, s, sw);
     for (; tile < end; tile += waves) {
         float Is, Ws;
         bool wv;
         int idx;
         warp_pass_pc<F16, LOG2B>(G, pc, tile * CL::GPP, gd.n, lane, Is, Ws, wv, idx);
-        // children of the next tile: their W_A loads overlap this tile's tail
+        // the next tile's children and reference values: their loads overlap
+        // this tile's tail
         const int ntile = tile + waves < end ? tile + waves : tile;
         pc = pass_children<F16, LOG2B>(G, ntile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane);
+        const SampleRef cur = sr;
+        sr = sample_ref<F16, LOG2B>(A, gd, ntile * CL::GPP, lane, fused, s, sw);
         if ((lane % CL::LPP) != 0 || idx >= gd.n) continue;
-        int gu, gv;
-        split_index(idx, gd.gw, gd.inv_gw, gu, gv);
-        const int u = gu * gd.gs, v = gv * gd.gs;
         if (!fused) store_f2(warped, idx, Is, wv ? Ws : 0.0f);
-        int sidx;
-        if (fused) sidx = idx;
-        else if ((u % s) == 0 && (v % s) == 0) sidx = (v / s) * sw + u / s;
-        else continue;
+        if (cur.sidx < 0) continue;
         Terms T;
-        pixel_terms<F16, false>(A, ifx, ify, u, v, Is, Ws, wv, T);
-        store_f2(sample, sidx, T.vI ? T.rI : __int_as_float(0x7fc00000),
+        terms_core<false>(A, ifx, ify, cur.u, cur.v, cur.c, cur.n, Is, Ws, wv, T);
+        store_f2(sample, cur.sidx, T.vI ? T.rI : __int_as_float(0x7fc00000),
                  T.vW ? T.rW : __int_as_float(0x7fc00000));
     }
 }
