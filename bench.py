@@ -40,25 +40,31 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(level, kernel, npairs, w0, h0, f16, warp_fullres, fused):
+def algorithmic_bytes(level, kernel, sizes, f16, warp_fullres, fused):
     """Bytes the method must move for one launch of (level, kernel) over the
-    batch.  Per pixel, FP32 storage: a level-0 pixel of the full-resolution
-    warp needs W_A (4 B) and I_B, W_B (8 B); the residual of a level pixel
-    needs I_A, W_A (8 B); a stored warped level image is 8 B per level pixel
-    (written once, read once).  FP16 storage halves the image bytes."""
+    batch (sizes: level-0 (w, h) of every pair).  Per pixel, FP32 storage: a
+    level-0 pixel of the full-resolution warp needs W_A (4 B) and I_B, W_B
+    (8 B); the residual of a level pixel needs I_A, W_A (8 B); a stored warped
+    level image is 8 B per level pixel (written once, read once).  FP16
+    storage halves the image bytes."""
     e = 2 if f16 else 4
-    n0 = w0 * h0
-    nl = (w0 >> level) * (h0 >> level)
-    nw = n0 if warp_fullres else nl       # pixels warped per iteration
-    if kernel == "reduce":
-        if fused:       # warp + residual in one kernel
-            return npairs * (nw * 3 * e + nl * 2 * e - (nl * e if nw == nl else 0))
-        return npairs * nl * (2 * e + 8)
-    if kernel == "warp":
-        if fused:       # sample pixels only: not a bandwidth kernel
+    total = 0
+    for w0, h0 in sizes:
+        n0 = w0 * h0
+        nl = (w0 >> level) * (h0 >> level)
+        nw = n0 if warp_fullres else nl       # pixels warped per iteration
+        if kernel == "reduce":
+            if fused:       # warp + residual in one kernel
+                total += nw * 3 * e + nl * 2 * e - (nl * e if nw == nl else 0)
+            else:
+                total += nl * (2 * e + 8)
+        elif kernel == "warp":
+            if fused:       # sample pixels only: not a bandwidth kernel
+                return None
+            total += nw * 3 * e + nl * 8
+        else:
             return None
-        return npairs * (nw * 3 * e + nl * 8)
-    return None
+    return total
 
 
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
@@ -85,10 +91,13 @@ def counter_summary():
     return d if d.get("source_sha") == source_sha() else None
 
 
-def make_inputs(npairs, device):
+def make_inputs(npairs, device, mixed=False):
     import synth
     t0 = time.time()
-    pairs = [synth.pair_c2(i, ss=2, device=device) for i in range(npairs)]
+    if mixed:
+        pairs = synth.batch_c4(ss=2, device=device)
+    else:
+        pairs = [synth.pair_c2(i, ss=2, device=device) for i in range(npairs)]
     cam, kf, frames, poses = synth.keyframe_sequence(20, seed=0, ss=2, device=device)
     log("generated %d pairs + 21 fusion frames in %.1fs" % (npairs, time.time() - t0))
     return pairs, (cam, kf, frames, poses)
@@ -179,6 +188,9 @@ def main():
     ap.add_argument("--weight", choices=["huber", "student_t"], default="huber")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batch", choices=["uniform", "mixed"], default="uniform",
+                    help="uniform: --pairs pairs at 640x480 (the headline workload); mixed: "
+                         "24 x 320x240 + 32 x 640x480 + 8 x 1280x960 pairs (batched form)")
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--ws-pairs", type=int, default=64)
     ap.add_argument("--tune-file", default=None, help="load tuned launch shapes from this file")
@@ -211,8 +223,12 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
-    pairs, fusion = make_inputs(args.pairs, dev)
+    mixed = args.batch == "mixed"
+    pairs, fusion = make_inputs(args.pairs, dev, mixed)
+    if mixed:
+        args.pairs = len(pairs)
     cam = pairs[0].cam
+    sizes = [(p.cam.w, p.cam.h) for p in pairs]
     f16 = args.storage == "f16"
     storage = rg.RGBID_F16 if f16 else rg.RGBID_F32
 
@@ -222,8 +238,8 @@ def main():
     WA = [up(p.A.W) for p in pairs]
     IB = [up(p.B.I) for p in pairs]
     WB = [up(p.B.W) for p in pairs]
-    As = [rg.rgbid_pyramid(ctx, cam, 4, storage, i, w) for i, w in zip(IA, WA)]
-    Bs = [rg.rgbid_pyramid(ctx, cam, 4, storage, i, w) for i, w in zip(IB, WB)]
+    As = [rg.rgbid_pyramid(ctx, p.cam, 4, storage, i, w) for p, i, w in zip(pairs, IA, WA)]
+    Bs = [rg.rgbid_pyramid(ctx, p.cam, 4, storage, i, w) for p, i, w in zip(pairs, IB, WB)]
     fcam, kf, frames, fposes = fusion
     kfW = up(kf.W)
     fW = [up(f.W) for f in frames]
@@ -257,7 +273,7 @@ def main():
     fused_level = {}
     for line in open(tune_txt):
         f = line.split()
-        if len(f) == 5 and f[0].endswith("x%d" % args.pairs):
+        if len(f) == 5:    # one batch shape per bench run
             fused_level[int(f[0].split("_")[0][1:])] = f[1] == "1"
     os.remove(tune_txt)
 
@@ -297,7 +313,7 @@ def main():
     rows = []
     for (lvl, kname), (ms, nl) in sorted(kt.items()):
         fused = fused_level.get(lvl, lvl == 0) if kname in ("warp", "reduce") else False
-        b = algorithmic_bytes(lvl, kname, args.pairs, cam.w, cam.h, f16, fullres, fused)
+        b = algorithmic_bytes(lvl, kname, sizes, f16, fullres, fused)
         avg_us = 1e3 * ms / nl
         rows.append((ms, lvl, kname, avg_us, b))
         log("kernel %-6s level %d: %6d launches, avg %8.2f us, total %8.2f ms%s" % (
@@ -306,7 +322,7 @@ def main():
     dom = max((r for r in rows if r[4] is not None), key=lambda r: r[0])
     _, lvl, kname, avg_us, b = dom
     achieved = b / (avg_us * 1e-6) / 1e9
-    cs = counter_summary()
+    cs = None if mixed else counter_summary()
     ent = (cs or {}).get("kernels", {}).get("%s_l%d" % (kname, lvl))
     traffic = ent["hbm_bytes_per_launch"] if ent else None
     roofline = {"bound": "hbm", "kernel": "k_%s level %d" % (kname, lvl),
@@ -343,9 +359,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f16-storage/f32" if f16 else "f32",
         "data": "synthetic",
-        "config": {"workload": "%d pairs of 640x480 (room+boxes generator, 10%% holes), "
+        "config": {"workload": "%s (room+boxes generator, 10%% holes), "
                                "4-level %s warp, 10 Huber GN iterations per level, + fusion of "
-                               "20 frames into one keyframe" % (args.pairs, args.warp),
+                               "20 frames into one 640x480 keyframe" % (
+                                   "24 x 320x240 + 32 x 640x480 + 8 x 1280x960 pairs" if mixed
+                                   else "%d pairs of 640x480" % args.pairs, args.warp),
+                   "batch": args.batch,
                    "pairs_per_step": args.pairs, "width": cam.w, "height": cam.h, "levels": 4,
                    "iters_per_level": 10, "warp": args.warp, "weight": args.weight,
                    "storage": args.storage, "parallelism": "single GPU",

@@ -586,89 +586,102 @@ __device__ double digamma_d(double x)
     return r + log(x) - 0.5 / x - series;
 }
 
-// Block sums for the scale kernel with one barrier per call: each wave
-// reduces its FP32 values with cross-lane shuffles, lane 0 stores them in the
-// LDS slot of this call's parity, and after the barrier every wave adds the
-// per-wave values in FP64 in wave order (identical on all lanes, so the
-// result is block-uniform and deterministic).  Alternating slots make the
-// next call's stores safe without a second barrier.
-template <int NV>
-struct BlockSums {
-    double v[NV];
-};
+// Sum of v over the 64 lanes of a wave, left in lane 63, with DPP: a scan
+// inside each row of 16 lanes (row_shr 1, 2, 4, 8, zero fill), then the
+// totals of rows 0 and 2 added into rows 1 and 3 (row_bcast:15), then the
+// total of rows 0-1 into rows 2-3 (row_bcast:31).  A fixed order.
+#define RGBID_DPP_ADD(v, ctrl, rows)                                                            \
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, rows, 0xf, true))
 
-template <int NV>
-__device__ __forceinline__ BlockSums<NV> block_sums(const float (&x)[NV], float* lds, int parity)
+__device__ __forceinline__ float wave_sum_to_last(float v)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    float* slot = lds + parity * 16 * NV;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const float w = wave_sum(x[k]);
-        if (lane == 0) slot[wave * NV + k] = w;
-    }
-    __syncthreads();
-    BlockSums<NV> r;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) r.v[k] = 0.0;
-    for (int w = 0; w < nw; ++w)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) r.v[k] += (double)slot[w * NV + k];
-    return r;
+    RGBID_DPP_ADD(v, 0x111, 0xf);   // row_shr:1
+    RGBID_DPP_ADD(v, 0x112, 0xf);   // row_shr:2
+    RGBID_DPP_ADD(v, 0x114, 0xf);   // row_shr:4
+    RGBID_DPP_ADD(v, 0x118, 0xf);   // row_shr:8
+    RGBID_DPP_ADD(v, 0x142, 0xa);   // row_bcast:15 into rows 1 and 3
+    RGBID_DPP_ADD(v, 0x143, 0xc);   // row_bcast:31 into rows 2 and 3
+    return v;
 }
 
-// n f_c(nu) + sum_i (1 + ln w_i - w_i), w_i = (nu + 1)/(nu + x_i^2), with
-// f_c(nu) = -psi(nu/2) + ln(nu/2) + psi((nu+1)/2) - ln((nu+1)/2): the left side
-// of the nu equation of sec. 6.3 (eq:robustnessValue).  x2 holds x_i^2
-// (NaN = not in the sample); block-uniform result.
-__device__ __forceinline__ double nu_equation(const float (&x2)[kScalePerThread], double n,
-                                              double nud, float* lds, int parity)
+// Block totals of NV per-thread FP32 values, in FP64 and valid in wave 0
+// only: every wave reduces its values (lane 63 stores them to LDS), then
+// after a barrier wave 0 adds the per-wave values in wave order.  The scale
+// kernel's FP64 step runs once per block (in wave 0) and its result reaches
+// the other waves through LDS after a second barrier.
+template <int NV>
+__device__ __forceinline__ void block_totals(const float (&x)[NV], float* part, double (&tot)[NV])
 {
-    const float nf = (float)nud;
-    float part[2] = {0.0f, 0.0f};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-    for (int q = 0; q < kScalePerThread; ++q) {
-        // a padding entry (NaN) takes w = 1, whose term 1 + ln 1 - 1 is 0
-        const float w = x2[q] == x2[q] ? (nf + 1.0f) / (nf + x2[q]) : 1.0f;
-        part[q & 1] += 1.0f + logf(w) - w;
+    for (int k = 0; k < NV; ++k) {
+        const float w = wave_sum_to_last(x[k]);
+        if (lane == 63) part[wave * NV + k] = w;
     }
-    float acc[1] = {part[0] + part[1]};
-    const BlockSums<1> z = block_sums<1>(acc, lds, parity);
-    const double c = -digamma_d(0.5 * nud) + log(0.5 * nud) + digamma_d(0.5 * (nud + 1.0)) -
-                     log(0.5 * (nud + 1.0));
-    return n * c + z.v[0];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    if (wave == 0)
+        for (int w = 0; w < nw; ++w)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) tot[k] += (double)part[w * NV + k];
+}
+
+// n f_c(nu) with f_c(nu) = -psi(nu/2) + ln(nu/2) + psi((nu+1)/2) - ln((nu+1)/2):
+// the data-free part of the left side of the nu equation of sec. 6.3
+// (eq:robustnessValue); the data part is sum_i (1 + ln w_i - w_i).
+__device__ __forceinline__ double nu_equation_const(double n, double nud)
+{
+    return n * (-digamma_d(0.5 * nud) + log(0.5 * nud) + digamma_d(0.5 * (nud + 1.0)) -
+                log(0.5 * (nud + 1.0)));
 }
 
 // The location / scale fixed point with nu = 5 (Student-t) or the Huber
 // threshold k: every step sums w, w d and w d^2 (d = r - mu, weights from
 // the previous estimate) over the block and moves mu by S1/S0, sigma^2 to
-// (S2 - S1^2/S0)/n.  Branch-free per element (padding entries get w = 0);
-// two partial sums per lane in a fixed order.
+// (S2 - S1^2/S0)/n.  Branch-free per element (padding entries get w = 0;
+// entries past `per` are padding in every thread and skipped); two partial
+// sums per lane in a fixed order.  bc[0..2] broadcast mu, sigma and 1/sigma.
 template <int KIND>
-__device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThread], double n,
-                                                  float floor_s, float k, int iters, float* lds,
-                                                  int& parity, double& mu, double& sigma)
+__device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThread], int per,
+                                                  double n, float floor_s, float k, int iters,
+                                                  float* part, double* bc, double& mu,
+                                                  double& sigma)
 {
+    const int wave = threadIdx.x >> 6;
+    float fmu = (float)mu, isg = (float)(1.0 / sigma);
     for (int it = 0; it < iters; ++it) {
-        const float fmu = (float)mu, isg = (float)(1.0 / sigma);
         float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < kScalePerThread; ++q) {
-            const bool ok = r[q] == r[q];
-            const float d = ok ? r[q] - fmu : 0.0f;
-            const float w = ok ? omega_k<KIND>(d * isg, 5.0f, k) : 0.0f;
-            s0[q & 1] += w;
-            s1[q & 1] = fmaf(w, d, s1[q & 1]);
-            s2[q & 1] = fmaf(w * d, d, s2[q & 1]);
+            if (q < per) {
+                const bool ok = r[q] == r[q];
+                const float d = ok ? r[q] - fmu : 0.0f;
+                const float w = ok ? omega_k<KIND>(d * isg, 5.0f, k) : 0.0f;
+                s0[q & 1] += w;
+                s1[q & 1] = fmaf(w, d, s1[q & 1]);
+                s2[q & 1] = fmaf(w * d, d, s2[q & 1]);
+            }
         }
-        float acc[3] = {s0[0] + s0[1], s1[0] + s1[1], s2[0] + s2[1]};
-        const BlockSums<3> z = block_sums<3>(acc, lds, parity);
-        parity ^= 1;
-        // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
-        const double dm = z.v[1] / z.v[0];
-        mu += dm;
-        const double var = fmax((z.v[2] - z.v[1] * dm) / n, 0.0);
-        sigma = fmax(sqrt(var), (double)floor_s);
+        const float acc[3] = {s0[0] + s0[1], s1[0] + s1[1], s2[0] + s2[1]};
+        double tot[3];
+        block_totals<3>(acc, part, tot);
+        if (wave == 0) {
+            // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
+            const double dm = tot[1] / tot[0];
+            const double var = fmax((tot[2] - tot[1] * dm) / n, 0.0);
+            const double sg = fmax(sqrt(var), (double)floor_s);
+            if (threadIdx.x == 0) {
+                bc[0] = mu + dm;
+                bc[1] = sg;
+                bc[2] = 1.0 / sg;
+            }
+        }
+        __syncthreads();
+        mu = bc[0];
+        sigma = bc[1];
+        fmu = (float)mu;
+        isg = (float)bc[2];
     }
 }
 
@@ -677,15 +690,19 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThre
 // equations of sec. 6.3 (weights from the previous estimate), starting at
 // mu = 0, sigma^2 = mean r^2, with nu = 5 for Student-t; then (Student-t with
 // estimation) nu by bisection of the nu equation on [2, 10] with the
-// normalised residuals frozen.
+// normalised residuals frozen: f(10) > 0 gives 10, f(2) < 0 gives 2, else 30
+// halvings of [2, 10] and the midpoint.
 __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
 {
-    __shared__ float lds[2 * 16 * 3];
+    __shared__ float part[16 * 3];
+    __shared__ double bc[4];
     const int p = blockIdx.x, ch = blockIdx.y;
     PairState& S = L.states[p];
     if (!S.active || S.level_stop) return;
     const PairDesc& D = L.pairs[p];
     const int n_all = D.sw[L.level] * D.sh[L.level];
+    const int per = (n_all + kScaleThreads - 1) / kScaleThreads;
+    const int wave = threadIdx.x >> 6;
     const float floor_s = ch == 0 ? 1e-3f : 1e-6f;
     float r[kScalePerThread];
     float cs[2] = {0.0f, 0.0f};
@@ -698,25 +715,29 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
             x = ch == 0 ? e.x : e.y;
         }
         r[k] = x;
-        if (x == x) {
-            cs[0] += 1.0f;
-            cs[1] = fmaf(x, x, cs[1]);
-        }
+        const bool ok = x == x;
+        cs[0] += ok ? 1.0f : 0.0f;
+        cs[1] = ok ? fmaf(x, x, cs[1]) : cs[1];
     }
-    int parity = 0;
-    const BlockSums<2> t = block_sums<2>(cs, lds, parity);
-    parity ^= 1;
-    const double n = t.v[0];
-    double mu = 0.0, sigma = floor_s;
+    {
+        double t[2];
+        block_totals<2>(cs, part, t);
+        if (threadIdx.x == 0) {
+            bc[0] = t[0];
+            bc[1] = t[0] > 0.0 ? fmax(sqrt(t[1] / t[0]), (double)floor_s) : (double)floor_s;
+        }
+        __syncthreads();
+    }
+    const double n = bc[0];
+    double mu = 0.0, sigma = bc[1];
     float nu = 5.0f;
     if (n > 0.0) {
-        sigma = fmax(sqrt(t.v[1] / n), (double)floor_s);
         if (L.ip.weight == RGBID_W_HUBER)
-            scale_fixed_point<RGBID_W_HUBER>(r, n, floor_s, L.ip.huber_k, L.ip.scale_iters, lds,
-                                             parity, mu, sigma);
+            scale_fixed_point<RGBID_W_HUBER>(r, per, n, floor_s, L.ip.huber_k, L.ip.scale_iters,
+                                             part, bc, mu, sigma);
         else
-            scale_fixed_point<RGBID_W_STUDENT_T>(r, n, floor_s, L.ip.huber_k, L.ip.scale_iters, lds,
-                                                 parity, mu, sigma);
+            scale_fixed_point<RGBID_W_STUDENT_T>(r, per, n, floor_s, L.ip.huber_k,
+                                                 L.ip.scale_iters, part, bc, mu, sigma);
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
             const float fmu = (float)mu, isg = (float)(1.0 / sigma);
 #pragma unroll
@@ -724,24 +745,50 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
                 const float x = (r[q] - fmu) * isg;
                 r[q] = x * x;     // r now holds x^2 (NaN stays NaN)
             }
-            // sequence of evaluations: f(10), f(2), then 30 bisection steps
-            double lo = 2.0, hi = 10.0, nv = 0.0;
-            bool done = false;
-            for (int ev = 0; ev < 32 && !done; ++ev) {
-                const double nud = ev == 0 ? 10.0 : ev == 1 ? 2.0 : 0.5 * (lo + hi);
-                const double f = nu_equation(r, n, nud, lds, parity);
-                parity ^= 1;
-                if (ev == 0) {
-                    if (f > 0.0) { nv = 10.0; done = true; }
-                } else if (ev == 1) {
-                    if (f < 0.0) { nv = 2.0; done = true; }
-                } else {
-                    if (f > 0.0) lo = nud;
-                    else hi = nud;
+            // evaluations f(10), f(2), then up to 30 bisection steps; the
+            // bracket lives in wave 0, the next nu and the stop flag reach
+            // every wave through LDS
+            double lo = 2.0, hi = 10.0, nud = 10.0;
+            for (int ev = 0;; ++ev) {
+                const float nf = (float)nud;
+                float e2[2] = {0.0f, 0.0f};
+#pragma unroll
+                for (int q = 0; q < kScalePerThread; ++q) {
+                    if (q < per) {
+                        // a padding entry (NaN) takes w = 1, whose term 1 + ln 1 - 1 is 0
+                        const float w = r[q] == r[q] ? (nf + 1.0f) / (nf + r[q]) : 1.0f;
+                        e2[q & 1] += 1.0f + logf(w) - w;
+                    }
                 }
+                const float acc[1] = {e2[0] + e2[1]};
+                double tot[1];
+                block_totals<1>(acc, part, tot);
+                if (wave == 0) {
+                    const double f = nu_equation_const(n, nud) + tot[0];
+                    double next = nud;
+                    bool stop = false;
+                    if (ev == 0) {
+                        stop = f > 0.0;           // nu = 10
+                        next = stop ? 10.0 : 2.0;
+                    } else if (ev == 1) {
+                        stop = f < 0.0;           // nu = 2
+                        next = stop ? 2.0 : 0.5 * (lo + hi);
+                    } else {
+                        if (f > 0.0) lo = nud;
+                        else hi = nud;
+                        next = 0.5 * (lo + hi);
+                        stop = ev == 31;
+                    }
+                    if (threadIdx.x == 0) {
+                        bc[2] = next;
+                        bc[3] = stop ? 1.0 : 0.0;
+                    }
+                }
+                __syncthreads();
+                nud = bc[2];
+                if (bc[3] != 0.0) break;
             }
-            if (!done) nv = 0.5 * (lo + hi);
-            nu = (float)nv;
+            nu = (float)nud;
         }
     }
     if (threadIdx.x == 0) {
