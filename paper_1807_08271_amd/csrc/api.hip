@@ -330,7 +330,11 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         auto it = c->tunes.find(key);
         tune[l] = it != c->tunes.end() ? it->second : default_tune(b);
         const int gpp = warp_pixels_per_pass(b);
-        const int wtiles_per_chunk = tune[l].waves * tune[l].tiles_per_wave;
+        const int rtiles_per_chunk = tune[l].waves * tune[l].tiles_per_wave;
+        // When the reduction warps its own pixels, the warp kernel only forms
+        // the systematic sample: a few passes per pair, latency-bound, so one
+        // pass per wave to have as many in flight as possible.
+        const int wtiles_per_chunk = tune[l].fused ? tune[l].waves : rtiles_per_chunk;
         for (int k = 0; k < nch; ++k) {
             rbeg[k][l].push_back(0);
             for (int i = cfirst[k]; i < cfirst[k + 1]; ++i) {
@@ -347,9 +351,9 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                     wch[k][l].push_back(
                         Chunk{li, (int)t, (int)std::min<long long>(wtiles_per_chunk, wt - t)});
                 const long long rt = ((long long)w * h + 63) / 64;
-                for (long long t = 0; t < rt; t += wtiles_per_chunk)
+                for (long long t = 0; t < rt; t += rtiles_per_chunk)
                     rch[k][l].push_back(
-                        Chunk{li, (int)t, (int)std::min<long long>(wtiles_per_chunk, rt - t)});
+                        Chunk{li, (int)t, (int)std::min<long long>(rtiles_per_chunk, rt - t)});
                 rbeg[k][l].push_back((int)rch[k][l].size());
             }
             max_red[k] = std::max(max_red[k], rch[k][l].size());
