@@ -150,10 +150,16 @@ __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x);
 // bilinear W_B(p_B).  Valid iff w_a valid, in front, p_B in
 // [-0.5, w-0.5) x [-0.5, h-0.5), four valid W taps and W* positive and
 // finite.  Branch-free: the four taps are always loaded (at clamped, in-bounds
-// addresses) so the loads of several pixels can be in flight together.
+// addresses).  Split in two phases so that a lane can issue the tap loads of
+// all its pixels before it consumes any of them.
+struct WarpTaps {
+    float2 p00, p10, p01, p11;
+    float a, b, az;
+    bool ok;
+};
+
 template <bool F16>
-__device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa, float& Io,
-                                          float& Wo)
+__device__ __forceinline__ void warp_fetch(const Geom& G, int u, int v, float wa, WarpTaps& T)
 {
     bool ok = w_valid(wa);
     const float rx = ((float)u - G.cx) * G.ifx, ry = ((float)v - G.cy) * G.ify;
@@ -168,27 +174,45 @@ __device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa,
     ub = ok ? ub : 0.0f;
     vb = ok ? vb : 0.0f;
     const float fu = floorf(ub), fv = floorf(vb);
-    const float a = ub - fu, b = vb - fv;
+    T.a = ub - fu;
+    T.b = vb - fv;
+    T.az = az;
+    T.ok = ok;
     // taps: x0 = floor(u_B) (>= -1 in bounds), clamped to the image
     const int xf = (int)fu, yf = (int)fv;
     const unsigned x0 = (unsigned)max(xf, 0), y0 = (unsigned)max(yf, 0);
     const unsigned dx = xf + 1 <= G.w - 1 && xf >= 0 ? 1u : 0u;
     const unsigned dy = yf + 1 <= G.h - 1 && yf >= 0 ? (unsigned)G.w : 0u;
     const unsigned i00 = __umul24(y0, (unsigned)G.w) + x0;
-    const float2 p00 = load_iw<F16>(G.Biw, i00);
-    const float2 p10 = load_iw<F16>(G.Biw, i00 + dx);
-    const float2 p01 = load_iw<F16>(G.Biw, i00 + dy);
-    const float2 p11 = load_iw<F16>(G.Biw, i00 + dy + dx);
-    ok = ok && w_valid(p00.y) && w_valid(p10.y) && w_valid(p01.y) && w_valid(p11.y);
+    T.p00 = load_iw<F16>(G.Biw, i00);
+    T.p10 = load_iw<F16>(G.Biw, i00 + dx);
+    T.p01 = load_iw<F16>(G.Biw, i00 + dy);
+    T.p11 = load_iw<F16>(G.Biw, i00 + dy + dx);
+}
+
+__device__ __forceinline__ bool warp_finish(const Geom& G, const WarpTaps& T, float& Io, float& Wo)
+{
+    bool ok = T.ok && w_valid(T.p00.y) && w_valid(T.p10.y) && w_valid(T.p01.y) &&
+              w_valid(T.p11.y);
+    const float a = T.a, b = T.b;
     const float c00 = (1.0f - a) * (1.0f - b), c10 = a * (1.0f - b);
     const float c01 = (1.0f - a) * b, c11 = a * b;
-    const float ib = c00 * p00.x + c10 * p10.x + c01 * p01.x + c11 * p11.x;
-    const float wb = c00 * p00.y + c10 * p10.y + c01 * p01.y + c11 * p11.y;
-    const float ws = az * wb * rcp(fmaf(wb, G.q[2], 1.0f));
+    const float ib = c00 * T.p00.x + c10 * T.p10.x + c01 * T.p01.x + c11 * T.p11.x;
+    const float wb = c00 * T.p00.y + c10 * T.p10.y + c01 * T.p01.y + c11 * T.p11.y;
+    const float ws = T.az * wb * rcp(fmaf(wb, G.q[2], 1.0f));
     ok = ok && w_valid(ws);
     Io = ok ? ib : 0.0f;
     Wo = ok ? ws : 0.0f;
     return ok;
+}
+
+template <bool F16>
+__device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa, float& Io,
+                                          float& Wo)
+{
+    WarpTaps T;
+    warp_fetch<F16>(G, u, v, wa, T);
+    return warp_finish(G, T, Io, Wo);
 }
 
 template <bool F16>
@@ -256,10 +280,14 @@ __device__ __forceinline__ void warp_pass_pc(const Geom& G, const PassChildren<F
     const int idx = first + g;
     bool ok = idx < ngrid;
     float sI = 0.0f, sW = 0.0f;
+    // every child's tap loads first, then the arithmetic on them
+    WarpTaps T[CL::CPL];
+#pragma unroll
+    for (int m = 0; m < CL::CPL; ++m) warp_fetch<F16>(G, pc.u[m], pc.v[m], pc.wa[m], T[m]);
 #pragma unroll
     for (int m = 0; m < CL::CPL; ++m) {
         float ci, cw;
-        const bool okc = warp_core<F16>(G, pc.u[m], pc.v[m], pc.wa[m], ci, cw);
+        const bool okc = warp_finish(G, T[m], ci, cw);
         ok = ok && okc;
         sI += ci;
         sW += cw;

@@ -523,7 +523,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                 hipError_t e2 = hipStreamEndCapture(c->cap, &g);
                 hipGraphExec_t ex = nullptr;
                 if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 if (e != hipSuccess || e2 != hipSuccess) {
                     for (hipGraphExec_t x : execs) (void)hipGraphExecDestroy(x);
                     return set_err(c, RGBID_E_DEVICE, "graph capture failed: %s",
@@ -679,23 +679,23 @@ rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream)
 void rgbid_destroy(rgbid_ctx* c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
     clear_graphs(c);
     if (c->cov_pyr) rgbid_pyramid_free(c->cov_pyr);
-    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
                       &c->frames, &c->covis, &c->cov_img, &c->reg})
-        if (b->p) hipFree(b->p);
-    if (c->h_stage) hipHostFree(c->h_stage);
-    if (c->h_down) hipHostFree(c->h_down);
-    if (c->stage_done) hipEventDestroy(c->stage_done);
+        if (b->p) (void)hipFree(b->p);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_down) (void)hipHostFree(c->h_down);
+    if (c->stage_done) (void)hipEventDestroy(c->stage_done);
     for (hipEvent_t e : c->tev)
-        if (e) hipEventDestroy(e);
-    for (hipStream_t cs : c->chain_streams) hipStreamDestroy(cs);
-    for (hipEvent_t e : c->joins) hipEventDestroy(e);
-    if (c->fork) hipEventDestroy(c->fork);
-    if (c->cap) hipStreamDestroy(c->cap);
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t cs : c->chain_streams) (void)hipStreamDestroy(cs);
+    for (hipEvent_t e : c->joins) (void)hipEventDestroy(e);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }
 
@@ -752,7 +752,7 @@ rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rg
     const size_t pt[1] = {pitch_elems};
     rgbid_status st = build_pyramids(c, 1, arr, Is, Ws, pt);
     if (st != RGBID_OK) {
-        hipFree(p->base);
+        (void)hipFree(p->base);
         delete p;
         return st;
     }
@@ -808,9 +808,9 @@ rgbid_status rgbid_pyramid_level_size(const rgbid_pyr* p, int level, int* w, int
 void rgbid_pyramid_free(rgbid_pyr* p)
 {
     if (!p) return;
-    hipSetDevice(p->device);
-    hipDeviceSynchronize();
-    hipFree(p->base);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->base);
     delete p;
 }
 
@@ -979,7 +979,7 @@ rgbid_status rgbid_keyframe_init(rgbid_ctx* c, const rgbid_camera* cam, const fl
     e = launch_copy_valid(c->stream, W_dev, (long long)pitch_elems, cam->width, cam->height, k->W);
     if (e == hipSuccess) e = launch_fill(c->stream, k->C, (int)np, 1.0f);
     if (e != hipSuccess) {
-        hipFree(k->base);
+        (void)hipFree(k->base);
         delete k;
         return set_err(c, RGBID_E_DEVICE, "keyframe init failed: %s", hipGetErrorString(e));
     }
@@ -1197,9 +1197,9 @@ rgbid_status rgbid_kernel_times(const rgbid_ctx* c, double* ms_total, long long*
 void rgbid_keyframe_free(rgbid_kf* kf)
 {
     if (!kf) return;
-    hipSetDevice(kf->device);
-    hipDeviceSynchronize();
-    hipFree(kf->base);
+    (void)hipSetDevice(kf->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(kf->base);
     delete kf;
 }
 
@@ -1344,7 +1344,7 @@ rgbid_status rgbid_warmstart_create(rgbid_ctx* c, const float* params, rgbid_net
     if (e == hipSuccess) e = hipMemsetAsync(net->buf.m, 0, 2 * f, c->stream);
     if (e == hipSuccess) e = cnn_refresh_bf16(c->stream, net->buf);
     if (e != hipSuccess) {
-        hipFree(net->base);
+        (void)hipFree(net->base);
         delete net;
         return set_err(c, RGBID_E_DEVICE, "warm-start init failed: %s", hipGetErrorString(e));
     }
@@ -1355,10 +1355,10 @@ rgbid_status rgbid_warmstart_create(rgbid_ctx* c, const float* params, rgbid_net
 void rgbid_warmstart_free(rgbid_net* net)
 {
     if (!net) return;
-    hipSetDevice(net->device);
-    hipDeviceSynchronize();
-    if (net->act_base) hipFree(net->act_base);
-    hipFree(net->base);
+    (void)hipSetDevice(net->device);
+    (void)hipDeviceSynchronize();
+    if (net->act_base) (void)hipFree(net->act_base);
+    (void)hipFree(net->base);
     delete net;
 }
 
@@ -1752,12 +1752,12 @@ void rgbid_tracker_default_params(rgbid_tracker_params* p)
 void rgbid_tracker_free(rgbid_tracker* t)
 {
     if (!t) return;
-    hipSetDevice(t->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(t->device);
+    (void)hipDeviceSynchronize();
     for (auto* s : t->slot)
         if (s) rgbid_pyramid_free(s);
     if (t->kf) rgbid_keyframe_free(t->kf);
-    if (t->maps) hipFree(t->maps);
+    if (t->maps) (void)hipFree(t->maps);
     delete t;
 }
 
