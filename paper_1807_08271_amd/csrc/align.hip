@@ -249,7 +249,8 @@ struct ChildLayout {
 // `first` (grid of width gw, grid stride gs in level pixels), with their W_A.
 template <bool F16, int LOG2B>
 __device__ __forceinline__ PassChildren<F16, ChildLayout<LOG2B>::CPL>
-pass_children(const Geom& G, int first, int gw, float inv_gw, int ngrid, int gs, int lane)
+pass_children(const Geom& G, int first, int gw, float inv_gw, int ngrid, int gs, int lane,
+              bool load_wa = true)
 {
     using CL = ChildLayout<LOG2B>;
     PassChildren<F16, CL::CPL> pc;
@@ -262,7 +263,7 @@ pass_children(const Geom& G, int first, int gw, float inv_gw, int ngrid, int gs,
         const int c = j + CL::LPP * m;
         pc.u[m] = __umul24(gu, gs * CL::B) + (c % CL::B);
         pc.v[m] = __umul24(gv, gs * CL::B) + (c / CL::B);
-        pc.wa[m] = load_w<F16>(G.WA, __umul24(pc.v[m], G.w) + pc.u[m]);
+        pc.wa[m] = load_wa ? load_w<F16>(G.WA, __umul24(pc.v[m], G.w) + pc.u[m]) : 0.0f;
     }
     return pc;
 }
@@ -381,14 +382,23 @@ __device__ __forceinline__ Nbrs load_nbrs(const LevelView& A, int u, int v)
     return n;
 }
 
+__device__ __forceinline__ unsigned load_mask(const LevelView& A, unsigned i)
+{
+    return ld_at<unsigned char>(A.gm, i);
+}
+
+// Residuals of one level pixel (sec. 6.2) with c = A's (I, W) at the pixel
+// and m its validity flags (bit 0: interior with valid W, bit 1: also the W
+// gradient defined): r_I needs the warp and bit 0, r_W the warp and bit 1.
+// JAC: also the Jacobians J = (a, X x a) of eq:res_int / eq:res_depth from
+// the central differences of the neighbours n, and lambda_n.
 template <bool JAC>
 __device__ __forceinline__ void terms_core(const LevelView& A, float ifx, float ify, int u, int v,
-                                           float2 c, const Nbrs& n, float Is, float Ws, bool wv,
-                                           Terms& T)
+                                           float2 c, const Nbrs& n, unsigned m, float Is, float Ws,
+                                           bool wv, Terms& T)
 {
-    const bool inner = u >= 1 && v >= 1 && u <= A.w - 2 && v <= A.h - 2;
-    T.vI = wv && inner && w_valid(c.y);
-    T.vW = T.vI && w_valid(n.l.y) && w_valid(n.r.y) && w_valid(n.t.y) && w_valid(n.b.y);
+    T.vI = wv && (m & 1u);
+    T.vW = wv && (m & 2u);
     T.rI = Is - c.x;
     T.rW = Ws - c.y;
     if constexpr (JAC) {
@@ -425,9 +435,13 @@ template <bool F16, bool JAC>
 __device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float ify, int u, int v,
                                             float Is, float Ws, bool wv, Terms& T)
 {
-    const float2 c = load_iw<F16>(A.iw, __umul24(v, A.w) + u);
-    const Nbrs n = load_nbrs<F16>(A, u, v);
-    terms_core<JAC>(A, ifx, ify, u, v, c, n, Is, Ws, wv, T);
+    const unsigned i = __umul24(v, A.w) + u;
+    const float2 c = load_iw<F16>(A.iw, i);
+    const unsigned m = load_mask(A, i);
+    Nbrs n;
+    if constexpr (JAC) n = load_nbrs<F16>(A, u, v);
+    else n.l = n.r = n.t = n.b = c;
+    terms_core<JAC>(A, ifx, ify, u, v, c, n, m, Is, Ws, wv, T);
 }
 
 // Robust weight of a normalised residual x: Huber min(1, k/|x|) or Student-t
@@ -520,7 +534,7 @@ struct SampleRef {
     int idx, sidx;      // grid index, sample index (-1: not a sample pixel)
     int u, v;           // level coordinates
     float2 c;
-    Nbrs n;
+    unsigned m;
 };
 
 template <bool F16, int LOG2B>
@@ -533,7 +547,7 @@ __device__ __forceinline__ SampleRef sample_ref(const LevelView& A, const GridDi
     r.sidx = -1;
     r.u = r.v = 0;
     r.c = make_float2(0.0f, 0.0f);
-    r.n.l = r.n.r = r.n.t = r.n.b = r.c;
+    r.m = 0;
     if ((lane % CL::LPP) != 0 || r.idx >= gd.n) return r;
     int gu, gv;
     split_index(r.idx, gd.gw, gd.inv_gw, gu, gv);
@@ -542,8 +556,9 @@ __device__ __forceinline__ SampleRef sample_ref(const LevelView& A, const GridDi
     if (fused) r.sidx = r.idx;
     else if ((r.u % s) == 0 && (r.v % s) == 0) r.sidx = (r.v / s) * sw + r.u / s;
     if (r.sidx >= 0) {
-        r.c = load_iw<F16>(A.iw, __umul24(r.v, A.w) + r.u);
-        r.n = load_nbrs<F16>(A, r.u, r.v);
+        const unsigned i = __umul24(r.v, A.w) + r.u;
+        r.c = load_iw<F16>(A.iw, i);
+        r.m = load_mask(A, i);
     }
     return r;
 }
@@ -574,8 +589,13 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
     int tile = ch.first + wave;
-    auto pc = pass_children<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane);
+    // sample-only pass at level 0: the pixel is its own child, so W_A comes
+    // with the reference values and the W plane is not read
+    const bool own = LOG2B == 0 && fused;
     SampleRef sr = sample_ref<F16, LOG2B>(A, gd, tile * CL::GPP, lane, fused, s, sw);
+    auto pc = pass_children<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane,
+                                        !own);
+    if (own) pc.wa[0] = sr.c.y;
     for (; tile < end; tile += waves) {
         float Is, Ws;
         bool wv;
@@ -584,14 +604,18 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
         // the next tile's children and reference values: their loads overlap
         // this tile's tail
         const int ntile = tile + waves < end ? tile + waves : tile;
-        pc = pass_children<F16, LOG2B>(G, ntile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane);
         const SampleRef cur = sr;
         sr = sample_ref<F16, LOG2B>(A, gd, ntile * CL::GPP, lane, fused, s, sw);
+        pc = pass_children<F16, LOG2B>(G, ntile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane,
+                                       !own);
+        if (own) pc.wa[0] = sr.c.y;
         if ((lane % CL::LPP) != 0 || idx >= gd.n) continue;
         if (!fused) store_f2(warped, idx, Is, wv ? Ws : 0.0f);
         if (cur.sidx < 0) continue;
         Terms T;
-        terms_core<false>(A, ifx, ify, cur.u, cur.v, cur.c, cur.n, Is, Ws, wv, T);
+        Nbrs none;
+        none.l = none.r = none.t = none.b = cur.c;
+        terms_core<false>(A, ifx, ify, cur.u, cur.v, cur.c, none, cur.m, Is, Ws, wv, T);
         store_f2(sample, cur.sidx, T.vI ? T.rI : __int_as_float(0x7fc00000),
                  T.vW ? T.rW : __int_as_float(0x7fc00000));
     }
@@ -679,16 +703,24 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThre
     const int wave = threadIdx.x >> 6;
     float fmu = (float)mu, isg = (float)(1.0 / sigma);
     for (int it = 0; it < iters; ++it) {
+        // the weight of x = d / sigma written in d: Huber min(1, k sigma / |d|),
+        // Student-t (nu + 1) sigma^2 / (nu sigma^2 + d^2) with nu = 5
+        const float sg = 1.0f / isg;
+        const float hk = k * sg, tA = 6.0f * sg * sg, tB = 5.0f * sg * sg;
         float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < kScalePerThread; ++q) {
             if (q < per) {
                 const bool ok = r[q] == r[q];
-                const float d = ok ? r[q] - fmu : 0.0f;
-                const float w = ok ? omega_k<KIND>(d * isg, 5.0f, k) : 0.0f;
+                const float d = r[q] - fmu;
+                float w;
+                if constexpr (KIND == RGBID_W_HUBER) w = fminf(1.0f, hk * rcp(fabsf(d)));
+                else w = tA * rcp(fmaf(d, d, tB));
+                w = ok ? w : 0.0f;
+                const float dd = ok ? d : 0.0f;
                 s0[q & 1] += w;
-                s1[q & 1] = fmaf(w, d, s1[q & 1]);
-                s2[q & 1] = fmaf(w * d, d, s2[q & 1]);
+                s1[q & 1] = fmaf(w, dd, s1[q & 1]);
+                s2[q & 1] = fmaf(w * dd, dd, s2[q & 1]);
             }
         }
         const float acc[3] = {s0[0] + s0[1], s1[0] + s1[1], s2[0] + s2[1]};
@@ -871,6 +903,7 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         int u, v;
         split_index(ic, gd.gw, gd.inv_gw, u, v);
         float2 c = load_iw<F16>(A.iw, ic);
+        unsigned m = load_mask(A, ic);
         Nbrs nb = load_nbrs<F16>(A, u, v);
         for (; tile < end; tile += waves) {
             float Is, Ws;
@@ -881,9 +914,10 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             int nu, nv;
             split_index(nic, gd.gw, gd.inv_gw, nu, nv);
             const float2 nc = load_iw<F16>(A.iw, nic);
+            const unsigned nm = load_mask(A, nic);
             const Nbrs nnb = load_nbrs<F16>(A, nu, nv);
             Terms T;
-            terms_core<true>(A, ifx, ify, u, v, c, nb, Is, Ws, wv, T);
+            terms_core<true>(A, ifx, ify, u, v, c, nb, m, Is, Ws, wv, T);
             if (T.vI && enI) {
                 const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
                 accum(acc, T.JI, w, T.rI);
@@ -899,6 +933,7 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             u = nu;
             v = nv;
             c = nc;
+            m = nm;
             nb = nnb;
         }
     } else {

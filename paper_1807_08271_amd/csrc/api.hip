@@ -27,6 +27,7 @@ struct rgbid_pyr {
     void* base;
     void* iw[kMaxLevels];
     void* wp[kMaxLevels];
+    void* gm[kMaxLevels];
 };
 
 struct rgbid_kf {
@@ -404,10 +405,12 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         for (int l = 0; l < L; ++l) {
             const rgbid_pyr* Pa = A[i];
             const rgbid_pyr* Pb = B[i];
-            d.A[l] = LevelView{Pa->iw[l], Pa->wp[l], Pa->w[l], Pa->h[l], (float)Pa->fx[l],
-                               (float)Pa->fy[l], (float)Pa->cx[l], (float)Pa->cy[l]};
-            d.B[l] = LevelView{Pb->iw[l], Pb->wp[l], Pb->w[l], Pb->h[l], (float)Pb->fx[l],
-                               (float)Pb->fy[l], (float)Pb->cx[l], (float)Pb->cy[l]};
+            d.A[l] = LevelView{Pa->iw[l], Pa->wp[l], static_cast<const unsigned char*>(Pa->gm[l]),
+                               Pa->w[l], Pa->h[l], (float)Pa->fx[l], (float)Pa->fy[l],
+                               (float)Pa->cx[l], (float)Pa->cy[l]};
+            d.B[l] = LevelView{Pb->iw[l], Pb->wp[l], static_cast<const unsigned char*>(Pb->gm[l]),
+                               Pb->w[l], Pb->h[l], (float)Pb->fx[l], (float)Pb->fy[l],
+                               (float)Pb->cx[l], (float)Pb->cy[l]};
             d.stride[l] = stride[i * L + l];
             d.sw[l] = sw[i * L + l];
             d.sh[l] = sh[i * L + l];
@@ -618,6 +621,7 @@ rgbid_status build_pyramids(rgbid_ctx* c, int n, rgbid_pyr* const* pyrs, const f
         for (int l = 0; l < p->levels; ++l) {
             f.iw[l] = p->iw[l];
             f.wp[l] = p->wp[l];
+            f.gm[l] = p->gm[l];
             f.w[l] = p->w[l];
             f.h[l] = p->h[l];
             mw[l] = std::max(mw[l], p->w[l]);
@@ -726,16 +730,18 @@ rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rg
     p->levels = levels;
     p->f16 = storage == RGBID_F16;
     const size_t e_iw = p->f16 ? 4 : 8, e_wp = p->f16 ? 2 : 4;
-    size_t off[2 * kMaxLevels], total = 0;
+    size_t off[3 * kMaxLevels], total = 0;
     for (int l = 0; l < levels; ++l) {
         p->w[l] = cam->width >> l;
         p->h[l] = cam->height >> l;
         level_camera(*cam, l, p->fx[l], p->fy[l], p->cx[l], p->cy[l]);
         const size_t np = (size_t)p->w[l] * p->h[l];
-        off[2 * l] = total;
+        off[3 * l] = total;
         total = align_up(total + np * e_iw, 256);
-        off[2 * l + 1] = total;
+        off[3 * l + 1] = total;
         total = align_up(total + np * e_wp, 256);
+        off[3 * l + 2] = total;
+        total = align_up(total + np, 256);
     }
     hipError_t e = hipMalloc(&p->base, total);
     if (e != hipSuccess) {
@@ -743,8 +749,9 @@ rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rg
         return set_err(c, RGBID_E_NOMEM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
     }
     for (int l = 0; l < levels; ++l) {
-        p->iw[l] = static_cast<char*>(p->base) + off[2 * l];
-        p->wp[l] = static_cast<char*>(p->base) + off[2 * l + 1];
+        p->iw[l] = static_cast<char*>(p->base) + off[3 * l];
+        p->wp[l] = static_cast<char*>(p->base) + off[3 * l + 1];
+        p->gm[l] = static_cast<char*>(p->base) + off[3 * l + 2];
     }
     rgbid_pyr* const arr[1] = {p};
     const float* const Is[1] = {I_dev};

@@ -76,6 +76,37 @@ __global__ void __launch_bounds__(256) k_down(const PyrFrame* __restrict__ frame
 }
 
 template <bool F16>
+__device__ __forceinline__ float load_wp(const void* p, int i)
+{
+    if constexpr (F16) return __half2float(static_cast<const __half*>(p)[i]);
+    else return static_cast<const float*>(p)[i];
+}
+
+// Validity flags of a level used by the residuals (sec. 6.2): bit 0 = the
+// pixel is interior (one pixel from every border) with a valid W, bit 1 =
+// bit 0 and the four W neighbours valid, i.e. the central-difference gradient
+// of W is defined.
+template <bool F16>
+__global__ void __launch_bounds__(256) k_mask(const PyrFrame* __restrict__ frames, int level)
+{
+    const PyrFrame& f = frames[blockIdx.y];
+    if (level >= f.levels) return;
+    const int w = f.w[level], h = f.h[level];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= w * h) return;
+    const int v = i / w, u = i - v * w;
+    const void* wp = f.wp[level];
+    unsigned char m = 0;
+    if (u >= 1 && v >= 1 && u <= w - 2 && v <= h - 2 && w_valid(load_wp<F16>(wp, i))) {
+        m = 1;
+        if (w_valid(load_wp<F16>(wp, i - 1)) && w_valid(load_wp<F16>(wp, i + 1)) &&
+            w_valid(load_wp<F16>(wp, i - w)) && w_valid(load_wp<F16>(wp, i + w)))
+            m = 3;
+    }
+    static_cast<unsigned char*>(f.gm[level])[i] = m;
+}
+
+template <bool F16>
 __global__ void __launch_bounds__(256) k_read(const void* __restrict__ iw, int n, float* I, float* W)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,6 +134,13 @@ hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes
         dim3 grid((n + 255) / 256, nframes);
         if (f16) hipLaunchKernelGGL(k_down<true>, grid, dim3(256), 0, s, frames_dev, l);
         else hipLaunchKernelGGL(k_down<false>, grid, dim3(256), 0, s, frames_dev, l);
+    }
+    for (int l = 0; l < levels; ++l) {
+        const int n = max_w[l] * max_h[l];
+        if (n <= 0) break;
+        dim3 grid((n + 255) / 256, nframes);
+        if (f16) hipLaunchKernelGGL(k_mask<true>, grid, dim3(256), 0, s, frames_dev, l);
+        else hipLaunchKernelGGL(k_mask<false>, grid, dim3(256), 0, s, frames_dev, l);
     }
     return hipGetLastError();
 }

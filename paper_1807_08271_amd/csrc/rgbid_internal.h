@@ -33,6 +33,8 @@ constexpr int warp_pixels_per_pass(int log2b) { return 64 / warp_lanes_per_pixel
 struct LevelView {
     const void* iw;   // interleaved (I, W): float2 or __half2, w*h, dense rows
     const void* wp;   // W plane: float or __half, w*h
+    const unsigned char* gm;   // per pixel: bit 0 interior with valid W, bit 1 also
+                               // the four W neighbours valid (gradient defined)
     int w, h;
     float fx, fy, cx, cy;
 };
@@ -98,6 +100,7 @@ struct PyrFrame {
     long long pitch;                // elements
     void* iw[kMaxLevels];
     void* wp[kMaxLevels];
+    void* gm[kMaxLevels];
     int w[kMaxLevels], h[kMaxLevels];
     int levels;
     int pad;
