@@ -215,12 +215,6 @@ __device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa,
     return warp_finish(G, T, Io, Wo);
 }
 
-template <bool F16>
-__device__ __forceinline__ bool warp_px(const Geom& G, int u, int v, float& Io, float& Wo)
-{
-    return warp_core<F16>(G, u, v, load_w<F16>(G.WA, __umul24(v, G.w) + u), Io, Wo);
-}
-
 // Warp-level coordinates of the children this lane handles in one pass, and
 // their W_A (loaded ahead so the next pass's loads overlap this pass's
 // gathers).

@@ -86,13 +86,22 @@ __device__ __forceinline__ float load_wp(const void* p, int i)
 // pixel is interior (one pixel from every border) with a valid W, bit 1 =
 // bit 0 and the four W neighbours valid, i.e. the central-difference gradient
 // of W is defined.
+// Workgroups are dealt to the 8 XCDs in turn, each with its own L2; this
+// maps consecutive row ranges of an image to one XCD so that the stencil's
+// neighbouring rows are found in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
 template <bool F16>
 __global__ void __launch_bounds__(256) k_mask(const PyrFrame* __restrict__ frames, int level)
 {
     const PyrFrame& f = frames[blockIdx.y];
     if (level >= f.levels) return;
     const int w = f.w[level], h = f.h[level];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= w * h) return;
     const int v = i / w, u = i - v * w;
     const void* wp = f.wp[level];
