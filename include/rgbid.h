@@ -199,6 +199,20 @@ rgbid_status rgbid_align_batch(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
                                const rgbid_align_params* params, rgbid_pose* out,
                                rgbid_align_stats* stats);
 
+/* Asynchronous form of rgbid_align_batch for callers that keep results on
+   the device (serving loops, pipelines that enqueue the next batch while
+   this one runs): the same computation, but the n poses and (if stats_dev
+   != NULL) the n statistics are written to caller-owned device memory in
+   the layouts above, and the call returns as soon as the work is enqueued
+   on the context's stream.  init is host memory (n poses or NULL), read
+   before the call returns.  Pyramids and output buffers must stay alive
+   until the stream reaches this work.  Errors (argument checks only):
+   E_ARG, E_SHAPE, E_NOMEM, E_DEVICE. */
+rgbid_status rgbid_align_batch_async(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
+                                     const rgbid_pyr* const* B, const rgbid_pose* init,
+                                     const rgbid_align_params* params, rgbid_pose* out_dev,
+                                     rgbid_align_stats* stats_dev);
+
 /* One linearisation without an update: the normal equations of the pair at
    pyramid level `level` and pose T, with the same sampling and weights as an
    alignment iteration (diagnostic; also the Hessian for a covariance).

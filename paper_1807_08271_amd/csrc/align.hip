@@ -1169,6 +1169,54 @@ hipError_t launch_iteration(hipStream_t s, const IterLaunch& L, hipEvent_t const
     return L.f16 ? launch_iteration_f<true>(s, L, ev) : launch_iteration_f<false>(s, L, ev);
 }
 
+namespace {
+
+// Per-pair results in the public layouts, written to device memory (the
+// asynchronous batch call): the pose and the statistics of the last
+// linearisation, field by field as the synchronous call fills them on the host.
+__global__ void __launch_bounds__(64) k_export(const PairState* __restrict__ states, int n,
+                                               rgbid_pose* out, rgbid_align_stats* stats)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PairState& s = states[i];
+    if (out) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[i].R[k] = s.R[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[i].t[k] = s.t[k];
+    }
+    if (stats) {
+        rgbid_align_stats& o = stats[i];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) o.H[k] = s.H[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o.g[k] = s.g[k];
+        o.mu_I = s.mu[0];
+        o.sigma_I = s.sigma[0];
+        o.nu_I = s.nu[0];
+        o.mu_W = s.mu[1];
+        o.sigma_W = s.sigma[1];
+        o.nu_W = s.nu[1];
+        o.cost = s.cost;
+        o.n_valid_I = s.nI;
+        o.n_valid_W = s.nW;
+#pragma unroll
+        for (int l = 0; l < 8; ++l) o.iters_done[l] = l < kMaxLevels ? s.iters_done[l] : 0;
+        o.status = s.status;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_export(hipStream_t s, const PairState* states, int n, rgbid_pose* out,
+                         rgbid_align_stats* stats)
+{
+    if (n <= 0 || (!out && !stats)) return hipSuccess;
+    hipLaunchKernelGGL(k_export, dim3((n + 63) / 64), dim3(64), 0, s, states, n, out, stats);
+    return hipGetLastError();
+}
+
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs)
 {
     hipLaunchKernelGGL(k_level_start, dim3((npairs + 63) / 64), dim3(64), 0, s, states, npairs);

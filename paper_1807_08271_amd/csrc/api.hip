@@ -272,7 +272,8 @@ rgbid_status ensure_chain_streams(rgbid_ctx* c, int nch)
 rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgbid_pyr* const* B,
                        const rgbid_pose* init, const rgbid_align_params* P,
                        const std::vector<Step>& sched, int update, rgbid_pose* out,
-                       rgbid_align_stats* stats, float* launch_ms = nullptr)
+                       rgbid_align_stats* stats, float* launch_ms = nullptr,
+                       bool device_out = false)
 {
     if (!c) return RGBID_E_ARG;
     if (n < 1 || !A || !B) return set_err(c, RGBID_E_ARG, "need n >= 1 and pyramid arrays");
@@ -559,6 +560,13 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     }
 
     // ---- results
+    if (device_out && !c->profiling && !launch_ms) {
+        // asynchronous form: results stay in device memory, nothing waits
+        HIPCHK(c, launch_export(c->stream, static_cast<const PairState*>(c->states.p), n, out, stats));
+        return RGBID_OK;
+    }
+    if (device_out) HIPCHK(c, launch_export(c->stream, static_cast<const PairState*>(c->states.p), n,
+                                            out, stats));
     if ((st = ensure_down(c, states_bytes)) != RGBID_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->h_down, c->states.p, states_bytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -574,6 +582,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                 }
     }
     if (launch_ms) HIPCHK(c, hipEventElapsedTime(launch_ms, c->tev[0], c->tev[1]));
+    if (device_out) return RGBID_OK;
     const PairState* res = static_cast<const PairState*>(c->h_down);
     for (int i = 0; i < n; ++i) {
         const PairState& s = res[i];
@@ -835,6 +844,22 @@ rgbid_status rgbid_align_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
     for (int l = P->levels - 1; l >= 0; --l)
         if (P->iters[l] > 0) sched.push_back(Step{l, P->iters[l]});
     return run_batch(c, n, A, B, init, P, sched, 1, out, stats);
+}
+
+rgbid_status rgbid_align_batch_async(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
+                                     const rgbid_pyr* const* B, const rgbid_pose* init,
+                                     const rgbid_align_params* P, rgbid_pose* out_dev,
+                                     rgbid_align_stats* stats_dev)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out_dev) return set_err(c, RGBID_E_ARG, "out_dev is NULL");
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<Step> sched;
+    for (int l = P->levels - 1; l >= 0; --l)
+        if (P->iters[l] > 0) sched.push_back(Step{l, P->iters[l]});
+    return run_batch(c, n, A, B, init, P, sched, 1, out_dev, stats_dev, nullptr, true);
 }
 
 rgbid_status rgbid_align(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B,

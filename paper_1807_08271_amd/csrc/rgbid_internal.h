@@ -132,6 +132,8 @@ struct IterLaunch {
 // the four kernels (for per-kernel timing).
 hipError_t launch_iteration(hipStream_t s, const IterLaunch& L, hipEvent_t const* ev);
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs);
+hipError_t launch_export(hipStream_t s, const PairState* states, int n, rgbid_pose* out,
+                         rgbid_align_stats* stats);
 
 struct FuseArgs {
     float* Wkf;

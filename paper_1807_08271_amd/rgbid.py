@@ -133,6 +133,9 @@ _SIGS = {
     "rgbid_align_batch": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
                                     C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
                                     C.POINTER(rgbid_pose), C.POINTER(rgbid_align_stats)]),
+    "rgbid_align_batch_async": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                          C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
+                                          _P, _P]),
     "rgbid_normal_equations": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(rgbid_pose),
                                          C.POINTER(rgbid_align_params),
                                          C.POINTER(rgbid_align_stats)]),
@@ -362,6 +365,41 @@ def rgbid_align_batch(ctx, As, Bs, params: rgbid_align_params, inits=None):
     st = (rgbid_align_stats * n)()
     _check(ctx, lib().rgbid_align_batch(ctx, n, a, b, ini, C.byref(params), out, st))
     return [pose_tuple(out[i]) for i in range(n)], [st[i].as_dict() for i in range(n)]
+
+
+POSE_BYTES = C.sizeof(rgbid_pose)
+STATS_BYTES = C.sizeof(rgbid_align_stats)
+
+
+def rgbid_align_batch_async(ctx, As, Bs, params: rgbid_align_params, out, stats=None, inits=None):
+    """Enqueues the batch; poses (and stats) land in the device tensors out
+    (>= n * POSE_BYTES bytes) and stats (>= n * STATS_BYTES bytes).  Nothing
+    waits; read them with unpack_poses / unpack_stats after synchronising."""
+    n = len(As)
+    for t, need in ((out, n * POSE_BYTES), (stats, n * STATS_BYTES)):
+        if t is not None and (not t.is_cuda or t.numel() * t.element_size() < need):
+            raise ValueError("output buffers must be device tensors of the required size")
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    ini = None
+    if inits is not None:
+        ini = (rgbid_pose * n)(*[make_pose(*x) for x in inits])
+    _check(ctx, lib().rgbid_align_batch_async(
+        ctx, n, a, b, ini, C.byref(params), C.c_void_p(out.data_ptr()),
+        C.c_void_p(stats.data_ptr()) if stats is not None else None))
+
+
+def unpack_poses(buf, n):
+    """(R, t) list from a host copy of rgbid_align_batch_async's output."""
+    raw = bytes(buf.cpu().numpy().tobytes()[:n * POSE_BYTES])
+    arr = (rgbid_pose * n).from_buffer_copy(raw)
+    return [pose_tuple(arr[i]) for i in range(n)]
+
+
+def unpack_stats(buf, n):
+    raw = bytes(buf.cpu().numpy().tobytes()[:n * STATS_BYTES])
+    arr = (rgbid_align_stats * n).from_buffer_copy(raw)
+    return [arr[i].as_dict() for i in range(n)]
 
 
 def rgbid_normal_equations(ctx, A, B, level: int, T, params: rgbid_align_params):

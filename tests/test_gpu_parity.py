@@ -210,6 +210,36 @@ def test_align_is_deterministic(ctx, c2_pairs):
     rg.rgbid_pyramid_free(B)
 
 
+def test_align_batch_async_matches_sync(ctx, c2_pairs):
+    # the asynchronous batch writes the same poses and statistics to device
+    # memory, bit for bit, including a degenerate pair and two calls in a row
+    rg = _rg()
+    import torch
+    pairs = list(c2_pairs)
+    As = [_pyr(ctx, p.cam, 4, p.A) for p in pairs]
+    Bs = [_pyr(ctx, p.cam, 4, p.B) for p in pairs]
+    prm = _params(4, [10] * 4)
+    poses, stats = rg.rgbid_align_batch(ctx, As, Bs, prm)
+    n = len(As)
+    out = torch.zeros(n * rg.POSE_BYTES, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(n * rg.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        rg.rgbid_align_batch_async(ctx, As, Bs, prm, out, st)
+    torch.cuda.synchronize()
+    ap = rg.unpack_poses(out, n)
+    ast = rg.unpack_stats(st, n)
+    for i in range(n):
+        np.testing.assert_array_equal(ap[i][0], poses[i][0])
+        np.testing.assert_array_equal(ap[i][1], poses[i][1])
+        for key in ("H", "g", "cost", "mu_I", "sigma_I", "mu_W", "sigma_W", "n_valid_I",
+                    "n_valid_W", "iters_done", "status"):
+            np.testing.assert_array_equal(np.asarray(ast[i][key]), np.asarray(stats[i][key]), key)
+    with pytest.raises(ValueError):
+        rg.rgbid_align_batch_async(ctx, As, Bs, prm, out[:8])
+    for P in As + Bs:
+        rg.rgbid_pyramid_free(P)
+
+
 # ----------------------------------------------------------------- edge cases
 
 
