@@ -67,9 +67,42 @@ def algorithmic_bytes(level, kernel, sizes, f16, warp_fullres, fused):
     return total
 
 
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
-# (one FP32 operation per lane and cycle; packed FP32 is disabled in the build)
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# FP32 vector peak without packed math (the build disables packed FP32):
+# 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s; the published
+# 157.3 TFLOP/s counts packed FP32.
+FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# VALU issue: one wave64 instruction per SIMD every 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+# Algorithmic FP32 flops (an FMA counts 2) the method needs, per unit:
+#   a warped full-resolution child: ray and rotation 22, projection 8,
+#   bilinear weights 6 and two 4-tap interpolations 16, W* 5  -> 57;
+#   its share of the level mean (two channels)                 -> 2;
+#   a level pixel's residual terms: residuals 2, gradients 8, two Jacobians
+#   38, lambda_n 12, two robust weights 12, two rank-one updates of the
+#   21 + 6 + 1 sums (w J, then FMAs) 124                       -> 196;
+#   a sample residual pair                                      -> 2.
+FLOPS_CHILD, FLOPS_MEAN, FLOPS_TERMS, FLOPS_SAMPLE = 57, 2, 196, 2
+
+
+def algorithmic_flops(level, kernel, sizes, warp_fullres, fused):
+    """FP32 flops of one launch of (level, kernel) over the batch."""
+    total = 0
+    for w0, h0 in sizes:
+        n0 = w0 * h0
+        nl = (w0 >> level) * (h0 >> level)
+        nw = n0 if warp_fullres else nl
+        if kernel == "reduce":
+            total += nl * FLOPS_TERMS
+            if fused:
+                total += nw * (FLOPS_CHILD + (FLOPS_MEAN if nw != nl else 0))
+        elif kernel == "warp":
+            if fused:
+                return None
+            total += nw * (FLOPS_CHILD + (FLOPS_MEAN if nw != nl else 0)) + nl * FLOPS_SAMPLE
+        else:
+            return None
+    return total
 
 
 def counter_summary():
@@ -350,28 +383,28 @@ def main():
     dom = max((r for r in rows if r[4] is not None), key=lambda r: r[0])
     _, lvl, kname, avg_us, b = dom
     achieved = b / (avg_us * 1e-6) / 1e9
+    fused = fused_level.get(lvl, lvl == 0)
+    fl = algorithmic_flops(lvl, kname, sizes, fullres, fused)
+    tflops = fl / (avg_us * 1e-6) / 1e12 if fl else 0.0
     cs = None if mixed else counter_summary()
     ent = (cs or {}).get("kernels", {}).get("%s_l%d" % (kname, lvl))
     traffic = ent["hbm_bytes_per_launch"] if ent else None
-    roofline = {"bound": "hbm", "kernel": "k_%s level %d" % (kname, lvl),
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": b, "avg_launch_us": round(avg_us, 2)}
-    roofline["hbm_GBs"] = round(achieved, 1)
+    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    alu = {"achieved": round(tflops, 2), "peak": round(FP32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+           "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "flops_per_launch": fl}
+    # the roof with the larger fraction binds
+    top = alu if alu["frac"] > hbm["frac"] else hbm
+    roofline = {"bound": "alu" if top is alu else "hbm", "kernel": "k_%s level %d" % (kname, lvl),
+                "achieved": top["achieved"], "peak": top["peak"], "unit": top["unit"],
+                "frac": top["frac"], "traffic": traffic, "bytes_per_launch": b,
+                "avg_launch_us": round(avg_us, 2), "hbm": hbm, "alu": alu}
     if traffic:
-        roofline["measured_GBs"] = round(traffic / (avg_us * 1e-6) / 1e9, 1)
+        hbm["measured_GBs"] = round(traffic / (avg_us * 1e-6) / 1e9, 1)
     if ent and ent.get("valu_insts_per_launch"):
-        # executed wave instructions x 64 lanes / live duration, against the
-        # VALU issue peak: when this is the larger fraction the kernel is
-        # bound by arithmetic issue, not by HBM
-        gops = ent["valu_insts_per_launch"] * 64 / (avg_us * 1e-6) / 1e9
-        alu = {"achieved": round(gops, 1), "peak": VALU_PEAK_GOPS, "unit": "G lane-ops/s",
-               "frac": round(gops / VALU_PEAK_GOPS, 4)}
-        roofline["valu"] = alu
-        if alu["frac"] > roofline["frac"]:
-            roofline.update({"bound": "alu", "achieved": alu["achieved"], "peak": alu["peak"],
-                             "unit": alu["unit"], "frac": alu["frac"],
-                             "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)})
+        # executed VALU wave instructions against one per SIMD every 4 cycles
+        alu["valu_issue_frac"] = round(ent["valu_insts_per_launch"] / (avg_us * 1e-6) /
+                                       VALU_ISSUE_PEAK, 4)
 
     value = args.pairs * args.steps / dt
     out = {
