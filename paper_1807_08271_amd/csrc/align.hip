@@ -682,28 +682,17 @@ __device__ __forceinline__ double nu_equation_const(double n, double nud)
                 log(0.5 * (nud + 1.0)));
 }
 
-// The sample after compaction: element q of a thread is a valid residual for
-// q < full, and for q == full in threads t < rem; nothing after that.
-struct Compact {
-    int full, rem;
-};
-
-__device__ __forceinline__ bool element_valid(const Compact& cp, int q)
-{
-    return q < cp.full || (q == cp.full && (int)threadIdx.x < cp.rem);
-}
-
 // The location / scale fixed point with nu = 5 (Student-t) or the Huber
 // threshold k: every step sums w, w d and w d^2 (d = r - mu, weights from
 // the previous estimate) over the block and moves mu by S1/S0, sigma^2 to
-// (S2 - S1^2/S0)/n.  The sample is compacted, so whole rounds of elements
-// need no validity test; two partial sums per lane in a fixed order.
-// bc[0..2] broadcast mu, sigma and 1/sigma.
+// (S2 - S1^2/S0)/n.  Branch-free per element (padding entries get w = 0;
+// entries past `per` are padding in every thread and skipped); two partial
+// sums per lane in a fixed order.  bc[0..2] broadcast mu, sigma and 1/sigma.
 template <int KIND>
-__device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThread],
-                                                  const Compact& cp, double n, float floor_s,
-                                                  float k, int iters, float* part, double* bc,
-                                                  double& mu, double& sigma)
+__device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThread], int per,
+                                                  double n, float floor_s, float k, int iters,
+                                                  float* part, double* bc, double& mu,
+                                                  double& sigma)
 {
     const int wave = threadIdx.x >> 6;
     float fmu = (float)mu, isg = (float)(1.0 / sigma);
@@ -715,17 +704,14 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThre
         float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < kScalePerThread; ++q) {
-            if (q <= cp.full) {
+            if (q < per) {
+                const bool ok = r[q] == r[q];
                 const float d = r[q] - fmu;
                 float w;
                 if constexpr (KIND == RGBID_W_HUBER) w = fminf(1.0f, hk * rcp(fabsf(d)));
                 else w = tA * rcp(fmaf(d, d, tB));
-                float dd = d;
-                if (q == cp.full) {      // the partial last round
-                    const bool ok = (int)threadIdx.x < cp.rem;
-                    w = ok ? w : 0.0f;
-                    dd = ok ? d : 0.0f;
-                }
+                w = ok ? w : 0.0f;
+                const float dd = ok ? d : 0.0f;
                 s0[q & 1] += w;
                 s1[q & 1] = fmaf(w, dd, s1[q & 1]);
                 s2[q & 1] = fmaf(w * dd, dd, s2[q & 1]);
@@ -738,11 +724,11 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThre
             // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
             const double dm = tot[1] / tot[0];
             const double var = fmax((tot[2] - tot[1] * dm) / n, 0.0);
-            const double sgd = fmax(sqrt(var), (double)floor_s);
+            const double sg = fmax(sqrt(var), (double)floor_s);
             if (threadIdx.x == 0) {
                 bc[0] = mu + dm;
-                bc[1] = sgd;
-                bc[2] = 1.0 / sgd;
+                bc[1] = sg;
+                bc[2] = 1.0 / sg;
             }
         }
         __syncthreads();
@@ -759,60 +745,33 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThre
 // mu = 0, sigma^2 = mean r^2, with nu = 5 for Student-t; then (Student-t with
 // estimation) nu by bisection of the nu equation on [2, 10] with the
 // normalised residuals frozen: f(10) > 0 gives 10, f(2) < 0 gives 2, else 30
-// halvings of [2, 10] and the midpoint.  The valid residuals are first packed
-// through LDS (block prefix sum of the per-thread counts), in a fixed order.
+// halvings of [2, 10] and the midpoint.
 __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
 {
     __shared__ float part[16 * 3];
     __shared__ double bc[4];
-    __shared__ float packed[kMaxSample];
     const int p = blockIdx.x, ch = blockIdx.y;
     PairState& S = L.states[p];
     if (!S.active || S.level_stop) return;
     const PairDesc& D = L.pairs[p];
     const int n_all = D.sw[L.level] * D.sh[L.level];
     const int per = (n_all + kScaleThreads - 1) / kScaleThreads;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
     const float floor_s = ch == 0 ? 1e-3f : 1e-6f;
     float r[kScalePerThread];
-    int cnt = 0;
+    float cs[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < kScalePerThread; ++k) {
         const int i = threadIdx.x + k * kScaleThreads;
         float x = __int_as_float(0x7fc00000);
-        if (k < per && i < n_all) {
+        if (i < n_all) {
             const float2 e = load_f2(D.sample, i);
             x = ch == 0 ? e.x : e.y;
         }
         r[k] = x;
-        cnt += x == x ? 1 : 0;
-    }
-    // exclusive block prefix of the counts: wave scan (lane i holds lanes
-    // 0..i), then the totals of the earlier waves
-    const float incl = wave_sum_to_last((float)cnt);
-    if (lane == 63) part[wave] = incl;
-    __syncthreads();
-    float before = 0.0f, all = 0.0f;
-    for (int w = 0; w < nw; ++w) {
-        const float t = part[w];
-        before += w < wave ? t : 0.0f;
-        all += t;
-    }
-    int pos = (int)(before + incl) - cnt;
-#pragma unroll
-    for (int k = 0; k < kScalePerThread; ++k)
-        if (r[k] == r[k]) packed[pos++] = r[k];
-    __syncthreads();
-    const int nv = (int)all;
-    const Compact cp{nv / kScaleThreads, nv % kScaleThreads};
-    float cs[2] = {0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < kScalePerThread; ++k) {
-        const bool ok = element_valid(cp, k);
-        const float x = ok ? packed[threadIdx.x + k * kScaleThreads] : 0.0f;
-        r[k] = x;
+        const bool ok = x == x;
         cs[0] += ok ? 1.0f : 0.0f;
-        cs[1] = fmaf(x, x, cs[1]);
+        cs[1] = ok ? fmaf(x, x, cs[1]) : cs[1];
     }
     {
         double t[2];
@@ -828,17 +787,17 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     float nu = 5.0f;
     if (n > 0.0) {
         if (L.ip.weight == RGBID_W_HUBER)
-            scale_fixed_point<RGBID_W_HUBER>(r, cp, n, floor_s, L.ip.huber_k, L.ip.scale_iters,
+            scale_fixed_point<RGBID_W_HUBER>(r, per, n, floor_s, L.ip.huber_k, L.ip.scale_iters,
                                              part, bc, mu, sigma);
         else
-            scale_fixed_point<RGBID_W_STUDENT_T>(r, cp, n, floor_s, L.ip.huber_k,
+            scale_fixed_point<RGBID_W_STUDENT_T>(r, per, n, floor_s, L.ip.huber_k,
                                                  L.ip.scale_iters, part, bc, mu, sigma);
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
             const float fmu = (float)mu, isg = (float)(1.0 / sigma);
 #pragma unroll
             for (int q = 0; q < kScalePerThread; ++q) {
                 const float x = (r[q] - fmu) * isg;
-                r[q] = x * x;     // r now holds x^2
+                r[q] = x * x;     // r now holds x^2 (NaN stays NaN)
             }
             // evaluations f(10), f(2), then up to 30 bisection steps; the
             // bracket lives in wave 0, the next nu and the stop flag reach
@@ -849,9 +808,9 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
                 float e2[2] = {0.0f, 0.0f};
 #pragma unroll
                 for (int q = 0; q < kScalePerThread; ++q) {
-                    if (q <= cp.full) {
-                        // an empty slot takes w = 1, whose term 1 + ln 1 - 1 is 0
-                        const float w = element_valid(cp, q) ? (nf + 1.0f) / (nf + r[q]) : 1.0f;
+                    if (q < per) {
+                        // a padding entry (NaN) takes w = 1, whose term 1 + ln 1 - 1 is 0
+                        const float w = r[q] == r[q] ? (nf + 1.0f) / (nf + r[q]) : 1.0f;
                         e2[q & 1] += 1.0f + logf(w) - w;
                     }
                 }
