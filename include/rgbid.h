@@ -139,7 +139,8 @@ const char* rgbid_last_error(const rgbid_ctx* ctx);
    The input is copied (not aliased) and may be released when the call
    returns; the call does not synchronise.  *out is library-owned; free it
    with rgbid_pyramid_free.  Errors: E_ARG (NULL, levels outside 1..8, a
-   level smaller than 1x1), E_NOMEM, E_DEVICE. */
+   level smaller than 1x1, 2^22 = 4194304 pixels or more), E_NOMEM,
+   E_DEVICE. */
 rgbid_status rgbid_pyramid(rgbid_ctx* ctx, const rgbid_camera* cam, int levels,
                            rgbid_format storage, const float* I_dev, const float* W_dev,
                            size_t pitch_elems, rgbid_pyr** out);

@@ -68,6 +68,28 @@ __device__ __forceinline__ float2 load_iw(const void* p, unsigned i)
     }
 }
 
+// (I, W) texel at byte offset off of an interleaved plane.
+template <bool F16>
+__device__ __forceinline__ float2 load_iw_at(const void* p, unsigned off)
+{
+    const RGBID_GLOBAL char* b = (const RGBID_GLOBAL char*)p + off;
+    if constexpr (F16) {
+        const h2v h = *(const RGBID_GLOBAL h2v*)b;
+        return make_float2((float)h.x, (float)h.y);
+    } else {
+        const f2v f = *(const RGBID_GLOBAL f2v*)b;
+        return make_float2(f.x, f.y);
+    }
+}
+
+// floor(x) as an integer (v_cvt_flr_i32_f32) for |x| < 2^31.
+__device__ __forceinline__ int floor_i(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 template <bool F16>
 __device__ __forceinline__ float load_w(const void* p, unsigned i)
 {
@@ -89,14 +111,15 @@ __device__ __forceinline__ void store_f2(void* p, size_t i, float a, float b)
     gmut<f2v>(p)[i] = v;
 }
 
-// Row / column of raster index idx in a grid of width gw (idx < 2^24).
-__device__ __forceinline__ void split_index(int idx, int gw, float inv_gw, int& gu, int& gv)
+// Row / column of raster index idx in a grid of width gw, with inv_gw =
+// 1/gw and half_inv = 1/(2 gw): the row is floor((idx + 1/2) / gw) formed in
+// FP32, whose fraction stays 1/(2 gw) away from an integer, more than the
+// rounding error for idx < 2^22.
+__device__ __forceinline__ void split_index(int idx, int gw, float inv_gw, float half_inv, int& gu,
+                                            int& gv)
 {
-    int v = (int)((float)idx * inv_gw);
-    int u = idx - (int)__umul24((unsigned)v, (unsigned)gw);
-    if (u < 0) { u += gw; --v; }
-    else if (u >= gw) { u -= gw; ++v; }
-    gu = u;
+    const int v = (int)fmaf((float)idx, inv_gw, half_inv);
+    gu = idx - (int)__umul24((unsigned)v, (unsigned)gw);
     gv = v;
 }
 
@@ -108,34 +131,10 @@ __device__ __forceinline__ int chunk_of_block(int b, int n, int remap)
     return x * q + min(x, r) + k;
 }
 
-// Warp parameters of one pair at the warp level.
-struct Geom {
-    float m[9];       // R^T
-    float q[3];       // R^T t
-    float fx, fy, cx, cy, ifx, ify;
-    int w, h;
-    const void* WA;   // W plane of A at the warp level
-    const void* Biw;  // interleaved (I, W) of B at the warp level
-};
-
-__device__ __forceinline__ Geom make_geom(const PairState& S, const LevelView& A, const LevelView& B)
+// A value every lane holds alike, moved to a scalar register.
+__device__ __forceinline__ float uniform_f(float x)
 {
-    Geom G;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) G.m[k] = S.RT[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) G.q[k] = S.Rtt[k];
-    G.fx = A.fx;
-    G.fy = A.fy;
-    G.cx = A.cx;
-    G.cy = A.cy;
-    G.ifx = 1.0f / A.fx;
-    G.ify = 1.0f / A.fy;
-    G.w = A.w;
-    G.h = A.h;
-    G.WA = A.wp;
-    G.Biw = B.iw;
-    return G;
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
 // Reciprocal and reciprocal square root (v_rcp_f32 / v_rsq_f32, 1 ulp) for
@@ -143,13 +142,120 @@ __device__ __forceinline__ Geom make_geom(const PairState& S, const LevelView& A
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// Inverse geometric warp of one pixel (u, v) of A (sec. 5.3) with w_a =
-// W_A(u, v) already loaded.  With x = K^-1 p,
-// W_A(p) * R^T (x / w_a - t) = R^T x - w_a R^T t locates p_B; I* is the
-// bilinear I_B(p_B) and W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) with w_b the
-// bilinear W_B(p_B).  Valid iff w_a valid, in front, p_B in
-// [-0.5, w-0.5) x [-0.5, h-0.5), four valid W taps and W* positive and
-// finite.  Branch-free: the four taps are always loaded (at clamped, in-bounds
+// Grid of a level for the pixel kernels: the full level grid, or the sample
+// grid (every s-th pixel in both directions).
+struct GridDim {
+    int gw, n, gs;
+    float inv_gw, half_inv;
+};
+
+__device__ __forceinline__ GridDim level_grid(const LevelView& A)
+{
+    GridDim d;
+    d.gw = A.w;
+    d.n = A.w * A.h;
+    d.gs = 1;
+    d.inv_gw = uniform_f(1.0f / (float)A.w);
+    d.half_inv = uniform_f(0.5f * d.inv_gw);
+    return d;
+}
+
+__device__ __forceinline__ GridDim sample_grid(const PairDesc& D, int l)
+{
+    GridDim d;
+    d.gw = D.sw[l];
+    d.n = D.sw[l] * D.sh[l];
+    d.gs = D.stride[l];
+    d.inv_gw = uniform_f(1.0f / (float)D.sw[l]);
+    d.half_inv = uniform_f(0.5f * d.inv_gw);
+    return d;
+}
+
+// Pixel rays of a level: x = K^-1 (u, v, 1) = (u/fx - cx/fx, v/fy - cy/fy, 1),
+// and half the focal lengths for the central-difference gradients.
+struct LevelRay {
+    float ifx, ify, ncx, ncy, hfx, hfy;
+};
+
+__device__ __forceinline__ LevelRay level_ray(const LevelView& A)
+{
+    LevelRay R;
+    R.ifx = uniform_f(1.0f / A.fx);
+    R.ify = uniform_f(1.0f / A.fy);
+    R.ncx = uniform_f(-A.cx * R.ifx);
+    R.ncy = uniform_f(-A.cy * R.ify);
+    R.hfx = 0.5f * A.fx;
+    R.hfy = 0.5f * A.fy;
+    return R;
+}
+
+__device__ __forceinline__ float ray_x(const LevelRay& R, int u) { return fmaf((float)u, R.ifx, R.ncx); }
+__device__ __forceinline__ float ray_y(const LevelRay& R, int v) { return fmaf((float)v, R.ify, R.ncy); }
+
+// Warp parameters of one pair at the warp level.  The first two rows of R^T
+// are scaled by fx and fy: a ray x maps to a = (fx (R^T x)_x, fy (R^T x)_y,
+// (R^T x)_z), and with q = (fx (R^T t)_x, fy (R^T t)_y, (R^T t)_z) the point
+// W_A R^T (x / W_A - t) projects to (cx + (a_x - W_A q_x) / z,
+// cy + (a_y - W_A q_y) / z), z = a_z - W_A q_z.  su, sv: the change of a per
+// pixel step in u and in v.
+struct Geom {
+    float m[9];
+    float q[3];
+    float su[3], sv[3];
+    float cx, cy, ulim, vlim;   // ulim = w - 1/2, vlim = h - 1/2
+    LevelRay ray;
+    int w, h;
+    unsigned texb, rowb;        // bytes per texel and per row of B's (I, W) plane
+    const void* WA;   // W plane of A at the warp level
+    const void* Biw;  // interleaved (I, W) of B at the warp level
+};
+
+template <bool F16>
+__device__ __forceinline__ Geom make_geom(const PairState& S, const LevelView& A, const LevelView& B)
+{
+    Geom G;
+    G.ray = level_ray(A);
+    const float sc[3] = {A.fx, A.fy, 1.0f};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G.m[3 * r + c] = uniform_f(sc[r] * S.RT[3 * r + c]);
+        G.q[r] = uniform_f(sc[r] * S.Rtt[r]);
+        G.su[r] = uniform_f(G.m[3 * r] * G.ray.ifx);
+        G.sv[r] = uniform_f(G.m[3 * r + 1] * G.ray.ify);
+    }
+    G.cx = A.cx;
+    G.cy = A.cy;
+    G.ulim = uniform_f((float)A.w - 0.5f);
+    G.vlim = uniform_f((float)A.h - 0.5f);
+    G.w = A.w;
+    G.h = A.h;
+    G.texb = F16 ? 4u : 8u;
+    G.rowb = G.texb * (unsigned)A.w;
+    G.WA = A.wp;
+    G.Biw = B.iw;
+    return G;
+}
+
+struct Ray3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ Ray3 rotate_ray(const Geom& G, float xu, float xv)
+{
+    Ray3 a;
+    a.x = fmaf(G.m[0], xu, fmaf(G.m[1], xv, G.m[2]));
+    a.y = fmaf(G.m[3], xu, fmaf(G.m[4], xv, G.m[5]));
+    a.z = fmaf(G.m[6], xu, fmaf(G.m[7], xv, G.m[8]));
+    return a;
+}
+
+// Inverse geometric warp of one pixel of A (sec. 5.3) from its rotated ray a
+// and w_a = W_A at the pixel.  I* is the bilinear I_B at the projection p_B
+// and W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) with w_b the bilinear W_B.
+// Valid iff w_a valid, in front, p_B in [-0.5, w-0.5) x [-0.5, h-0.5), four
+// valid W taps and W* positive and finite; I* and W* are undefined otherwise.
+// Branch-free: the four taps are always loaded (at clamped, in-bounds
 // addresses).  Split in two phases so that a lane can issue the tap loads of
 // all its pixels before it consumes any of them.
 struct WarpTaps {
@@ -159,76 +265,84 @@ struct WarpTaps {
 };
 
 template <bool F16>
-__device__ __forceinline__ void warp_fetch(const Geom& G, int u, int v, float wa, WarpTaps& T)
+__device__ __forceinline__ void warp_fetch(const Geom& G, const Ray3& a, float wa, WarpTaps& T)
 {
-    bool ok = w_valid(wa);
-    const float rx = ((float)u - G.cx) * G.ifx, ry = ((float)v - G.cy) * G.ify;
-    const float ax = fmaf(G.m[0], rx, fmaf(G.m[1], ry, G.m[2]));
-    const float ay = fmaf(G.m[3], rx, fmaf(G.m[4], ry, G.m[5]));
-    const float az = fmaf(G.m[6], rx, fmaf(G.m[7], ry, G.m[8]));
-    const float yx = fmaf(-wa, G.q[0], ax), yy = fmaf(-wa, G.q[1], ay), yz = fmaf(-wa, G.q[2], az);
-    ok = ok && yz > 0.0f;
+    const float yx = fmaf(-wa, G.q[0], a.x), yy = fmaf(-wa, G.q[1], a.y);
+    const float yz = fmaf(-wa, G.q[2], a.z);
     const float iz = rcp(yz);
-    float ub = fmaf(G.fx * yx, iz, G.cx), vb = fmaf(G.fy * yy, iz, G.cy);
-    ok = ok && ub >= -0.5f && ub < (float)G.w - 0.5f && vb >= -0.5f && vb < (float)G.h - 0.5f;
+    float ub = fmaf(yx, iz, G.cx), vb = fmaf(yy, iz, G.cy);
+    const bool ok = (int)w_valid(wa) & (yz > 0.0f) & (ub >= -0.5f) & (ub < G.ulim) &
+                    (vb >= -0.5f) & (vb < G.vlim);
     ub = ok ? ub : 0.0f;
     vb = ok ? vb : 0.0f;
-    const float fu = floorf(ub), fv = floorf(vb);
-    T.a = ub - fu;
-    T.b = vb - fv;
-    T.az = az;
+    T.a = __builtin_amdgcn_fractf(ub);
+    T.b = __builtin_amdgcn_fractf(vb);
+    T.az = a.z;
     T.ok = ok;
-    // taps: x0 = floor(u_B) (>= -1 in bounds), clamped to the image
-    const int xf = (int)fu, yf = (int)fv;
+    // taps x0 = floor(u_B) (>= -1 in bounds) and x0 + 1, each clamped to
+    // the image: the second tap is one texel on iff 0 <= x0 < w - 1
+    const int xf = floor_i(ub), yf = floor_i(vb);
     const unsigned x0 = (unsigned)max(xf, 0), y0 = (unsigned)max(yf, 0);
-    const unsigned dx = xf + 1 <= G.w - 1 && xf >= 0 ? 1u : 0u;
-    const unsigned dy = yf + 1 <= G.h - 1 && yf >= 0 ? (unsigned)G.w : 0u;
-    const unsigned i00 = __umul24(y0, (unsigned)G.w) + x0;
-    T.p00 = load_iw<F16>(G.Biw, i00);
-    T.p10 = load_iw<F16>(G.Biw, i00 + dx);
-    T.p01 = load_iw<F16>(G.Biw, i00 + dy);
-    T.p11 = load_iw<F16>(G.Biw, i00 + dy + dx);
+    const unsigned dx = (unsigned)xf < (unsigned)(G.w - 1) ? G.texb : 0u;
+    const unsigned dy = (unsigned)yf < (unsigned)(G.h - 1) ? G.rowb : 0u;
+    const unsigned o00 = __umul24(y0, G.rowb) + x0 * G.texb;
+    const unsigned o01 = o00 + dy;
+    T.p00 = load_iw_at<F16>(G.Biw, o00);
+    T.p10 = load_iw_at<F16>(G.Biw, o00 + dx);
+    T.p01 = load_iw_at<F16>(G.Biw, o01);
+    T.p11 = load_iw_at<F16>(G.Biw, o01 + dx);
 }
 
 __device__ __forceinline__ bool warp_finish(const Geom& G, const WarpTaps& T, float& Io, float& Wo)
 {
-    bool ok = T.ok && w_valid(T.p00.y) && w_valid(T.p10.y) && w_valid(T.p01.y) &&
-              w_valid(T.p11.y);
-    const float a = T.a, b = T.b;
-    const float c00 = (1.0f - a) * (1.0f - b), c10 = a * (1.0f - b);
-    const float c01 = (1.0f - a) * b, c11 = a * b;
-    const float ib = c00 * T.p00.x + c10 * T.p10.x + c01 * T.p01.x + c11 * T.p11.x;
-    const float wb = c00 * T.p00.y + c10 * T.p10.y + c01 * T.p01.y + c11 * T.p11.y;
-    const float ws = T.az * wb * rcp(fmaf(wb, G.q[2], 1.0f));
-    ok = ok && w_valid(ws);
-    Io = ok ? ib : 0.0f;
-    Wo = ok ? ws : 0.0f;
-    return ok;
+    const bool ok = T.ok & (int)w_valid(T.p00.y) & (int)w_valid(T.p10.y) &
+                    (int)w_valid(T.p01.y) & (int)w_valid(T.p11.y);
+    // bilinear: along u on both rows, then along v
+    const float i0 = fmaf(T.a, T.p10.x - T.p00.x, T.p00.x);
+    const float i1 = fmaf(T.a, T.p11.x - T.p01.x, T.p01.x);
+    const float w0 = fmaf(T.a, T.p10.y - T.p00.y, T.p00.y);
+    const float w1 = fmaf(T.a, T.p11.y - T.p01.y, T.p01.y);
+    const float wb = fmaf(T.b, w1 - w0, w0);
+    Io = fmaf(T.b, i1 - i0, i0);
+    Wo = T.az * wb * rcp(fmaf(wb, G.q[2], 1.0f));
+    return ok & (int)w_valid(Wo);
 }
 
+// Warp of one pixel with ray (xu, xv, 1) at the warp level.
 template <bool F16>
-__device__ __forceinline__ bool warp_core(const Geom& G, int u, int v, float wa, float& Io,
-                                          float& Wo)
+__device__ __forceinline__ bool warp_ray(const Geom& G, float xu, float xv, float wa, float& Io,
+                                         float& Wo)
 {
     WarpTaps T;
-    warp_fetch<F16>(G, u, v, wa, T);
+    warp_fetch<F16>(G, rotate_ray(G, xu, xv), wa, T);
     return warp_finish(G, T, Io, Wo);
 }
 
-// Warp-level coordinates of the children this lane handles in one pass, and
-// their W_A (loaded ahead so the next pass's loads overlap this pass's
-// gathers).
-template <bool F16, int CPL>
-struct PassChildren {
-    int u[CPL], v[CPL];
-    float wa[CPL];
-};
+// Sum over aligned groups of LPP lanes (a power of two), the same in every
+// lane of the group, added in a fixed tree: pairs, quads (DPP quad_perm),
+// eights (row_half_mirror), rows of 16 (row_mirror), then shuffles.
+#define RGBID_DPP_MOV(v, ctrl) \
+    __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, true))
+
+template <int LPP>
+__device__ __forceinline__ float group_sum(float v)
+{
+    if constexpr (LPP >= 2) v += RGBID_DPP_MOV(v, 0xb1);    // quad_perm [1,0,3,2]
+    if constexpr (LPP >= 4) v += RGBID_DPP_MOV(v, 0x4e);    // quad_perm [2,3,0,1]
+    if constexpr (LPP >= 8) v += RGBID_DPP_MOV(v, 0x141);   // row_half_mirror
+    if constexpr (LPP >= 16) v += RGBID_DPP_MOV(v, 0x140);  // row_mirror
+    if constexpr (LPP >= 32) v += __shfl_xor(v, 16);
+    if constexpr (LPP >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
 
 // Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
 // children at the warp level; each lane warps CPL = min(C, 4) of them (four
 // independent load chains per lane), LPP = C / CPL lanes share one pixel and
-// combine their sums with cross-lane shuffles, and GPP = 64 / LPP pixels are
-// warped per pass.
+// combine their sums across lanes, and GPP = 64 / LPP pixels are warped per
+// pass.  Lane j of a group takes children c = j + LPP m (m < CPL), child c at
+// offset (c % B, c / B) from the pixel's first child; du(m), dv(m) are the
+// offsets of the lane's m-th child from its first.
 template <int LOG2B>
 struct ChildLayout {
     static constexpr int B = 1 << LOG2B;
@@ -237,63 +351,95 @@ struct ChildLayout {
     static constexpr int LPP = warp_lanes_per_pixel(LOG2B);     // lanes per pixel
     static constexpr int GPP = warp_pixels_per_pass(LOG2B);     // pixels per pass
     static_assert(CPL * LPP == C && LPP <= 64, "at most 64 lanes per level pixel");
+    static_assert(LPP == 1 || LPP % B == 0, "a lane's children share a column");
+    static constexpr int du(int m) { return LPP == 1 ? m % B : 0; }
+    static constexpr int dv(int m) { return LPP == 1 ? m / B : (LPP / B) * m; }
 };
 
-// Children of the pixel of lane group g in the pass starting at grid pixel
-// `first` (grid of width gw, grid stride gs in level pixels), with their W_A.
+// Grid position of the pixel of lane group g in the pass that starts at grid
+// pixel `first`; past the grid end the position of the last pixel (so that
+// every derived address stays in bounds).
+struct PassPos {
+    int idx, gu, gv;
+};
+
+__device__ __forceinline__ PassPos pass_pos(int first, int g, const GridDim& gd)
+{
+    PassPos p;
+    p.idx = first + g;
+    split_index(min(p.idx, gd.n - 1), gd.gw, gd.inv_gw, gd.half_inv, p.gu, p.gv);
+    return p;
+}
+
+// The ray of the lane's first child and the W_A of all its children (loaded
+// ahead so the next pass's loads overlap this pass's gathers).
+template <int CPL>
+struct PassChildren {
+    float xu, xv;
+    float wa[CPL];
+};
+
 template <bool F16, int LOG2B>
-__device__ __forceinline__ PassChildren<F16, ChildLayout<LOG2B>::CPL>
-pass_children(const Geom& G, int first, int gw, float inv_gw, int ngrid, int gs, int lane,
-              bool load_wa = true)
+__device__ __forceinline__ PassChildren<ChildLayout<LOG2B>::CPL>
+pass_children(const Geom& G, const PassPos& p, int gs, int lane, bool load_wa = true)
 {
     using CL = ChildLayout<LOG2B>;
-    PassChildren<F16, CL::CPL> pc;
-    const int j = lane % CL::LPP, g = lane / CL::LPP;
-    const int idx = first + g;
-    int gu = 0, gv = 0;
-    if (idx < ngrid) split_index(idx, gw, inv_gw, gu, gv);
+    PassChildren<CL::CPL> pc;
+    const int j = lane % CL::LPP;
+    const int u0 = (int)__umul24(p.gu, gs * CL::B) + j % CL::B;
+    const int v0 = (int)__umul24(p.gv, gs * CL::B) + j / CL::B;
+    pc.xu = ray_x(G.ray, u0);
+    pc.xv = ray_y(G.ray, v0);
+    const unsigned i0 = __umul24(v0, G.w) + u0;
 #pragma unroll
-    for (int m = 0; m < CL::CPL; ++m) {
-        const int c = j + CL::LPP * m;
-        pc.u[m] = __umul24(gu, gs * CL::B) + (c % CL::B);
-        pc.v[m] = __umul24(gv, gs * CL::B) + (c / CL::B);
-        pc.wa[m] = load_wa ? load_w<F16>(G.WA, __umul24(pc.v[m], G.w) + pc.u[m]) : 0.0f;
-    }
+    for (int m = 0; m < CL::CPL; ++m)
+        pc.wa[m] = load_wa ? load_w<F16>(G.WA, i0 + CL::dv(m) * G.w + CL::du(m)) : 0.0f;
     return pc;
 }
 
-// One pass: the GPP consecutive grid pixels first .. first+GPP-1.  Every lane
-// of group g = lane / LPP returns the mean warped values of pixel first + g
-// and whether all its children are warp-valid (the strict downsampling rule).
+// One pass: every lane of group g returns the mean warped values of its pixel
+// and whether the pixel is inside the grid (`in`) with all its children
+// warp-valid (the strict downsampling rule).  The means are undefined for an
+// invalid pixel.
 template <bool F16, int LOG2B>
-__device__ __forceinline__ void warp_pass_pc(const Geom& G, const PassChildren<F16, ChildLayout<LOG2B>::CPL>& pc,
-                                             int first, int ngrid, int lane, float& Io,
-                                             float& Wo, bool& Vo, int& idxo)
+__device__ __forceinline__ void warp_pass(const Geom& G, const PassChildren<ChildLayout<LOG2B>::CPL>& pc,
+                                          bool in, int lane, float& Io, float& Wo, bool& Vo)
 {
     using CL = ChildLayout<LOG2B>;
-    const int g = lane / CL::LPP;
-    const int idx = first + g;
-    bool ok = idx < ngrid;
-    float sI = 0.0f, sW = 0.0f;
+    const Ray3 a0 = rotate_ray(G, pc.xu, pc.xv);
     // every child's tap loads first, then the arithmetic on them
     WarpTaps T[CL::CPL];
 #pragma unroll
-    for (int m = 0; m < CL::CPL; ++m) warp_fetch<F16>(G, pc.u[m], pc.v[m], pc.wa[m], T[m]);
+    for (int m = 0; m < CL::CPL; ++m) {
+        Ray3 a = a0;
+        if (CL::du(m) != 0) {
+            const float d = (float)CL::du(m);
+            a.x = fmaf(d, G.su[0], a.x);
+            a.y = fmaf(d, G.su[1], a.y);
+            a.z = fmaf(d, G.su[2], a.z);
+        }
+        if (CL::dv(m) != 0) {
+            const float d = (float)CL::dv(m);
+            a.x = fmaf(d, G.sv[0], a.x);
+            a.y = fmaf(d, G.sv[1], a.y);
+            a.z = fmaf(d, G.sv[2], a.z);
+        }
+        warp_fetch<F16>(G, a, pc.wa[m], T[m]);
+    }
+    bool ok = in;
+    float sI, sW;
 #pragma unroll
     for (int m = 0; m < CL::CPL; ++m) {
         float ci, cw;
-        const bool okc = warp_finish(G, T[m], ci, cw);
-        ok = ok && okc;
-        sI += ci;
-        sW += cw;
+        ok = ok & warp_finish(G, T[m], ci, cw);
+        sI = m == 0 ? ci : sI + ci;
+        sW = m == 0 ? cw : sW + cw;
     }
-#pragma unroll
-    for (int off = 1; off < CL::LPP; off <<= 1) {
-        sI += __shfl_xor(sI, off);
-        sW += __shfl_xor(sW, off);
-    }
+    sI = group_sum<CL::LPP>(sI);
+    sW = group_sum<CL::LPP>(sW);
     bool gvalid = ok;
     if constexpr (CL::LPP > 1) {
+        const int g = lane / CL::LPP;
         const unsigned long long bal = __ballot(ok);
         const unsigned long long full =
             CL::LPP == 64 ? ~0ull : ((1ull << CL::LPP) - 1ull) << (unsigned)(g * CL::LPP);
@@ -303,57 +449,46 @@ __device__ __forceinline__ void warp_pass_pc(const Geom& G, const PassChildren<F
     Io = sI * invC;
     Wo = sW * invC;
     Vo = gvalid;
-    idxo = idx;
-}
-
-template <bool F16, int LOG2B>
-__device__ __forceinline__ void warp_pass(const Geom& G, int first, int gw, float inv_gw, int ngrid,
-                                          int gs, int lane, float& Io, float& Wo, bool& Vo,
-                                          int& idxo)
-{
-    const auto pc = pass_children<F16, LOG2B>(G, first, gw, inv_gw, ngrid, gs, lane);
-    warp_pass_pc<F16, LOG2B>(G, pc, first, ngrid, lane, Io, Wo, Vo, idxo);
 }
 
 // A tile of 64 consecutive grid pixels in LPP passes; afterwards lane L owns
-// the tile pixel q = (L % LPP) * GPP + L / LPP.
+// the tile pixel q = (L % LPP) * GPP + L / LPP, at level coordinates (uo, vo).
 template <bool F16, int LOG2B>
-__device__ __forceinline__ void warp_tile(const Geom& G, int tile_first, int gw, float inv_gw,
-                                          int ngrid, int gs, int lane, float& Io, float& Wo,
-                                          bool& Vo, int& uo, int& vo, int& idxo)
+__device__ __forceinline__ void warp_tile(const Geom& G, int tile_first, const GridDim& gd,
+                                          int lane, float& Io, float& Wo, bool& Vo, int& uo,
+                                          int& vo, int& idxo)
 {
     using CL = ChildLayout<LOG2B>;
     const int j = lane % CL::LPP, g = lane / CL::LPP;
     float mI = 0.0f, mW = 0.0f;
     bool mV = false;
+    PassPos own;
 #pragma unroll 1
     for (int k = 0; k < CL::LPP; ++k) {
+        const PassPos p = pass_pos(tile_first + k * CL::GPP, g, gd);
+        const auto pc = pass_children<F16, LOG2B>(G, p, gd.gs, lane);
         float pI, pW;
         bool pV;
-        int pidx;
-        warp_pass<F16, LOG2B>(G, tile_first + k * CL::GPP, gw, inv_gw, ngrid, gs, lane, pI, pW,
-                              pV, pidx);
+        warp_pass<F16, LOG2B>(G, pc, p.idx < gd.n, lane, pI, pW, pV);
         if (j == k) {
             mI = pI;
             mW = pW;
             mV = pV;
         }
+        if constexpr (CL::LPP == 1) own = p;
     }
-    idxo = tile_first + j * CL::GPP + g;
-    const bool in = idxo < ngrid;
-    int gu = 0, gv = 0;
-    if (in) split_index(idxo, gw, inv_gw, gu, gv);
-    uo = gu * gs;
-    vo = gv * gs;
+    if constexpr (CL::LPP > 1) own = pass_pos(tile_first + j * CL::GPP, g, gd);
+    idxo = own.idx;
+    uo = (int)__umul24(own.gu, gd.gs);
+    vo = (int)__umul24(own.gv, gd.gs);
     Io = mI;
     Wo = mW;
-    Vo = in && mV;
+    Vo = mV;
 }
 
 // Residuals (and Jacobians) of one level pixel (sec. 6.2).  r_I needs an
 // interior pixel, a valid W_A and warped values; r_W additionally the four
-// W_A neighbours (central-difference gradient).  c is A's (I, W) at the
-// pixel; the four neighbours are loaded at clamped (in-bounds) positions.
+// W_A neighbours (central-difference gradient).
 struct Terms {
     bool vI, vW;
     float rI, rW, lam;
@@ -364,15 +499,17 @@ struct Nbrs {
     float2 l, r, t, b;
 };
 
+// The four neighbours of pixel i of A.  Only interior pixels use them; the
+// clamped raster indices keep the loads of every other pixel in bounds.
 template <bool F16>
-__device__ __forceinline__ Nbrs load_nbrs(const LevelView& A, int u, int v)
+__device__ __forceinline__ Nbrs load_nbrs(const LevelView& A, unsigned i)
 {
-    const int i = (int)__umul24(v, A.w) + u;
+    const unsigned w = (unsigned)A.w, last = (unsigned)(A.w * A.h - 1);
     Nbrs n;
-    n.l = load_iw<F16>(A.iw, u > 0 ? i - 1 : i);
-    n.r = load_iw<F16>(A.iw, u < A.w - 1 ? i + 1 : i);
-    n.t = load_iw<F16>(A.iw, v > 0 ? i - A.w : i);
-    n.b = load_iw<F16>(A.iw, v < A.h - 1 ? i + A.w : i);
+    n.l = load_iw<F16>(A.iw, i > 0u ? i - 1u : 0u);
+    n.r = load_iw<F16>(A.iw, min(i + 1u, last));
+    n.t = load_iw<F16>(A.iw, i >= w ? i - w : 0u);
+    n.b = load_iw<F16>(A.iw, min(i + w, last));
     return n;
 }
 
@@ -381,43 +518,46 @@ __device__ __forceinline__ unsigned load_mask(const LevelView& A, unsigned i)
     return ld_at<unsigned char>(A.gm, i);
 }
 
-// Residuals of one level pixel (sec. 6.2) with c = A's (I, W) at the pixel
-// and m its validity flags (bit 0: interior with valid W, bit 1: also the W
-// gradient defined): r_I needs the warp and bit 0, r_W the warp and bit 1.
-// JAC: also the Jacobians J = (a, X x a) of eq:res_int / eq:res_depth from
-// the central differences of the neighbours n, and lambda_n.
+// Residuals of one level pixel (sec. 6.2) with ray x = (xu, xv, 1), c = A's
+// (I, W) at the pixel and m its validity flags (bit 0: interior with valid
+// W, bit 1: also the W gradient defined): r_I needs the warp and bit 0, r_W
+// the warp and bit 1.  JAC: also the Jacobians J = (a, X x a) of eq:res_int /
+// eq:res_depth and lambda_n.  With g = (fx dI/du, fy dI/dv) from central
+// differences, a_I = W_A (g_u, g_v, -(xu g_u + xv g_v)) (the third entry is
+// g_u (cx - u) + g_v (cy - v) written in the ray), and since X = x / W_A,
+// X x a_I = x x (a_I / W_A); likewise for a_W from the W_A gradient, whose
+// third entry adds W*.
 template <bool JAC>
-__device__ __forceinline__ void terms_core(const LevelView& A, float ifx, float ify, int u, int v,
-                                           float2 c, const Nbrs& n, unsigned m, float Is, float Ws,
-                                           bool wv, Terms& T)
+__device__ __forceinline__ void terms_core(const LevelRay& R, float xu, float xv, float2 c,
+                                           const Nbrs& n, unsigned m, float Is, float Ws, bool wv,
+                                           Terms& T)
 {
-    T.vI = wv && (m & 1u);
-    T.vW = wv && (m & 2u);
+    T.vI = wv & ((m & 1u) != 0u);
+    T.vW = wv & ((m & 2u) != 0u);
     T.rI = Is - c.x;
     T.rW = Ws - c.y;
     if constexpr (JAC) {
-        const float wa = c.y, Z = rcp(wa);
-        const float du = A.cx - (float)u, dv = A.cy - (float)v;
-        const float xu = -du * ifx, xv = -dv * ify;
-        const float X0 = Z * xu, X1 = Z * xv, X2 = Z;
-        const float gu = 0.5f * (n.r.x - n.l.x), gv = 0.5f * (n.b.x - n.t.x);
-        const float a0 = wa * gu * A.fx, a1 = wa * gv * A.fy, a2 = wa * fmaf(gu, du, gv * dv);
-        T.JI[0] = a0;
-        T.JI[1] = a1;
-        T.JI[2] = a2;
-        T.JI[3] = X1 * a2 - X2 * a1;
-        T.JI[4] = X2 * a0 - X0 * a2;
-        T.JI[5] = X0 * a1 - X1 * a0;
-        const float wu = 0.5f * (n.r.y - n.l.y), wv2 = 0.5f * (n.b.y - n.t.y);
-        const float k0 = wu * A.fx, k1 = wv2 * A.fy, k2 = fmaf(wu, du, wv2 * dv);
-        const float b0 = wa * k0, b1 = wa * k1, b2 = wa * (k2 + Ws);
-        T.JW[0] = b0;
-        T.JW[1] = b1;
-        T.JW[2] = b2;
-        T.JW[3] = X1 * b2 - X2 * b1;
-        T.JW[4] = X2 * b0 - X0 * b2;
-        T.JW[5] = X0 * b1 - X1 * b0;
-        // n~ = Z grad W (K - p e_z^T) + e_z, n~ . x = 1, lambda = 1/(|n~||x|)
+        const float wa = c.y;
+        const float g0 = (n.r.x - n.l.x) * R.hfx, g1 = (n.b.x - n.t.x) * R.hfy;
+        const float g2 = -fmaf(xu, g0, xv * g1);
+        T.JI[0] = wa * g0;
+        T.JI[1] = wa * g1;
+        T.JI[2] = wa * g2;
+        T.JI[3] = fmaf(xv, g2, -g1);
+        T.JI[4] = fmaf(-xu, g2, g0);
+        T.JI[5] = fmaf(xu, g1, -(xv * g0));
+        const float k0 = (n.r.y - n.l.y) * R.hfx, k1 = (n.b.y - n.t.y) * R.hfy;
+        const float k2 = -fmaf(xu, k0, xv * k1);
+        const float kw = k2 + Ws;
+        T.JW[0] = wa * k0;
+        T.JW[1] = wa * k1;
+        T.JW[2] = wa * kw;
+        T.JW[3] = fmaf(xv, kw, -k1);
+        T.JW[4] = fmaf(-xu, kw, k0);
+        T.JW[5] = fmaf(xu, k1, -(xv * k0));
+        // n~ = Z grad W (K - p e_z^T) + e_z = Z (k0, k1, k2) + e_z (Z = 1 / W_A),
+        // lambda = 1 / (|n~| |x|)
+        const float Z = rcp(wa);
         const float n0 = Z * k0, n1 = Z * k1, n2 = fmaf(Z, k2, 1.0f);
         const float nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
         const float xx = fmaf(xu, xu, fmaf(xv, xv, 1.0f));
@@ -426,16 +566,16 @@ __device__ __forceinline__ void terms_core(const LevelView& A, float ifx, float 
 }
 
 template <bool F16, bool JAC>
-__device__ __forceinline__ void pixel_terms(const LevelView& A, float ifx, float ify, int u, int v,
+__device__ __forceinline__ void pixel_terms(const LevelView& A, const LevelRay& R, int u, int v,
                                             float Is, float Ws, bool wv, Terms& T)
 {
     const unsigned i = __umul24(v, A.w) + u;
     const float2 c = load_iw<F16>(A.iw, i);
     const unsigned m = load_mask(A, i);
     Nbrs n;
-    if constexpr (JAC) n = load_nbrs<F16>(A, u, v);
+    if constexpr (JAC) n = load_nbrs<F16>(A, i);
     else n.l = n.r = n.t = n.b = c;
-    terms_core<JAC>(A, ifx, ify, u, v, c, n, m, Is, Ws, wv, T);
+    terms_core<JAC>(R, ray_x(R, u), ray_y(R, v), c, n, m, Is, Ws, wv, T);
 }
 
 // Robust weight of a normalised residual x: Huber min(1, k/|x|) or Student-t
@@ -477,89 +617,122 @@ __device__ __forceinline__ void accum(float* acc, const float* J, float w, float
     acc[27] = fmaf(w * r, r, acc[27]);
 }
 
-__device__ __forceinline__ float wave_sum(float v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// Grid of a level for the pixel kernels: the full level grid, or the sample
-// grid (every s-th pixel in both directions).
-struct GridDim {
-    int gw, n, gs;
-    float inv_gw;
+// Robust weighting of one iteration: the channels' location, inverse scale,
+// nu and prior weight 1/sigma^2, and whether a channel takes part.
+struct RobustW {
+    int kind;
+    float kh;
+    float muI, isI, nuI, wI0;
+    float muW, isW, nuW, wW0;
+    bool enI, enW;
 };
 
-__device__ __forceinline__ GridDim level_grid(const LevelView& A)
+__device__ __forceinline__ RobustW robust_w(const IterLaunch& L, const PairState& S)
 {
-    GridDim d;
-    d.gw = A.w;
-    d.n = A.w * A.h;
-    d.gs = 1;
-    d.inv_gw = 1.0f / (float)A.w;
-    return d;
+    RobustW W;
+    W.kind = L.ip.weight;
+    W.kh = L.ip.huber_k;
+    W.enI = S.ns[0] > 0;
+    W.enW = S.ns[1] > 0;
+    W.muI = S.mu[0];
+    W.isI = 1.0f / S.sigma[0];
+    W.muW = S.mu[1];
+    W.isW = 1.0f / S.sigma[1];
+    W.nuW = S.nu[1];
+    W.nuI = (W.kind == RGBID_W_STUDENT_T && L.ip.estimate_nu) ? fmaxf(S.nu[0], W.nuW) : S.nu[0];
+    W.wI0 = W.isI * W.isI;
+    W.wW0 = W.isW * W.isW;
+    return W;
 }
 
-__device__ __forceinline__ GridDim sample_grid(const PairDesc& D, int l)
+// Adds one pixel's weighted terms to the 28 per-lane sums; the counts of
+// contributing pixels go to the wave-uniform counters cI, cW.
+__device__ __forceinline__ void accumulate_terms(float* acc, const Terms& T, const RobustW& W,
+                                                 unsigned& cI, unsigned& cW)
 {
-    GridDim d;
-    d.gw = D.sw[l];
-    d.n = D.sw[l] * D.sh[l];
-    d.gs = D.stride[l];
-    d.inv_gw = 1.0f / (float)D.sw[l];
-    return d;
+    const bool tI = T.vI & W.enI, tW = T.vW & W.enW;
+    cI += (unsigned)__popcll(__ballot(tI));
+    cW += (unsigned)__popcll(__ballot(tW));
+    if (tI) {
+        const float w = omega(W.kind, (T.rI - W.muI) * W.isI, W.nuI, W.kh) * W.wI0;
+        accum(acc, T.JI, w, T.rI);
+    }
+    if (tW) {
+        const float w = T.lam * omega(W.kind, (T.rW - W.muW) * W.isW, W.nuW, W.kh) * W.wW0;
+        accum(acc, T.JW, w, T.rW);
+    }
 }
 
 // ------------------------------------------------------------------ k_warp
 
+// Membership of the systematic sample of stride s: x = s q exactly, with the
+// quotient q = floor((x + 1/2) / s) formed in FP32 (exact for x < 2^20, s <=
+// 64: the fraction stays at least 1/(2s) away from an integer).
+struct SampleDiv {
+    int s;
+    float inv, half_inv;
+};
+
+__device__ __forceinline__ SampleDiv sample_div(int s)
+{
+    SampleDiv d;
+    d.s = s;
+    d.inv = uniform_f(1.0f / (float)s);
+    d.half_inv = uniform_f(0.5f * d.inv);
+    return d;
+}
+
+__device__ __forceinline__ int sample_quot(const SampleDiv& d, int x)
+{
+    return (int)fmaf((float)x, d.inv, d.half_inv);
+}
+
 // Reference values a pass's group leader needs for its pixel's sample
-// residuals: A's (I, W) at the pixel and its four neighbours (for the
-// validity of the inverse-depth gradient).  Loaded one pass ahead, together
-// with that pass's children, so the residual step has no dependent load.
+// residuals: A's (I, W) and validity flags at the pixel, and its ray.
+// Loaded one pass ahead, together with that pass's children, so the residual
+// step has no dependent load.
 struct SampleRef {
-    int idx, sidx;      // grid index, sample index (-1: not a sample pixel)
-    int u, v;           // level coordinates
+    int sidx;           // sample index (-1: not a sample pixel)
+    float xu, xv;
     float2 c;
     unsigned m;
 };
 
 template <bool F16, int LOG2B>
-__device__ __forceinline__ SampleRef sample_ref(const LevelView& A, const GridDim& gd, int first,
-                                                int lane, bool fused, int s, int sw)
+__device__ __forceinline__ SampleRef sample_ref(const LevelView& A, const LevelRay& R,
+                                                const PassPos& p, const GridDim& gd, int lane,
+                                                bool fused, const SampleDiv& sd, int sw)
 {
     using CL = ChildLayout<LOG2B>;
     SampleRef r;
-    r.idx = first + lane / CL::LPP;
     r.sidx = -1;
-    r.u = r.v = 0;
+    r.xu = r.xv = 0.0f;
     r.c = make_float2(0.0f, 0.0f);
     r.m = 0;
-    if ((lane % CL::LPP) != 0 || r.idx >= gd.n) return r;
-    int gu, gv;
-    split_index(r.idx, gd.gw, gd.inv_gw, gu, gv);
-    r.u = gu * gd.gs;
-    r.v = gv * gd.gs;
-    if (fused) r.sidx = r.idx;
-    else if ((r.u % s) == 0 && (r.v % s) == 0) r.sidx = (r.v / s) * sw + r.u / s;
+    if ((lane % CL::LPP) != 0 || p.idx >= gd.n) return r;
+    const int u = (int)__umul24(p.gu, gd.gs), v = (int)__umul24(p.gv, gd.gs);
+    if (fused) {
+        r.sidx = p.idx;
+    } else {
+        const int qu = sample_quot(sd, u), qv = sample_quot(sd, v);
+        if (u == (int)__umul24(qu, sd.s) && v == (int)__umul24(qv, sd.s))
+            r.sidx = (int)__umul24(qv, sw) + qu;
+    }
     if (r.sidx >= 0) {
-        const unsigned i = __umul24(r.v, A.w) + r.u;
+        const unsigned i = __umul24(v, A.w) + u;
         r.c = load_iw<F16>(A.iw, i);
         r.m = load_mask(A, i);
+        r.xu = ray_x(R, u);
+        r.xv = ray_y(R, v);
     }
     return r;
 }
 
 // Tiles of this kernel are single passes of GPP grid pixels.  The group
-// leader of each pixel stores the warped values (store mode) and, for sample
-// pixels, the two residuals (NaN = not defined).
+// leader of each pixel stores the warped values (store mode; zeros for an
+// invalid pixel) and, for sample pixels, the two residuals (NaN = not
+// defined).
 template <bool F16, int LOG2B>
 __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
 {
@@ -571,45 +744,47 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
     const PairDesc& D = L.pairs[ch.pair];
     const int l = L.level;
     const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
-    const Geom G = make_geom(S, D.A[wl], D.B[wl]);
+    const Geom G = make_geom<F16>(S, D.A[wl], D.B[wl]);
     const LevelView A = D.A[l];
-    const float ifx = 1.0f / A.fx, ify = 1.0f / A.fy;
+    const LevelRay R = level_ray(A);
     const bool fused = L.tune.fused;
     const GridDim gd = fused ? sample_grid(D, l) : level_grid(A);
-    const int s = D.stride[l], sw = D.sw[l];
+    const SampleDiv sd = sample_div(D.stride[l]);
+    const int sw = D.sw[l];
     void* const warped = D.warped;
     void* const sample = D.sample;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / CL::LPP;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
     int tile = ch.first + wave;
     // sample-only pass at level 0: the pixel is its own child, so W_A comes
     // with the reference values and the W plane is not read
     const bool own = LOG2B == 0 && fused;
-    SampleRef sr = sample_ref<F16, LOG2B>(A, gd, tile * CL::GPP, lane, fused, s, sw);
-    auto pc = pass_children<F16, LOG2B>(G, tile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane,
-                                        !own);
+    PassPos pp = pass_pos(tile * CL::GPP, g, gd);
+    SampleRef sr = sample_ref<F16, LOG2B>(A, R, pp, gd, lane, fused, sd, sw);
+    auto pc = pass_children<F16, LOG2B>(G, pp, gd.gs, lane, !own);
     if (own) pc.wa[0] = sr.c.y;
     for (; tile < end; tile += waves) {
         float Is, Ws;
         bool wv;
-        int idx;
-        warp_pass_pc<F16, LOG2B>(G, pc, tile * CL::GPP, gd.n, lane, Is, Ws, wv, idx);
+        const int idx = pp.idx;
+        warp_pass<F16, LOG2B>(G, pc, idx < gd.n, lane, Is, Ws, wv);
         // the next tile's children and reference values: their loads overlap
         // this tile's tail
         const int ntile = tile + waves < end ? tile + waves : tile;
         const SampleRef cur = sr;
-        sr = sample_ref<F16, LOG2B>(A, gd, ntile * CL::GPP, lane, fused, s, sw);
-        pc = pass_children<F16, LOG2B>(G, ntile * CL::GPP, gd.gw, gd.inv_gw, gd.n, gd.gs, lane,
-                                       !own);
+        pp = pass_pos(ntile * CL::GPP, g, gd);
+        sr = sample_ref<F16, LOG2B>(A, R, pp, gd, lane, fused, sd, sw);
+        pc = pass_children<F16, LOG2B>(G, pp, gd.gs, lane, !own);
         if (own) pc.wa[0] = sr.c.y;
         if ((lane % CL::LPP) != 0 || idx >= gd.n) continue;
-        if (!fused) store_f2(warped, idx, Is, wv ? Ws : 0.0f);
+        if (!fused) store_f2(warped, idx, wv ? Is : 0.0f, wv ? Ws : 0.0f);
         if (cur.sidx < 0) continue;
         Terms T;
         Nbrs none;
         none.l = none.r = none.t = none.b = cur.c;
-        terms_core<false>(A, ifx, ify, cur.u, cur.v, cur.c, none, cur.m, Is, Ws, wv, T);
+        terms_core<false>(R, cur.xu, cur.xv, cur.c, none, cur.m, Is, Ws, wv, T);
         store_f2(sample, cur.sidx, T.vI ? T.rI : __int_as_float(0x7fc00000),
                  T.vW ? T.rW : __int_as_float(0x7fc00000));
     }
@@ -650,11 +825,24 @@ __device__ __forceinline__ float wave_sum_to_last(float v)
     return v;
 }
 
-// Block totals of NV per-thread FP32 values, in FP64 and valid in wave 0
-// only: every wave reduces its values (lane 63 stores them to LDS), then
-// after a barrier wave 0 adds the per-wave values in wave order.  The scale
-// kernel's FP64 step runs once per block (in wave 0) and its result reaches
-// the other waves through LDS after a second barrier.
+// Block totals of NV per-thread FP32 values, in FP64 and valid in lane 15 of
+// wave 0 only: every wave reduces its values (lane 63 stores them to LDS);
+// after a barrier, lane j < 16 of wave 0 takes the values of wave j (zero
+// past the last wave) and an FP64 scan across the row of 16 lanes leaves the
+// totals in lane 15.  A fixed order.  The scale kernel's update runs in that
+// lane and reaches the other waves through LDS after a second barrier.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kTotalsLane = 15;
+
 template <int NV>
 __device__ __forceinline__ void block_totals(const float (&x)[NV], float* part, double (&tot)[NV])
 {
@@ -665,12 +853,17 @@ __device__ __forceinline__ void block_totals(const float (&x)[NV], float* part, 
         if (lane == 63) part[wave * NV + k] = w;
     }
     __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    if (wave == 0)
-        for (int w = 0; w < nw; ++w)
-#pragma unroll
-            for (int k = 0; k < NV; ++k) tot[k] += (double)part[w * NV + k];
+        for (int k = 0; k < NV; ++k) {
+            double t = lane < nw ? (double)part[lane * NV + k] : 0.0;
+            t += dpp_d<0x111>(t);   // row_shr:1
+            t += dpp_d<0x112>(t);   // row_shr:2
+            t += dpp_d<0x114>(t);   // row_shr:4
+            t += dpp_d<0x118>(t);   // row_shr:8
+            tot[k] = t;
+        }
+    }
 }
 
 // n f_c(nu) with f_c(nu) = -psi(nu/2) + ln(nu/2) + psi((nu+1)/2) - ln((nu+1)/2):
@@ -682,61 +875,58 @@ __device__ __forceinline__ double nu_equation_const(double n, double nud)
                 log(0.5 * (nud + 1.0)));
 }
 
+// A sample entry that takes no part: +inf, whose weight is exactly 0 under
+// both rules (1/inf = 0), and whose residual is clamped to a finite value in
+// the sums, so its terms are 0 * finite.
+constexpr float kNoSample = __builtin_inff();
+constexpr float kResClamp = 3.0e38f;
+
 // The location / scale fixed point with nu = 5 (Student-t) or the Huber
 // threshold k: every step sums w, w d and w d^2 (d = r - mu, weights from
 // the previous estimate) over the block and moves mu by S1/S0, sigma^2 to
-// (S2 - S1^2/S0)/n.  Branch-free per element (padding entries get w = 0;
-// entries past `per` are padding in every thread and skipped); two partial
-// sums per lane in a fixed order.  bc[0..2] broadcast mu, sigma and 1/sigma.
-template <int KIND>
-__device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThread], int per,
-                                                  double n, float floor_s, float k, int iters,
-                                                  float* part, double* bc, double& mu,
-                                                  double& sigma)
+// (S2 - S1^2/S0)/n.  Sums in FP32 per lane (two partial sums in a fixed
+// order), FP64 across the block; mu is kept in FP64, S1/S0 and sigma are
+// formed in FP32 from the FP64 sums.  bcd / bcf broadcast mu and sigma.
+template <int KIND, int PER>
+__device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], float inv_n,
+                                                  float floor_s, float k, int iters, float* part,
+                                                  double* bcd, float* bcf, double& mu,
+                                                  float& sigma)
 {
-    const int wave = threadIdx.x >> 6;
-    float fmu = (float)mu, isg = (float)(1.0 / sigma);
+    float fmu = (float)mu, sg = sigma;
     for (int it = 0; it < iters; ++it) {
         // the weight of x = d / sigma written in d: Huber min(1, k sigma / |d|),
         // Student-t (nu + 1) sigma^2 / (nu sigma^2 + d^2) with nu = 5
-        const float sg = 1.0f / isg;
         const float hk = k * sg, tA = 6.0f * sg * sg, tB = 5.0f * sg * sg;
         float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
 #pragma unroll
-        for (int q = 0; q < kScalePerThread; ++q) {
-            if (q < per) {
-                const bool ok = r[q] == r[q];
-                const float d = r[q] - fmu;
-                float w;
-                if constexpr (KIND == RGBID_W_HUBER) w = fminf(1.0f, hk * rcp(fabsf(d)));
-                else w = tA * rcp(fmaf(d, d, tB));
-                w = ok ? w : 0.0f;
-                const float dd = ok ? d : 0.0f;
-                s0[q & 1] += w;
-                s1[q & 1] = fmaf(w, dd, s1[q & 1]);
-                s2[q & 1] = fmaf(w * dd, dd, s2[q & 1]);
-            }
+        for (int q = 0; q < PER; ++q) {
+            const float d = r[q] - fmu;
+            float w;
+            if constexpr (KIND == RGBID_W_HUBER) w = fminf(1.0f, hk * rcp(fabsf(d)));
+            else w = tA * rcp(fmaf(d, d, tB));
+            const float dd = fminf(d, kResClamp);
+            s0[q & 1] += w;
+            s1[q & 1] = fmaf(w, dd, s1[q & 1]);
+            s2[q & 1] = fmaf(w * dd, dd, s2[q & 1]);
         }
         const float acc[3] = {s0[0] + s0[1], s1[0] + s1[1], s2[0] + s2[1]};
         double tot[3];
         block_totals<3>(acc, part, tot);
-        if (wave == 0) {
+        if (threadIdx.x == kTotalsLane) {
             // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
-            const double dm = tot[1] / tot[0];
-            const double var = fmax((tot[2] - tot[1] * dm) / n, 0.0);
-            const double sg = fmax(sqrt(var), (double)floor_s);
-            if (threadIdx.x == 0) {
-                bc[0] = mu + dm;
-                bc[1] = sg;
-                bc[2] = 1.0 / sg;
-            }
+            const float dm = (float)tot[1] / (float)tot[0];
+            const double ss = tot[2] - tot[1] * (double)dm;
+            const float var = fmaxf((float)ss * inv_n, 0.0f);
+            bcd[0] = mu + (double)dm;
+            bcf[0] = fmaxf(sqrtf(var), floor_s);
         }
         __syncthreads();
-        mu = bc[0];
-        sigma = bc[1];
+        mu = bcd[0];
+        sg = bcf[0];
         fmu = (float)mu;
-        isg = (float)bc[2];
     }
+    sigma = sg;
 }
 
 // One workgroup per (pair, channel): location mu and scale sigma of the
@@ -745,79 +935,82 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[kScalePerThre
 // mu = 0, sigma^2 = mean r^2, with nu = 5 for Student-t; then (Student-t with
 // estimation) nu by bisection of the nu equation on [2, 10] with the
 // normalised residuals frozen: f(10) > 0 gives 10, f(2) < 0 gives 2, else 30
-// halvings of [2, 10] and the midpoint.
+// halvings of [2, 10] and the midpoint.  Thread t holds entries t + 1024 q,
+// q < PER, of the sample (PER * 1024 at least the largest sample of the
+// launch); undefined residuals and entries past the sample are kNoSample.
+template <int PER>
 __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
 {
     __shared__ float part[16 * 3];
-    __shared__ double bc[4];
+    __shared__ double bcd[2];
+    __shared__ float bcf[2];
     const int p = blockIdx.x, ch = blockIdx.y;
     PairState& S = L.states[p];
     if (!S.active || S.level_stop) return;
     const PairDesc& D = L.pairs[p];
     const int n_all = D.sw[L.level] * D.sh[L.level];
-    const int per = (n_all + kScaleThreads - 1) / kScaleThreads;
-    const int wave = threadIdx.x >> 6;
     const float floor_s = ch == 0 ? 1e-3f : 1e-6f;
-    float r[kScalePerThread];
+    float r[PER];
     float cs[2] = {0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < kScalePerThread; ++k) {
+    for (int k = 0; k < PER; ++k) {
         const int i = threadIdx.x + k * kScaleThreads;
-        float x = __int_as_float(0x7fc00000);
+        float x = kNoSample;
         if (i < n_all) {
             const float2 e = load_f2(D.sample, i);
-            x = ch == 0 ? e.x : e.y;
+            const float y = ch == 0 ? e.x : e.y;
+            x = y == y ? y : kNoSample;   // NaN: residual not defined
         }
         r[k] = x;
-        const bool ok = x == x;
+        const bool ok = x < kNoSample;
         cs[0] += ok ? 1.0f : 0.0f;
         cs[1] = ok ? fmaf(x, x, cs[1]) : cs[1];
     }
     {
         double t[2];
         block_totals<2>(cs, part, t);
-        if (threadIdx.x == 0) {
-            bc[0] = t[0];
-            bc[1] = t[0] > 0.0 ? fmax(sqrt(t[1] / t[0]), (double)floor_s) : (double)floor_s;
+        if (threadIdx.x == kTotalsLane) {
+            bcd[0] = t[0];
+            bcf[0] = t[0] > 0.0 ? (float)fmax(sqrt(t[1] / t[0]), (double)floor_s) : floor_s;
         }
         __syncthreads();
     }
-    const double n = bc[0];
-    double mu = 0.0, sigma = bc[1];
+    const double n = bcd[0];
+    double mu = 0.0;
+    float sigma = bcf[0];
     float nu = 5.0f;
     if (n > 0.0) {
+        const float inv_n = (float)(1.0 / n);
         if (L.ip.weight == RGBID_W_HUBER)
-            scale_fixed_point<RGBID_W_HUBER>(r, per, n, floor_s, L.ip.huber_k, L.ip.scale_iters,
-                                             part, bc, mu, sigma);
+            scale_fixed_point<RGBID_W_HUBER, PER>(r, inv_n, floor_s, L.ip.huber_k,
+                                                  L.ip.scale_iters, part, bcd, bcf, mu, sigma);
         else
-            scale_fixed_point<RGBID_W_STUDENT_T>(r, per, n, floor_s, L.ip.huber_k,
-                                                 L.ip.scale_iters, part, bc, mu, sigma);
+            scale_fixed_point<RGBID_W_STUDENT_T, PER>(r, inv_n, floor_s, L.ip.huber_k,
+                                                      L.ip.scale_iters, part, bcd, bcf, mu, sigma);
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
-            const float fmu = (float)mu, isg = (float)(1.0 / sigma);
+            const float fmu = (float)mu, isg = 1.0f / sigma;
 #pragma unroll
-            for (int q = 0; q < kScalePerThread; ++q) {
+            for (int q = 0; q < PER; ++q) {
                 const float x = (r[q] - fmu) * isg;
-                r[q] = x * x;     // r now holds x^2 (NaN stays NaN)
+                r[q] = x * x;     // r now holds x^2 (kNoSample stays +inf)
             }
             // evaluations f(10), f(2), then up to 30 bisection steps; the
-            // bracket lives in wave 0, the next nu and the stop flag reach
-            // every wave through LDS
+            // bracket lives in the totals lane, the next nu and the stop flag
+            // reach every wave through LDS
             double lo = 2.0, hi = 10.0, nud = 10.0;
             for (int ev = 0;; ++ev) {
                 const float nf = (float)nud;
                 float e2[2] = {0.0f, 0.0f};
 #pragma unroll
-                for (int q = 0; q < kScalePerThread; ++q) {
-                    if (q < per) {
-                        // a padding entry (NaN) takes w = 1, whose term 1 + ln 1 - 1 is 0
-                        const float w = r[q] == r[q] ? (nf + 1.0f) / (nf + r[q]) : 1.0f;
-                        e2[q & 1] += 1.0f + logf(w) - w;
-                    }
+                for (int q = 0; q < PER; ++q) {
+                    // an entry without a residual takes w = 1, whose term 1 + ln 1 - 1 is 0
+                    const float w = r[q] < kNoSample ? (nf + 1.0f) / (nf + r[q]) : 1.0f;
+                    e2[q & 1] += 1.0f + logf(w) - w;
                 }
                 const float acc[1] = {e2[0] + e2[1]};
                 double tot[1];
                 block_totals<1>(acc, part, tot);
-                if (wave == 0) {
+                if (threadIdx.x == kTotalsLane) {
                     const double f = nu_equation_const(n, nud) + tot[0];
                     double next = nud;
                     bool stop = false;
@@ -833,27 +1026,73 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
                         next = 0.5 * (lo + hi);
                         stop = ev == 31;
                     }
-                    if (threadIdx.x == 0) {
-                        bc[2] = next;
-                        bc[3] = stop ? 1.0 : 0.0;
-                    }
+                    bcd[1] = next;
+                    bcf[1] = stop ? 1.0f : 0.0f;
                 }
                 __syncthreads();
-                nud = bc[2];
-                if (bc[3] != 0.0) break;
+                nud = bcd[1];
+                if (bcf[1] != 0.0f) break;
             }
             nu = (float)nud;
         }
     }
     if (threadIdx.x == 0) {
         S.mu[ch] = (float)mu;
-        S.sigma[ch] = (float)sigma;
+        S.sigma[ch] = sigma;
         S.nu[ch] = nu;
         S.ns[ch] = (int)n;
     }
 }
 
 // ------------------------------------------------------------------ k_reduce
+
+// A level pixel of A with everything its terms need: raster index, ray,
+// (I, W), validity flags and the four neighbours.
+struct RefPx {
+    int idx;
+    float xu, xv;
+    float2 c;
+    unsigned m;
+    Nbrs nb;
+};
+
+template <bool F16>
+__device__ __forceinline__ void load_ref(const LevelView& A, const LevelRay& R, int n, int idx,
+                                         int u, int v, RefPx& r)
+{
+    const unsigned ic = (unsigned)min(idx, n - 1);
+    r.idx = idx;
+    r.xu = ray_x(R, u);
+    r.xv = ray_y(R, v);
+    r.c = load_iw<F16>(A.iw, ic);
+    r.m = load_mask(A, ic);
+    r.nb = load_nbrs<F16>(A, ic);
+}
+
+// Raster position `step` pixels further on (step = sv rows + su columns,
+// su < gw).
+__device__ __forceinline__ void advance(int& idx, int& u, int& v, int step, int su, int sv, int gw)
+{
+    idx += step;
+    u += su;
+    v += sv;
+    if (u >= gw) {
+        u -= gw;
+        ++v;
+    }
+}
+
+// Level pixel that is its own warp child: warp, residuals, terms.
+template <bool F16>
+__device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, const RefPx& r, int n,
+                                          const RobustW& W, float* acc, unsigned& cI, unsigned& cW)
+{
+    float Is, Ws;
+    const bool wv = warp_ray<F16>(G, r.xu, r.xv, r.c.y, Is, Ws) & (r.idx < n);
+    Terms T;
+    terms_core<true>(R, r.xu, r.xv, r.c, r.nb, r.m, Is, Ws, wv, T);
+    accumulate_terms(acc, T, W, cI, cW);
+}
 
 template <bool F16, int LOG2B, bool FUSED>
 __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
@@ -866,69 +1105,37 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const PairDesc& D = L.pairs[ch.pair];
     const int l = L.level;
     const LevelView A = D.A[l];
-    const float ifx = 1.0f / A.fx, ify = 1.0f / A.fy;
+    const LevelRay R = level_ray(A);
     const GridDim gd = level_grid(A);
     const void* const warped = D.warped;
-
-    const int kind = L.ip.weight;
-    const float kh = L.ip.huber_k;
-    const bool enI = S.ns[0] > 0, enW = S.ns[1] > 0;
-    const float muI = S.mu[0], isI = 1.0f / S.sigma[0], muW = S.mu[1], isW = 1.0f / S.sigma[1];
-    const float nuW = S.nu[1];
-    const float nuI = (kind == RGBID_W_STUDENT_T && L.ip.estimate_nu) ? fmaxf(S.nu[0], nuW) : S.nu[0];
-    const float wI0 = isI * isI, wW0 = isW * isW;
+    const RobustW W = robust_w(L, S);
 
     float acc[kNSum];
 #pragma unroll
     for (int k = 0; k < kNSum; ++k) acc[k] = 0.0f;
+    unsigned cI = 0, cW = 0;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
     const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
-    const Geom G = make_geom(S, D.A[wl], D.B[wl]);
+    const Geom G = make_geom<F16>(S, D.A[wl], D.B[wl]);
     if constexpr (FUSED && LOG2B == 0) {
         // The level pixel is its own warp child, so W_A comes with A's (I, W).
         // A's loads for the next tile are issued while this tile's gathers
         // from B are in flight.
+        const int step = waves * 64, su = step % gd.gw, sv = step / gd.gw;
         int tile = ch.first + wave;
-        int idx = tile * 64 + lane;
-        int ic = idx < gd.n ? idx : 0;
-        int u, v;
-        split_index(ic, gd.gw, gd.inv_gw, u, v);
-        float2 c = load_iw<F16>(A.iw, ic);
-        unsigned m = load_mask(A, ic);
-        Nbrs nb = load_nbrs<F16>(A, u, v);
+        int idx = tile * 64 + lane, u, v;
+        split_index(idx, gd.gw, gd.inv_gw, gd.half_inv, u, v);
+        RefPx r;
+        load_ref<F16>(A, R, gd.n, idx, u, v, r);
         for (; tile < end; tile += waves) {
-            float Is, Ws;
-            const bool wv = warp_core<F16>(G, u, v, c.y, Is, Ws) && idx < gd.n;
-            const int ntile = tile + waves;
-            const int nidx = ntile * 64 + lane;
-            const int nic = (ntile < end && nidx < gd.n) ? nidx : ic;
-            int nu, nv;
-            split_index(nic, gd.gw, gd.inv_gw, nu, nv);
-            const float2 nc = load_iw<F16>(A.iw, nic);
-            const unsigned nm = load_mask(A, nic);
-            const Nbrs nnb = load_nbrs<F16>(A, nu, nv);
-            Terms T;
-            terms_core<true>(A, ifx, ify, u, v, c, nb, m, Is, Ws, wv, T);
-            if (T.vI && enI) {
-                const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
-                accum(acc, T.JI, w, T.rI);
-                acc[28] += 1.0f;
-            }
-            if (T.vW && enW) {
-                const float w = T.lam * omega(kind, (T.rW - muW) * isW, nuW, kh) * wW0;
-                accum(acc, T.JW, w, T.rW);
-                acc[29] += 1.0f;
-            }
-            idx = nidx;
-            ic = nic;
-            u = nu;
-            v = nv;
-            c = nc;
-            m = nm;
-            nb = nnb;
+            advance(idx, u, v, step, su, sv, gd.gw);
+            RefPx nxt;
+            load_ref<F16>(A, R, gd.n, idx, u, v, nxt);
+            own_pixel<F16>(G, R, r, gd.n, W, acc, cI, cW);
+            r = nxt;
         }
     } else {
         for (int tile = ch.first + wave; tile < end; tile += waves) {
@@ -936,34 +1143,26 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             bool wv = false;
             int u = 0, v = 0, idx;
             if constexpr (FUSED) {
-                warp_tile<F16, LOG2B>(G, tile * 64, gd.gw, gd.inv_gw, gd.n, 1, lane, Is, Ws, wv, u,
-                                      v, idx);
+                warp_tile<F16, LOG2B>(G, tile * 64, gd, lane, Is, Ws, wv, u, v, idx);
             } else {
                 idx = tile * 64 + lane;
-                const int ic = idx < gd.n ? idx : 0;
+                const int ic = min(idx, gd.n - 1);
                 const float2 e = load_f2(warped, ic);
                 Is = e.x;
                 Ws = e.y;
-                wv = Ws > 0.0f && idx < gd.n;
-                split_index(ic, gd.gw, gd.inv_gw, u, v);
+                wv = (Ws > 0.0f) & (idx < gd.n);
+                split_index(ic, gd.gw, gd.inv_gw, gd.half_inv, u, v);
             }
             Terms T;
-            pixel_terms<F16, true>(A, ifx, ify, u, v, Is, Ws, wv, T);
-            if (T.vI && enI) {
-                const float w = omega(kind, (T.rI - muI) * isI, nuI, kh) * wI0;
-                accum(acc, T.JI, w, T.rI);
-                acc[28] += 1.0f;
-            }
-            if (T.vW && enW) {
-                const float w = T.lam * omega(kind, (T.rW - muW) * isW, nuW, kh) * wW0;
-                accum(acc, T.JW, w, T.rW);
-                acc[29] += 1.0f;
-            }
+            pixel_terms<F16, true>(A, R, u, v, Is, Ws, wv, T);
+            accumulate_terms(acc, T, W, cI, cW);
         }
     }
+    acc[28] = lane == 0 ? (float)cI : 0.0f;
+    acc[29] = lane == 0 ? (float)cW : 0.0f;
 #pragma unroll
-    for (int k = 0; k < kNSum; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane == 0) {
+    for (int k = 0; k < kNSum; ++k) acc[k] = wave_sum_to_last(acc[k]);
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < kNSum; ++k) lds[wave * kNSum + k] = acc[k];
     }
@@ -1018,21 +1217,36 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
     const int p = blockIdx.x;
     PairState& S = L.states[p];
     if (!S.active || S.level_stop) return;
+    __shared__ double part[64 * kNSum];
     const int lane = threadIdx.x;
     const int beg = L.pair_red_begin[p], end = L.pair_red_begin[p + 1];
+    // lane j adds the chunks beg + j, beg + j + 64, ...; then lane k < kNSum
+    // adds term k of the 64 lane sums in lane order
+    {
+        double t[kNSum];
+#pragma unroll
+        for (int k = 0; k < kNSum; ++k) t[k] = 0.0;
+        for (int c = beg + lane; c < end; c += 64) {
+#pragma unroll
+            for (int k = 0; k < kNSum; ++k) {
+                const float2 q = load_f2(L.partials, (size_t)c * kNSum + k);
+                t[k] += (double)q.x + (double)q.y;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kNSum; ++k) part[k * 64 + lane] = t[k];
+    }
+    __syncthreads();
+    if (lane < kNSum) {
+        double t = 0.0;
+        for (int j = 0; j < 64; ++j) t += part[lane * 64 + j];
+        part[lane * 64] = t;
+    }
+    __syncthreads();
+    if (lane != 0) return;
     double s[kNSum];
 #pragma unroll
-    for (int k = 0; k < kNSum; ++k) s[k] = 0.0;
-    for (int c = beg + lane; c < end; c += 64) {
-#pragma unroll
-        for (int k = 0; k < kNSum; ++k) {
-            const float2 q = load_f2(L.partials, (size_t)c * kNSum + k);
-            s[k] += (double)q.x + (double)q.y;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kNSum; ++k) s[k] = wave_sum_d(s[k]);
-    if (lane != 0) return;
+    for (int k = 0; k < kNSum; ++k) s[k] = part[k * 64];
 
     for (int k = 0; k < 21; ++k) S.H[k] = s[k];
     for (int k = 0; k < 6; ++k) S.g[k] = s[21 + k];
@@ -1059,7 +1273,7 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
 #pragma unroll
     for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A[a][a]);
     bool ok = (S.nI + S.nW >= 6) && dmax > 0.0;
-    double Lm[6][6];
+    double Lm[6][6], inv[6];   // inv[j] = 1 / L_jj
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double d = A[j][j];
@@ -1067,12 +1281,13 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
         for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
         ok = ok && d > 1e-12 * dmax;
         Lm[j][j] = sqrt(ok ? d : 1.0);
+        inv[j] = 1.0 / Lm[j][j];
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double e = A[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) e -= Lm[i][k] * Lm[j][k];
-            Lm[i][j] = e / Lm[j][j];
+            Lm[i][j] = e * inv[j];
         }
     }
     if (!ok) {
@@ -1086,14 +1301,14 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
         double e = -s[21 + i];
 #pragma unroll
         for (int k = 0; k < i; ++k) e -= Lm[i][k] * y[k];
-        y[i] = e / Lm[i][i];
+        y[i] = e * inv[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double e = y[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) e -= Lm[k][i] * xi[k];
-        xi[i] = e / Lm[i][i];
+        xi[i] = e * inv[i];
     }
     // T <- exp(xi)^-1 T = (E^T R, E^T (t - v))
     double E[9];
@@ -1134,7 +1349,12 @@ hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L, hipEvent_t con
     if (L.n_warp_chunks > 0)
         hipLaunchKernelGGL((k_warp<F16, LOG2B>), dim3(L.n_warp_chunks), blk, 0, s, L);
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scale, dim3(L.npairs, 2), dim3(kScaleThreads), 0, s, L);
+    const dim3 sg(L.npairs, 2), sb(kScaleThreads);
+    if (L.scale_per <= 5) hipLaunchKernelGGL(k_scale<5>, sg, sb, 0, s, L);
+    else if (L.scale_per <= 10) hipLaunchKernelGGL(k_scale<10>, sg, sb, 0, s, L);
+    else if (L.scale_per <= 15) hipLaunchKernelGGL(k_scale<15>, sg, sb, 0, s, L);
+    else if (L.scale_per <= 19) hipLaunchKernelGGL(k_scale<19>, sg, sb, 0, s, L);
+    else hipLaunchKernelGGL(k_scale<kScalePerThread>, sg, sb, 0, s, L);
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     if (L.n_red_chunks > 0) {
         if (L.tune.fused)

@@ -323,6 +323,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     std::vector<std::vector<std::vector<Chunk>>> wch(nch, std::vector<std::vector<Chunk>>(L)),
         rch(nch, std::vector<std::vector<Chunk>>(L));
     std::vector<std::vector<std::vector<int>>> rbeg(nch, std::vector<std::vector<int>>(L));
+    std::vector<std::vector<int>> scale_per(nch, std::vector<int>(L, 1));
     std::vector<size_t> max_red(nch, 0);
     size_t warped_per_pair_total = 0;
     std::vector<size_t> warped_off(n, 0);
@@ -346,6 +347,8 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                 stride[i * L + l] = s;
                 sw[i * L + l] = (w + s - 1) / s;
                 sh[i * L + l] = (h + s - 1) / s;
+                const int per = (sw[i * L + l] * sh[i * L + l] + kScaleThreads - 1) / kScaleThreads;
+                scale_per[k][l] = std::max(scale_per[k][l], per);
                 const long long ngrid = tune[l].fused ? (long long)sw[i * L + l] * sh[i * L + l]
                                                       : (long long)w * h;
                 const long long wt = (ngrid + gpp - 1) / gpp;
@@ -487,6 +490,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             il.pair_red_begin = reinterpret_cast<const int*>(tbase + lt[k][l].begin_off);
             il.partials = static_cast<float2*>(c->partials.p) + poff[k] * kNSum;
             il.update = update;
+            il.scale_per = scale_per[k][l];
             for (int it = 0; it < stp.iters; ++it) {
                 const hipEvent_t* ev = c->profiling ? &c->events[5 * (ev_base + it)] : nullptr;
                 if ((e = launch_iteration(s, il, ev)) != hipSuccess) return e;
@@ -726,8 +730,8 @@ rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rg
     if (storage != RGBID_F32 && storage != RGBID_F16) return set_err(c, RGBID_E_ARG, "unknown storage");
     if (cam->width < 1 || cam->height < 1 || pitch_elems < (size_t)cam->width)
         return set_err(c, RGBID_E_ARG, "bad image size or pitch");
-    if ((long long)cam->width * cam->height >= (1ll << 24))
-        return set_err(c, RGBID_E_ARG, "images of 2^24 pixels or more are not supported");
+    if ((long long)cam->width * cam->height >= (1ll << 22))
+        return set_err(c, RGBID_E_ARG, "images of 2^22 pixels or more are not supported");
     if (!(cam->fx > 0 && cam->fy > 0)) return set_err(c, RGBID_E_ARG, "focal lengths must be > 0");
     if ((cam->width >> (levels - 1)) < 1 || (cam->height >> (levels - 1)) < 1)
         return set_err(c, RGBID_E_ARG, "level %d would be empty", levels - 1);
@@ -913,8 +917,14 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
     for (int l = 0; l < P->levels; ++l) {
         const std::string key = tune_key(n, A, l, P->warp, f16);
         const int b = P->warp == RGBID_WARP_FULLRES ? l : 0;
-        LevelTune best = default_tune(b);
-        float best_t = 1e30f;
+        // every candidate is timed twice (the faster counts); the four best
+        // are timed four more times and the lowest median of their six
+        // timings wins
+        struct Cand {
+            LevelTune t;
+            std::vector<float> ms;
+        };
+        std::vector<Cand> cands;
         for (int fused = 0; fused < 2; ++fused)
             for (int waves : {2, 4, 8})
                 for (int tpw : {1, 2, 4, 8, 16})
@@ -924,24 +934,44 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
                         t.waves = waves;
                         t.tiles_per_wave = tpw;
                         t.xcd_remap = remap;
-                        c->tunes[key] = t;
-                        std::vector<Step> sched{Step{l, reps}};
-                        float ms = 0.0f;
-                        // first call captures the graph, second is timed
-                        rgbid_status st = run_batch(c, n, A, B, nullptr, P, sched, 0, o.data(),
-                                                    nullptr);
-                        if (st == RGBID_OK)
-                            st = run_batch(c, n, A, B, nullptr, P, sched, 0, o.data(), nullptr, &ms);
-                        if (st != RGBID_OK) {
-                            c->profiling = saved_prof;
-                            c->tunes[key] = best;
-                            return st;
-                        }
-                        if (ms < best_t) {
-                            best_t = ms;
-                            best = t;
-                        }
+                        cands.push_back(Cand{t, {}});
                     }
+        auto time_cand = [&](Cand& cd, int times) -> rgbid_status {
+            c->tunes[key] = cd.t;
+            std::vector<Step> sched{Step{l, reps}};
+            // the first call captures the graph (when not yet cached)
+            rgbid_status st = run_batch(c, n, A, B, nullptr, P, sched, 0, o.data(), nullptr);
+            for (int r = 0; r < times && st == RGBID_OK; ++r) {
+                float ms = 0.0f;
+                st = run_batch(c, n, A, B, nullptr, P, sched, 0, o.data(), nullptr, &ms);
+                cd.ms.push_back(ms);
+            }
+            return st;
+        };
+        auto fail = [&](rgbid_status st) {
+            c->profiling = saved_prof;
+            c->tunes[key] = default_tune(b);
+            return st;
+        };
+        for (Cand& cd : cands)
+            if (rgbid_status st = time_cand(cd, 2); st != RGBID_OK) return fail(st);
+        auto lowest = [](const Cand& x) { return *std::min_element(x.ms.begin(), x.ms.end()); };
+        std::sort(cands.begin(), cands.end(),
+                  [&](const Cand& x, const Cand& y) { return lowest(x) < lowest(y); });
+        const size_t nfin = std::min<size_t>(4, cands.size());
+        for (size_t i = 0; i < nfin; ++i)
+            if (rgbid_status st = time_cand(cands[i], 4); st != RGBID_OK) return fail(st);
+        auto median = [](std::vector<float> v) {
+            std::sort(v.begin(), v.end());
+            return 0.5f * (v[(v.size() - 1) / 2] + v[v.size() / 2]);
+        };
+        LevelTune best = cands[0].t;
+        float best_t = median(cands[0].ms);
+        for (size_t i = 1; i < nfin; ++i)
+            if (median(cands[i].ms) < best_t) {
+                best_t = median(cands[i].ms);
+                best = cands[i].t;
+            }
         c->tunes[key] = best;
         if (best_ms) best_ms[l] = best_t / reps;
     }

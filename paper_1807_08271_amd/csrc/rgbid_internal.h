@@ -127,6 +127,7 @@ struct IterLaunch {
     const int* pair_red_begin;   // npairs + 1
     float2* partials;            // n_red_chunks * kNSum
     int update;                  // 0: normal equations only
+    int scale_per;               // sample entries per scale thread: ceil(max sample / kScaleThreads)
 };
 // ev: NULL, or 5 events recorded before the warp kernel and after each of
 // the four kernels (for per-kernel timing).
