@@ -1346,24 +1346,26 @@ hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L, hipEvent_t con
     const dim3 blk(64 * L.tune.waves);
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    if (L.n_warp_chunks > 0)
+    if ((L.kernels & 1) && L.n_warp_chunks > 0)
         hipLaunchKernelGGL((k_warp<F16, LOG2B>), dim3(L.n_warp_chunks), blk, 0, s, L);
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    const dim3 sg(L.npairs, 2), sb(kScaleThreads);
-    if (L.scale_per <= 5) hipLaunchKernelGGL(k_scale<5>, sg, sb, 0, s, L);
-    else if (L.scale_per <= 10) hipLaunchKernelGGL(k_scale<10>, sg, sb, 0, s, L);
-    else if (L.scale_per <= 15) hipLaunchKernelGGL(k_scale<15>, sg, sb, 0, s, L);
-    else if (L.scale_per <= 19) hipLaunchKernelGGL(k_scale<19>, sg, sb, 0, s, L);
-    else hipLaunchKernelGGL(k_scale<kScalePerThread>, sg, sb, 0, s, L);
+    if (L.kernels & 2) {
+        const dim3 sg(L.npairs, 2), sb(kScaleThreads);
+        if (L.scale_per <= 5) hipLaunchKernelGGL(k_scale<5>, sg, sb, 0, s, L);
+        else if (L.scale_per <= 10) hipLaunchKernelGGL(k_scale<10>, sg, sb, 0, s, L);
+        else if (L.scale_per <= 15) hipLaunchKernelGGL(k_scale<15>, sg, sb, 0, s, L);
+        else if (L.scale_per <= 19) hipLaunchKernelGGL(k_scale<19>, sg, sb, 0, s, L);
+        else hipLaunchKernelGGL(k_scale<kScalePerThread>, sg, sb, 0, s, L);
+    }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    if (L.n_red_chunks > 0) {
+    if ((L.kernels & 4) && L.n_red_chunks > 0) {
         if (L.tune.fused)
             hipLaunchKernelGGL((k_reduce<F16, LOG2B, true>), dim3(L.n_red_chunks), blk, 0, s, L);
         else
             hipLaunchKernelGGL((k_reduce<F16, LOG2B, false>), dim3(L.n_red_chunks), blk, 0, s, L);
     }
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_solve, dim3(L.npairs), dim3(64), 0, s, L);
+    if (L.kernels & 8) hipLaunchKernelGGL(k_solve, dim3(L.npairs), dim3(64), 0, s, L);
     if (ev && (e = hipEventRecord(ev[4], s)) != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -464,15 +464,20 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         }
     }
     // the whole schedule of chain k on stream s
-    auto enqueue = [&](hipStream_t s, int k) -> hipError_t {
+    // part 0: everything; part 1: the first level start and the warp and
+    // scale kernels of the first iteration; part 2: the rest
+    auto enqueue = [&](hipStream_t s, int k, int part) -> hipError_t {
         hipError_t e = hipSuccess;
         int ev_base = 0;
         const int p0 = cfirst[k], np = cfirst[k + 1] - cfirst[k];
         if (np <= 0) return e;
         PairState* states = static_cast<PairState*>(c->states.p) + p0;
+        bool first = true;
         for (const Step& stp : sched) {
             const int l = stp.level;
-            if ((e = launch_level_start(s, states, np)) != hipSuccess) return e;
+            if (stp.iters <= 0) continue;
+            if (part != 2 || !first)
+                if ((e = launch_level_start(s, states, np)) != hipSuccess) return e;
             IterLaunch il;
             il.pairs = static_cast<const PairDesc*>(c->pairs.p) + p0;
             il.states = states;
@@ -493,9 +498,14 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             il.scale_per = scale_per[k][l];
             for (int it = 0; it < stp.iters; ++it) {
                 const hipEvent_t* ev = c->profiling ? &c->events[5 * (ev_base + it)] : nullptr;
+                il.kernels = 15;
+                if (first && it == 0) il.kernels = part == 1 ? 3 : part == 2 ? 12 : 15;
+                else if (part == 1) break;
                 if ((e = launch_iteration(s, il, ev)) != hipSuccess) return e;
             }
             ev_base += stp.iters;
+            first = false;
+            if (part == 1) break;
         }
         return e;
     };
@@ -523,11 +533,15 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         if ((st = ensure_chain_streams(c, nch)) != RGBID_OK) return st;
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
+            // with several chains, chain 0 is captured in two parts (graphs 0
+            // and nch) so the other chains can start half an iteration later
             std::vector<hipGraphExec_t> execs;
-            for (int k = 0; k < nch; ++k) {
+            for (int gi = 0; gi < nch + (nch > 1 ? 1 : 0); ++gi) {
+                const int k = gi < nch ? gi : 0;
+                const int part = nch == 1 ? 0 : gi == 0 ? 1 : gi == nch ? 2 : 0;
                 hipGraph_t g = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-                hipError_t e = enqueue(c->cap, k);
+                hipError_t e = enqueue(c->cap, k, part);
                 hipError_t e2 = hipStreamEndCapture(c->cap, &g);
                 hipGraphExec_t ex = nullptr;
                 if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -545,13 +559,15 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         // chains run concurrently on their own streams, forked from and joined
         // back into the context's stream
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
+        HIPCHK(c, hipGraphLaunch(it->second[0], c->stream));
         if (nch > 1) {
             HIPCHK(c, hipEventRecord(c->fork, c->stream));
             for (int k = 1; k < nch; ++k)
                 HIPCHK(c, hipStreamWaitEvent(c->chain_streams[k - 1], c->fork, 0));
+            for (int k = 1; k < nch; ++k)
+                HIPCHK(c, hipGraphLaunch(it->second[k], c->chain_streams[k - 1]));
+            HIPCHK(c, hipGraphLaunch(it->second[nch], c->stream));
         }
-        for (int k = 0; k < nch; ++k)
-            HIPCHK(c, hipGraphLaunch(it->second[k], k == 0 ? c->stream : c->chain_streams[k - 1]));
         for (int k = 1; k < nch; ++k) {
             HIPCHK(c, hipEventRecord(c->joins[k - 1], c->chain_streams[k - 1]));
             HIPCHK(c, hipStreamWaitEvent(c->stream, c->joins[k - 1], 0));
@@ -559,7 +575,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
     } else {
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
-        HIPCHK(c, enqueue(c->stream, 0));
+        HIPCHK(c, enqueue(c->stream, 0, 0));
         if (launch_ms) HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
     }
 

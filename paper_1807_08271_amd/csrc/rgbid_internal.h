@@ -128,6 +128,7 @@ struct IterLaunch {
     float2* partials;            // n_red_chunks * kNSum
     int update;                  // 0: normal equations only
     int scale_per;               // sample entries per scale thread: ceil(max sample / kScaleThreads)
+    int kernels;                 // kernels to launch: 1 warp, 2 scale, 4 reduce, 8 solve
 };
 // ev: NULL, or 5 events recorded before the warp kernel and after each of
 // the four kernels (for per-kernel timing).
