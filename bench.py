@@ -306,7 +306,7 @@ def main():
     fused_level = {}
     for line in open(tune_txt):
         f = line.split()
-        if len(f) == 5:    # one batch shape per bench run
+        if len(f) == 6:    # one batch shape per bench run
             fused_level[int(f[0].split("_")[0][1:])] = f[1] == "1"
     os.remove(tune_txt)
 

@@ -229,17 +229,20 @@ rgbid_status rgbid_normal_equations(rgbid_ctx* ctx, const rgbid_pyr* A, const rg
 /* Times, for every level of `params`, candidate launch shapes of the pixel
    kernels on this batch -- warp fused into the reduction or stored, 2 / 4 / 8
    waves per workgroup, 1 / 2 / 4 / 8 / 16 tiles of 64 pixels per wave, and
-   XCD-aware chunk order on or off -- over `reps` replayed iterations
-   (normal equations only, the poses stay at the identity), and keeps the
-   fastest for later calls with a batch of the same shape (pair sizes in
-   order, levels, warp mode, storage) on this context.  best_ms (params->levels
-   entries or NULL) receives the best time per iteration.  Synchronises. */
+   XCD-aware chunk order on or off; then, for the best of those, 1 / 2 / 4 /
+   8 / 16 passes per wave of the warp kernel -- over `reps` replayed
+   iterations (normal equations only, the poses stay at the identity), and
+   keeps the fastest for later calls with a batch of the same shape (pair
+   sizes in order, levels, warp mode, storage) on this context.  Every
+   candidate is timed twice; the four fastest four more times, and the lowest
+   median wins.  best_ms (params->levels entries or NULL) receives the best
+   time per iteration.  Synchronises. */
 rgbid_status rgbid_autotune(rgbid_ctx* ctx, int n, const rgbid_pyr* const* A,
                             const rgbid_pyr* const* B, const rgbid_align_params* params, int reps,
                             double* best_ms);
 
 /* Writes / reads the context's tuned launch shapes as text (one
-   "key fused waves tiles_per_wave xcd_remap" line per entry). */
+   "key fused waves tiles_per_wave xcd_remap warp_passes" line per entry). */
 rgbid_status rgbid_tune_save(const rgbid_ctx* ctx, const char* path);
 rgbid_status rgbid_tune_load(rgbid_ctx* ctx, const char* path);
 

@@ -351,9 +351,9 @@ struct ChildLayout {
     static constexpr int LPP = warp_lanes_per_pixel(LOG2B);     // lanes per pixel
     static constexpr int GPP = warp_pixels_per_pass(LOG2B);     // pixels per pass
     static_assert(CPL * LPP == C && LPP <= 64, "at most 64 lanes per level pixel");
-    static_assert(LPP == 1 || LPP % B == 0, "a lane's children share a column");
-    static constexpr int du(int m) { return LPP == 1 ? m % B : 0; }
-    static constexpr int dv(int m) { return LPP == 1 ? m / B : (LPP / B) * m; }
+    static_assert(LPP % B == 0 || B % LPP == 0, "children rows split evenly over lanes");
+    static constexpr int du(int m) { return LPP >= B ? 0 : LPP * (m % (B / LPP)); }
+    static constexpr int dv(int m) { return LPP >= B ? (LPP / B) * m : m / (B / LPP); }
 };
 
 // Grid position of the pixel of lane group g in the pass that starts at grid
@@ -877,7 +877,7 @@ __device__ __forceinline__ double nu_equation_const(double n, double nud)
 
 // A sample entry that takes no part: +inf, whose weight is exactly 0 under
 // both rules (1/inf = 0), and whose residual is clamped to a finite value in
-// the sums, so its terms are 0 * finite.
+// the sums (v_med3), so its terms are 0 * finite.
 constexpr float kNoSample = __builtin_inff();
 constexpr float kResClamp = 3.0e38f;
 
@@ -905,7 +905,7 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], float i
             float w;
             if constexpr (KIND == RGBID_W_HUBER) w = fminf(1.0f, hk * rcp(fabsf(d)));
             else w = tA * rcp(fmaf(d, d, tB));
-            const float dd = fminf(d, kResClamp);
+            const float dd = __builtin_amdgcn_fmed3f(d, -kResClamp, kResClamp);
             s0[q & 1] += w;
             s1[q & 1] = fmaf(w, dd, s1[q & 1]);
             s2[q & 1] = fmaf(w * dd, dd, s2[q & 1]);

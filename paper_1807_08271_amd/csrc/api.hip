@@ -187,10 +187,12 @@ LevelTune default_tune(int block_log2)
         t.fused = 1;
         t.waves = 4;
         t.tiles_per_wave = 8;
+        t.warp_passes = 1;
     } else {
         t.fused = 0;
         t.waves = 4;
         t.tiles_per_wave = 2;
+        t.warp_passes = 4;
     }
     t.xcd_remap = 1;
     return t;
@@ -334,10 +336,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         tune[l] = it != c->tunes.end() ? it->second : default_tune(b);
         const int gpp = warp_pixels_per_pass(b);
         const int rtiles_per_chunk = tune[l].waves * tune[l].tiles_per_wave;
-        // When the reduction warps its own pixels, the warp kernel only forms
-        // the systematic sample: a few passes per pair, latency-bound, so one
-        // pass per wave to have as many in flight as possible.
-        const int wtiles_per_chunk = tune[l].fused ? tune[l].waves : rtiles_per_chunk;
+        const int wtiles_per_chunk = tune[l].waves * tune[l].warp_passes;
         for (int k = 0; k < nch; ++k) {
             rbeg[k][l].push_back(0);
             for (int i = cfirst[k]; i < cfirst[k + 1]; ++i) {
@@ -950,6 +949,10 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
                         t.waves = waves;
                         t.tiles_per_wave = tpw;
                         t.xcd_remap = remap;
+                        // when the reduction warps its own pixels, the warp
+                        // kernel only forms the systematic sample: few passes
+                        // per pair, so one per wave
+                        t.warp_passes = fused ? 1 : tpw;
                         cands.push_back(Cand{t, {}});
                     }
         auto time_cand = [&](Cand& cd, int times) -> rgbid_status {
@@ -988,6 +991,23 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
                 best_t = median(cands[i].ms);
                 best = cands[i].t;
             }
+        // then the warp kernel's passes per wave, the rest fixed
+        {
+            std::vector<Cand> wc;
+            for (int wp : {1, 2, 4, 8, 16})
+                if (wp != best.warp_passes) {
+                    LevelTune t = best;
+                    t.warp_passes = wp;
+                    wc.push_back(Cand{t, {}});
+                }
+            for (Cand& cd : wc) {
+                if (rgbid_status st = time_cand(cd, 4); st != RGBID_OK) return fail(st);
+                if (median(cd.ms) < best_t) {
+                    best_t = median(cd.ms);
+                    best = cd.t;
+                }
+            }
+        }
         c->tunes[key] = best;
         if (best_ms) best_ms[l] = best_t / reps;
     }
@@ -1003,8 +1023,8 @@ rgbid_status rgbid_tune_save(const rgbid_ctx* c, const char* path)
     FILE* f = std::fopen(path, "w");
     if (!f) return RGBID_E_ARG;
     for (const auto& kv : c->tunes)
-        std::fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.fused, kv.second.waves,
-                     kv.second.tiles_per_wave, kv.second.xcd_remap);
+        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.fused, kv.second.waves,
+                     kv.second.tiles_per_wave, kv.second.xcd_remap, kv.second.warp_passes);
     std::fclose(f);
     return RGBID_OK;
 }
@@ -1017,9 +1037,11 @@ rgbid_status rgbid_tune_load(rgbid_ctx* c, const char* path)
     char key[512];
     LevelTune t;
     int nread = 0;
-    while (std::fscanf(f, "%511s %d %d %d %d", key, &t.fused, &t.waves, &t.tiles_per_wave,
-                       &t.xcd_remap) == 5) {
-        if (t.waves < 1 || t.waves > 8 || t.tiles_per_wave < 1 || t.tiles_per_wave > 64) continue;
+    while (std::fscanf(f, "%511s %d %d %d %d %d", key, &t.fused, &t.waves, &t.tiles_per_wave,
+                       &t.xcd_remap, &t.warp_passes) == 6) {
+        if (t.waves < 1 || t.waves > 8 || t.tiles_per_wave < 1 || t.tiles_per_wave > 64 ||
+            t.warp_passes < 1 || t.warp_passes > 64)
+            continue;
         c->tunes[key] = t;
         ++nread;
     }

@@ -86,8 +86,9 @@ struct IterParams {
 struct LevelTune {
     int fused;           // 1: reduce kernel warps itself; 0: warped images stored
     int waves;           // waves per workgroup of the pixel kernels
-    int tiles_per_wave;  // tiles each wave walks
+    int tiles_per_wave;  // tiles each wave of the reduction walks
     int xcd_remap;       // map consecutive chunks onto one XCD
+    int warp_passes;     // passes each wave of the warp kernel walks
 };
 
 // ---------------------------------------------------------------- launchers
