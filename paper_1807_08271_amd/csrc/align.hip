@@ -352,8 +352,16 @@ struct ChildLayout {
     static constexpr int GPP = warp_pixels_per_pass(LOG2B);     // pixels per pass
     static_assert(CPL * LPP == C && LPP <= 64, "at most 64 lanes per level pixel");
     static_assert(LPP % B == 0 || B % LPP == 0, "children rows split evenly over lanes");
-    static constexpr int du(int m) { return LPP >= B ? 0 : LPP * (m % (B / LPP)); }
-    static constexpr int dv(int m) { return LPP >= B ? (LPP / B) * m : m / (B / LPP); }
+    static constexpr int du(int m)
+    {
+        if constexpr (LPP >= B) return 0;
+        else return LPP * (m % (B / LPP));
+    }
+    static constexpr int dv(int m)
+    {
+        if constexpr (LPP >= B) return (LPP / B) * m;
+        else return m / (B / LPP);
+    }
 };
 
 // Grid position of the pixel of lane group g in the pass that starts at grid
@@ -578,53 +586,14 @@ __device__ __forceinline__ void pixel_terms(const LevelView& A, const LevelRay& 
     terms_core<JAC>(R, ray_x(R, u), ray_y(R, v), c, n, m, Is, Ws, wv, T);
 }
 
-// Robust weight of a normalised residual x: Huber min(1, k/|x|) or Student-t
-// (nu + 1)/(nu + x^2) (sec. 6.3).  Both branches of the Huber rule are
-// evaluated and selected, so the weight costs no divergent branch.
-template <int KIND>
-__device__ __forceinline__ float omega_k(float x, float nu, float k)
-{
-    if constexpr (KIND == RGBID_W_HUBER) {
-        const float ax = fabsf(x);
-        const float h = k * rcp(ax);
-        return ax <= k ? 1.0f : h;
-    } else {
-        return (nu + 1.0f) * rcp(fmaf(x, x, nu));
-    }
-}
-
-__device__ __forceinline__ float omega(int kind, float x, float nu, float k)
-{
-    return kind == RGBID_W_HUBER ? omega_k<RGBID_W_HUBER>(x, nu, k)
-                                 : omega_k<RGBID_W_STUDENT_T>(x, nu, k);
-}
-
-__device__ __forceinline__ void accum(float* acc, const float* J, float w, float r)
-{
-    float s[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) s[a] = w * J[a];
-    int k = 0;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int b = a; b < 6; ++b) {
-            acc[k] = fmaf(s[a], J[b], acc[k]);
-            ++k;
-        }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) acc[21 + a] = fmaf(s[a], r, acc[21 + a]);
-    acc[27] = fmaf(w * r, r, acc[27]);
-}
-
-
-// Robust weighting of one iteration: the channels' location, inverse scale,
-// nu and prior weight 1/sigma^2, and whether a channel takes part.
+// Robust weighting of one iteration: the channels' location, inverse scale
+// and nu, sqrt(k) and sqrt(nu + 1) for the square-rooted weights, and
+// whether a channel takes part.
 struct RobustW {
     int kind;
-    float kh;
-    float muI, isI, nuI, wI0;
-    float muW, isW, nuW, wW0;
+    float sqk;
+    float muI, isI, nuI, sqnuI;
+    float muW, isW, nuW, sqnuW;
     bool enI, enW;
 };
 
@@ -632,7 +601,7 @@ __device__ __forceinline__ RobustW robust_w(const IterLaunch& L, const PairState
 {
     RobustW W;
     W.kind = L.ip.weight;
-    W.kh = L.ip.huber_k;
+    W.sqk = sqrtf(L.ip.huber_k);
     W.enI = S.ns[0] > 0;
     W.enW = S.ns[1] > 0;
     W.muI = S.mu[0];
@@ -641,26 +610,107 @@ __device__ __forceinline__ RobustW robust_w(const IterLaunch& L, const PairState
     W.isW = 1.0f / S.sigma[1];
     W.nuW = S.nu[1];
     W.nuI = (W.kind == RGBID_W_STUDENT_T && L.ip.estimate_nu) ? fmaxf(S.nu[0], W.nuW) : S.nu[0];
-    W.wI0 = W.isI * W.isI;
-    W.wW0 = W.isW * W.isW;
+    W.sqnuI = sqrtf(W.nuI + 1.0f);
+    W.sqnuW = sqrtf(W.nuW + 1.0f);
     return W;
 }
 
-// Adds one pixel's weighted terms to the 28 per-lane sums; the counts of
+// sqrt of the robust weight of a normalised residual x (sec. 6.3): Huber
+// min(1, sqrt(k / |x|)), Student-t sqrt(nu + 1) / sqrt(nu + x^2).
+__device__ __forceinline__ float sqrt_omega(int kind, float x, float nu, float sqk, float sqnu1)
+{
+    return kind == RGBID_W_HUBER ? fminf(1.0f, sqk * rsq(fabsf(x))) : sqnu1 * rsq(fmaf(x, x, nu));
+}
+
+// The normal equations on the matrix cores.  The sums over pixels of w J J^T,
+// w J r and w r^2 (2eq:minimisationIRLS) are the upper blocks of the sum of
+// the outer products of v = sqrt(w) (J_0 .. J_5, r, 0) with themselves: rows
+// and columns 0-3 (TL), rows 0-3 x columns 4-7 (TR) and rows and columns 4-7
+// (BR).  Per tile a wave stages its 128 vectors (the I and W terms of 64
+// pixels) in LDS as two planes of float4, (v0, v4, v1, v5) and (v2, v6, v3,
+// v7), each plane in vector order (a lane's stores are consecutive 16-byte
+// words: no bank conflicts), and feeds them 16 at a time to
+// v_mfma_f32_4x4x1_16b_f32: block b takes vector 16 q + b, lane 4 b + i
+// supplying (v_i, v_4+i), and block b's 4x4 product accumulates in lanes
+// 4 b + j, register i.  Scaling uses the legacy multiply (0 x anything = 0),
+// so a term that takes no part stages exact zeros.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct NeAcc {
+    v4f tl, tr, br;
+};
+
+constexpr int kStageFloat4PerWave = 256;   // 128 vectors x 8 floats
+
+__device__ __forceinline__ float lmul(float a, float b)
+{
+    float r;
+    asm("v_mul_legacy_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ void stage_vector(float4* st, int slot, float s, const float* J, float r)
+{
+    st[slot] = make_float4(lmul(s, J[0]), lmul(s, J[4]), lmul(s, J[1]), lmul(s, J[5]));
+    st[128 + slot] = make_float4(lmul(s, J[2]), lmul(s, r), lmul(s, J[3]), 0.0f);
+}
+
+// One tile's terms of the 64 lanes into the accumulators; the counts of
 // contributing pixels go to the wave-uniform counters cI, cW.
-__device__ __forceinline__ void accumulate_terms(float* acc, const Terms& T, const RobustW& W,
-                                                 unsigned& cI, unsigned& cW)
+__device__ __forceinline__ void ne_add(NeAcc& na, float4* st, int lane, const Terms& T,
+                                       const RobustW& W, unsigned& cI, unsigned& cW)
 {
     const bool tI = T.vI & W.enI, tW = T.vW & W.enW;
     cI += (unsigned)__popcll(__ballot(tI));
     cW += (unsigned)__popcll(__ballot(tW));
-    if (tI) {
-        const float w = omega(W.kind, (T.rI - W.muI) * W.isI, W.nuI, W.kh) * W.wI0;
-        accum(acc, T.JI, w, T.rI);
+    const float xI = (T.rI - W.muI) * W.isI, xW = (T.rW - W.muW) * W.isW;
+    const float sI = tI ? sqrt_omega(W.kind, xI, W.nuI, W.sqk, W.sqnuI) * W.isI : 0.0f;
+    const float sW =
+        tW ? sqrt_omega(W.kind, xW, W.nuW, W.sqk, W.sqnuW) * W.isW * __builtin_amdgcn_sqrtf(T.lam)
+           : 0.0f;
+    stage_vector(st, lane, sI, T.JI, T.rI);
+    stage_vector(st, 64 + lane, sW, T.JW, T.rW);
+    // lane 4 b + i: plane i / 2, vector b (+ 16 q), half i % 2 of the float4
+    const float2* rd = reinterpret_cast<const float2*>(st) + 256 * ((lane & 3) >> 1) +
+                       2 * (lane >> 2) + (lane & 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float2 e = rd[32 * q];
+        na.tl = __builtin_amdgcn_mfma_f32_4x4x1f32(e.x, e.x, na.tl, 0, 0, 0);
+        na.tr = __builtin_amdgcn_mfma_f32_4x4x1f32(e.x, e.y, na.tr, 0, 0, 0);
+        na.br = __builtin_amdgcn_mfma_f32_4x4x1f32(e.y, e.y, na.br, 0, 0, 0);
     }
-    if (tW) {
-        const float w = T.lam * omega(W.kind, (T.rW - W.muW) * W.isW, W.nuW, W.kh) * W.wW0;
-        accum(acc, T.JW, w, T.rW);
+}
+
+// Where sum k of the 28 (H upper triangle row-major, g, cost) sits in the
+// accumulators: register row 4 t + i (t = 0 TL, 1 TR, 2 BR) of lanes
+// 4 b + j, coded 4 (4 t + i) + j.
+__constant__ unsigned char kNeMap[28] = {0,  1,  2,  3,  16, 17, 5,  6,  7,  20, 21, 10, 11, 24,
+                                         25, 15, 28, 29, 32, 33, 37, 18, 22, 26, 30, 34, 38, 42};
+
+// The wave's totals of the 28 sums and the two counts into out[0 .. 29]
+// (LDS), through the wave's staging area; sum k is added over the 16 blocks
+// in block order.
+__device__ __forceinline__ void ne_wave_totals(const NeAcc& na, float4* st, int lane, unsigned cI,
+                                               unsigned cW, float* out)
+{
+    float* sc = reinterpret_cast<float*>(st);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        sc[(0 + r) * 64 + lane] = na.tl[r];
+        sc[(4 + r) * 64 + lane] = na.tr[r];
+        sc[(8 + r) * 64 + lane] = na.br[r];
+    }
+    if (lane < 28) {
+        const unsigned c = kNeMap[lane];
+        const float* src = sc + (c >> 2) * 64 + (c & 3);
+        float t = 0.0f;
+        for (int b = 0; b < 16; ++b) t += src[4 * b];
+        out[lane] = t;
+    } else if (lane == 28) {
+        out[28] = (float)cI;
+    } else if (lane == 29) {
+        out[29] = (float)cW;
     }
 }
 
@@ -1085,19 +1135,23 @@ __device__ __forceinline__ void advance(int& idx, int& u, int& v, int step, int 
 // Level pixel that is its own warp child: warp, residuals, terms.
 template <bool F16>
 __device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, const RefPx& r, int n,
-                                          const RobustW& W, float* acc, unsigned& cI, unsigned& cW)
+                                          const RobustW& W, NeAcc& na, float4* st, int lane,
+                                          unsigned& cI, unsigned& cW)
 {
     float Is, Ws;
     const bool wv = warp_ray<F16>(G, r.xu, r.xv, r.c.y, Is, Ws) & (r.idx < n);
     Terms T;
     terms_core<true>(R, r.xu, r.xv, r.c, r.nb, r.m, Is, Ws, wv, T);
-    accumulate_terms(acc, T, W, cI, cW);
+    ne_add(na, st, lane, T, W, cI, cW);
 }
 
+// Dynamic LDS: kStageFloat4PerWave float4 per wave (the normal-equation
+// staging area).
 template <bool F16, int LOG2B, bool FUSED>
 __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
 {
     __shared__ float lds[8 * kNSum];
+    extern __shared__ float4 ne_stage[];
     const int ci = chunk_of_block(blockIdx.x, L.n_red_chunks, L.tune.xcd_remap);
     const Chunk ch = L.red_chunks[ci];
     const PairState& S = L.states[ch.pair];
@@ -1110,12 +1164,12 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const void* const warped = D.warped;
     const RobustW W = robust_w(L, S);
 
-    float acc[kNSum];
-#pragma unroll
-    for (int k = 0; k < kNSum; ++k) acc[k] = 0.0f;
+    NeAcc na;
+    na.tl = na.tr = na.br = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     unsigned cI = 0, cW = 0;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float4* const st = ne_stage + wave * kStageFloat4PerWave;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
     const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
@@ -1134,7 +1188,7 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             advance(idx, u, v, step, su, sv, gd.gw);
             RefPx nxt;
             load_ref<F16>(A, R, gd.n, idx, u, v, nxt);
-            own_pixel<F16>(G, R, r, gd.n, W, acc, cI, cW);
+            own_pixel<F16>(G, R, r, gd.n, W, na, st, lane, cI, cW);
             r = nxt;
         }
     } else {
@@ -1155,17 +1209,10 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             }
             Terms T;
             pixel_terms<F16, true>(A, R, u, v, Is, Ws, wv, T);
-            accumulate_terms(acc, T, W, cI, cW);
+            ne_add(na, st, lane, T, W, cI, cW);
         }
     }
-    acc[28] = lane == 0 ? (float)cI : 0.0f;
-    acc[29] = lane == 0 ? (float)cW : 0.0f;
-#pragma unroll
-    for (int k = 0; k < kNSum; ++k) acc[k] = wave_sum_to_last(acc[k]);
-    if (lane == 63) {
-#pragma unroll
-        for (int k = 0; k < kNSum; ++k) lds[wave * kNSum + k] = acc[k];
-    }
+    ne_wave_totals(na, st, lane, cI, cW, lds + wave * kNSum);
     __syncthreads();
     if (threadIdx.x < kNSum) {
         // compensated (two-sum) FP32 sum over the waves of the workgroup
@@ -1359,10 +1406,13 @@ hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L, hipEvent_t con
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     if ((L.kernels & 4) && L.n_red_chunks > 0) {
+        const size_t lds_bytes = sizeof(float4) * kStageFloat4PerWave * L.tune.waves;
         if (L.tune.fused)
-            hipLaunchKernelGGL((k_reduce<F16, LOG2B, true>), dim3(L.n_red_chunks), blk, 0, s, L);
+            hipLaunchKernelGGL((k_reduce<F16, LOG2B, true>), dim3(L.n_red_chunks), blk, lds_bytes, s,
+                               L);
         else
-            hipLaunchKernelGGL((k_reduce<F16, LOG2B, false>), dim3(L.n_red_chunks), blk, 0, s, L);
+            hipLaunchKernelGGL((k_reduce<F16, LOG2B, false>), dim3(L.n_red_chunks), blk, lds_bytes,
+                               s, L);
     }
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
     if (L.kernels & 8) hipLaunchKernelGGL(k_solve, dim3(L.npairs), dim3(64), 0, s, L);
