@@ -210,6 +210,88 @@ def warmstart_compare(ctx, npairs, steps):
     return res
 
 
+# Synthetic Kinect-like calibration for the sensor input path (Brown
+# coefficients k1 k2 p1 p2 k3, depth correction, spatial correction, depth ->
+# colour extrinsics): values of the order such sensors have, not a fit.
+SENSOR_K_COLOR = [0.12, -0.25, 0.0015, -0.001, 0.1]
+SENSOR_K_DEPTH = [-0.08, 0.15, -0.001, 0.0008, -0.05]
+SENSOR_Q0 = [1e-3, 2e-3, -1e-3, 5e-4, 1e-3, -2e-3, 1e-3, 5e-4, -5e-4]
+SENSOR_Q1 = [1.01, -0.02, 0.01, 0.005, 0.01, -0.01, 0.005, 0.002, -0.002]
+
+
+def frontend_measure(ctx, pair, reps=20):
+    """The entry points around the alignment at 640x480, each timed per call
+    on the host clock (the calls read their results back, so every figure
+    includes launch and read-back): pose covariance (bilateral filter + one
+    filtered linearisation), the covisibility ratio at level 2, the tracking
+    front-end over a constant-velocity sequence (alignment against the
+    reference, covisibility, switching, odometry covariance, fusion per
+    frame), and the sensor input path (depth correction, undistortion and
+    forward registration)."""
+    import numpy as np
+    import torch
+    from scipy.spatial.transform import Rotation
+    import synth
+    from paper_1807_08271_amd import rgbid as rg
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+    def per_call_us(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return round((time.perf_counter() - t0) / n * 1e6, 1)
+
+    out = {"workload": "640x480; pair 0 of the batch at its aligned pose; a 16-frame "
+                       "constant-velocity room sequence (2 deg, 2 cm per frame); one rendered "
+                       "room frame through a synthetic Kinect-like calibration"}
+    prm = rg.rgbid_default_params(levels=4, iters=[10] * 4, weight=rg.RGBID_W_HUBER)
+    A = rg.rgbid_pyramid(ctx, pair.cam, 4, rg.RGBID_F32, up(pair.A.I), up(pair.A.W))
+    B = rg.rgbid_pyramid(ctx, pair.cam, 4, rg.RGBID_F32, up(pair.B.I), up(pair.B.W))
+    R, t, _, _ = rg.rgbid_align(ctx, A, B, prm)
+    out["align_one_pair_us"] = per_call_us(lambda: rg.rgbid_align(ctx, A, B, prm), reps)
+    out["covariance_us"] = per_call_us(lambda: rg.rgbid_covariance(ctx, A, B, (R, t), prm), reps)
+    out["covisibility_us"] = per_call_us(
+        lambda: rg.rgbid_covisibility(ctx, A, B, 2, (R, t), 0.01), reps)
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+    cam, _, frames = synth.track_sequence(16, 2.0, 0.02, seed=1, cam=synth.camera_640(), ss=2)
+    tp = rg.rgbid_tracker_default_params(align=prm)
+    trk = rg.rgbid_tracker_create(ctx, cam, 4, rg.RGBID_F32, tp)
+    Is, Ws = [up(f.I) for f in frames], [up(f.W) for f in frames]
+    rg.rgbid_track(ctx, trk, Is[0], Ws[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, len(frames)):
+        rg.rgbid_track(ctx, trk, Is[k], Ws[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / (len(frames) - 1) * 1e3
+    out["tracker_ms_per_frame"] = round(ms, 3)
+    out["tracker_frames_per_s"] = round(1e3 / ms, 1)
+    rg.rgbid_tracker_free(trk)
+
+    color = synth.camera_640()
+    depth = synth.Camera(640, 480, 575.8, 575.8, 319.5, 239.5)
+    scene = synth.room_scene(7006)
+    Z, I = synth.render(scene, color, (Rotation.from_euler("x", -10, degrees=True).as_matrix(),
+                                       np.zeros(3)), ss=1)
+    Z = np.where(np.isfinite(Z) & (Z > 0.5) & (Z < 5.0), Z, 0.0)
+    S = rg.make_sensor(color, depth, k_color=SENSOR_K_COLOR, k_depth=SENSOR_K_DEPTH, beta0=0.002,
+                       beta1=0.995, p0=(4, 4), spatial=True, q0=SENSOR_Q0, q1=SENSOR_Q1,
+                       R_dc=Rotation.from_rotvec([0.002, -0.003, 0.001]).as_matrix(),
+                       t_dc=np.array([0.025, 0.001, -0.002]))
+    gI, gZ = up(I), up(Z)
+    oI, oW = rg.rgbid_preprocess(ctx, S, gI, gZ)
+    out["preprocess_us"] = per_call_us(lambda: rg.rgbid_preprocess(ctx, S, gI, gZ, oI, oW), reps)
+    L = rg.make_lens(color, SENSOR_K_COLOR)
+    out["undistort_us"] = per_call_us(lambda: rg.rgbid_undistort(ctx, L, gI, False, oI), reps)
+    log("front-end (per call, host clock): %s" % {k: v for k, v in out.items() if k != "workload"})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +307,10 @@ def main():
                     help="uniform: --pairs pairs at 640x480 (the headline workload); mixed: "
                          "24 x 320x240 + 32 x 640x480 + 8 x 1280x960 pairs (batched form)")
     ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--no-frontend", action="store_true",
+                    help="skip the per-call timings of covariance, covisibility, tracker, sensor path")
+    ap.add_argument("--frontend-only", action="store_true",
+                    help="only the front-end timings (for a kernel trace of those entry points)")
     ap.add_argument("--ws-pairs", type=int, default=64)
     ap.add_argument("--tune-file", default=None, help="load tuned launch shapes from this file")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -266,6 +352,10 @@ def main():
     storage = rg.RGBID_F16 if f16 else rg.RGBID_F32
 
     ctx = rg.rgbid_create(0)
+    if args.frontend_only:
+        print(json.dumps({"frontend": frontend_measure(ctx, pairs[0])}), flush=True)
+        rg.rgbid_destroy(ctx)
+        return
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     IA = [up(p.A.I) for p in pairs]
     WA = [up(p.A.W) for p in pairs]
@@ -437,6 +527,8 @@ def main():
     }
     if not args.no_warmstart:
         out["warmstart"] = warmstart_compare(ctx, args.ws_pairs, args.steps)
+    if not args.no_frontend:
+        out["frontend"] = frontend_measure(ctx, pairs[0])
     if not args.no_cpu:
         log("timing the FP64 oracle on a bounded sample ...")
         op = oracle.Params(levels=4, iters=[10] * 4, weight=args.weight, warp=args.warp,

@@ -52,6 +52,9 @@ def main(argv=None):
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--roof-bytes", nargs="*", default=[], metavar="KERNEL=BYTES",
+                    help="algorithmic bytes per launch of named kernels: adds a table of their "
+                         "achieved GB/s against the 8 TB/s HBM roof")
     a = ap.parse_args(argv)
 
     lines = ["# rocprofv3: %s" % a.workload, "", "Command (from the repository root):", "",
@@ -64,6 +67,20 @@ def main(argv=None):
         lines.append("| k_%s | %s | %s | %.2f | %.3f |" % (kk[0], kk[2], r["Calls"],
                                                            float(r["AverageNs"]) / 1e3,
                                                            float(r["TotalDurationNs"]) / 1e6))
+    if a.roof_bytes:
+        want = {k: float(v) for k, v in (e.split("=", 1) for e in a.roof_bytes)}
+        avg = {}
+        for r in csv.DictReader(open(a.stats)):
+            kk = kernel_key(r["Name"])
+            if kk and "rgbid" in r["Name"] and ("k_" + kk[0]) in want:
+                avg[("k_" + kk[0])] = float(r["AverageNs"]) / 1e3
+        lines += ["", "## Against the HBM roof (8 TB/s): algorithmic bytes per launch / average "
+                  "duration", "", "| kernel | bytes per launch | average us | GB/s | fraction |",
+                  "|---|---|---|---|---|"]
+        for k, b in want.items():
+            if k in avg:
+                gbs = b / (avg[k] * 1e-6) / 1e9
+                lines.append("| %s | %.0f | %.2f | %.1f | %.4f |" % (k, b, avg[k], gbs, gbs / 8000.0))
     # copy calibration: counters of the copy kernel against the known bytes
     cal = {}
     for path in a.copy:
