@@ -301,6 +301,18 @@ rgbid_status rgbid_keyframe_init(rgbid_ctx* ctx, const rgbid_camera* cam, const 
 rgbid_status rgbid_fuse(rgbid_ctx* ctx, rgbid_kf* kf, const float* Wk_dev, size_t pitch_elems,
                         const rgbid_pose* T_kf_k, double tol, long long* n_fused);
 
+/* Fuses n frames (1 <= n <= 256) into the keyframe in order, as n calls of
+   rgbid_fuse would (the same per-pixel arithmetic, so the same result bit for
+   bit), in one launch: each keyframe pixel is read and written once instead
+   of n times.  Wk_dev[i] is frame i's caller-owned FP32 inverse-depth map
+   (device, all with row pitch `pitch_elems`), T_kf_k[i] its pose in the
+   keyframe.  If n_fused != NULL (n entries) it receives the number of
+   pixels fused by each frame (synchronises); otherwise the call does not
+   synchronise.  Errors: E_ARG. */
+rgbid_status rgbid_fuse_batch(rgbid_ctx* ctx, rgbid_kf* kf, int n, const float* const* Wk_dev,
+                              size_t pitch_elems, const rgbid_pose* T_kf_k, double tol,
+                              long long* n_fused);
+
 /* Re-initialises an existing keyframe from a new FP32 inverse-depth map of
    the same size, with C = 1 (no allocation, does not synchronise). */
 rgbid_status rgbid_keyframe_reset(rgbid_ctx* ctx, rgbid_kf* kf, const float* W_dev,

@@ -68,7 +68,7 @@ struct rgbid_ctx {
     hipStream_t stream = nullptr;    // work stream (the caller's)
     hipStream_t cap = nullptr;       // private stream for graph capture
     std::string err;
-    DevBuf pairs, states, tables, partials, warped, sample, frames, covis, cov_img, reg;
+    DevBuf pairs, states, tables, partials, warped, sample, frames, covis, cov_img, reg, fuse;
     rgbid_pyr* cov_pyr = nullptr;    // filtered reference of the covariance iteration
     void* h_stage = nullptr;         // pinned upload staging
     size_t h_stage_bytes = 0;
@@ -717,7 +717,7 @@ void rgbid_destroy(rgbid_ctx* c)
     if (c->cov_pyr) rgbid_pyramid_free(c->cov_pyr);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     for (DevBuf* b : {&c->pairs, &c->states, &c->tables, &c->partials, &c->warped, &c->sample,
-                      &c->frames, &c->covis, &c->cov_img, &c->reg})
+                      &c->frames, &c->covis, &c->cov_img, &c->reg, &c->fuse})
         if (b->p) (void)hipFree(b->p);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_down) (void)hipHostFree(c->h_down);
@@ -1119,6 +1119,61 @@ rgbid_status rgbid_fuse(rgbid_ctx* c, rgbid_kf* kf, const float* Wk_dev, size_t 
                                  hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *n_fused = (long long)*static_cast<unsigned long long*>(c->h_down);
+    }
+    return RGBID_OK;
+}
+
+rgbid_status rgbid_fuse_batch(rgbid_ctx* c, rgbid_kf* kf, int n, const float* const* Wk_dev,
+                              size_t pitch_elems, const rgbid_pose* T, double tol,
+                              long long* n_fused)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!kf || !Wk_dev || !T) return set_err(c, RGBID_E_ARG, "NULL keyframe, images or poses");
+    if (n < 1 || n > kMaxFuseBatch) return set_err(c, RGBID_E_ARG, "n outside 1..%d", kMaxFuseBatch);
+    for (int i = 0; i < n; ++i)
+        if (!Wk_dev[i]) return set_err(c, RGBID_E_ARG, "NULL image %d", i);
+    if (kf->device != c->device) return set_err(c, RGBID_E_ARG, "keyframe on another device");
+    if (pitch_elems < (size_t)kf->cam.width) return set_err(c, RGBID_E_ARG, "pitch < width");
+    if (!(tol > 0.0)) return set_err(c, RGBID_E_ARG, "tol must be > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    // device workspace: the frame table, then n counters
+    const size_t tab = align_up((size_t)n * sizeof(FuseFrame), 256);
+    if ((st = ensure(c, c->fuse, tab + (size_t)n * sizeof(unsigned long long))) != RGBID_OK)
+        return st;
+    char* stage = nullptr;
+    if ((st = stage_begin(c, (size_t)n * sizeof(FuseFrame), &stage)) != RGBID_OK) return st;
+    FuseFrame* fr = reinterpret_cast<FuseFrame*>(stage);
+    for (int i = 0; i < n; ++i) {
+        fr[i].Wk = Wk_dev[i];
+        pose_floats(T[i].R, T[i].t, fr[i].RT, fr[i].Rtt);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->fuse.p, stage, (size_t)n * sizeof(FuseFrame), hipMemcpyHostToDevice,
+                             c->stream));
+    if ((st = stage_end(c)) != RGBID_OK) return st;
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(static_cast<char*>(c->fuse.p) + tab);
+    FuseBatchArgs a;
+    a.Wkf = kf->W;
+    a.Ckf = kf->C;
+    a.frames = static_cast<const FuseFrame*>(c->fuse.p);
+    a.n = n;
+    a.pitch = (long long)pitch_elems;
+    a.w = kf->cam.width;
+    a.h = kf->cam.height;
+    a.fx = (float)kf->cam.fx;
+    a.fy = (float)kf->cam.fy;
+    a.cx = (float)kf->cam.cx;
+    a.cy = (float)kf->cam.cy;
+    a.tol = (float)tol;
+    a.count = n_fused ? cnt : nullptr;
+    if (n_fused) HIPCHK(c, hipMemsetAsync(cnt, 0, (size_t)n * sizeof(unsigned long long), c->stream));
+    HIPCHK(c, launch_fuse_batch(c->stream, a));
+    if (n_fused) {
+        if ((st = ensure_down(c, (size_t)n * sizeof(unsigned long long))) != RGBID_OK) return st;
+        HIPCHK(c, hipMemcpyAsync(c->h_down, cnt, (size_t)n * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i < n; ++i) n_fused[i] = (long long)static_cast<unsigned long long*>(c->h_down)[i];
     }
     return RGBID_OK;
 }

@@ -10,6 +10,68 @@ namespace {
 
 __device__ __forceinline__ bool w_valid(float w) { return w > 0.0f && w < INFINITY; }
 
+// One frame's fusion step at keyframe pixel (u, v) (sec. 7.2): the pixel
+// with fused inverse depth wkf (valid) is transferred into frame k with the
+// pose (RT = R^T, Rtt = R^T t), W_k is sampled bilinearly, and if it passes
+// the covisibility test the warped inverse depth is merged into (wkf, ckf).
+// Returns whether the pixel fused.
+__device__ __forceinline__ bool fuse_step(const float* __restrict__ Wk, long long pitch, int w,
+                                          int h, float fx, float fy, float cx, float cy,
+                                          const float* RT, const float* Rtt, float tol, int u,
+                                          int v, float& wkf, float& ckf)
+{
+    const float rx = ((float)u - cx) / fx, ry = ((float)v - cy) / fy;
+    const float ax = fmaf(RT[0], rx, fmaf(RT[1], ry, RT[2]));
+    const float ay = fmaf(RT[3], rx, fmaf(RT[4], ry, RT[5]));
+    const float az = fmaf(RT[6], rx, fmaf(RT[7], ry, RT[8]));
+    // W_kf * Y with Y = R^T (x / W_kf - t)
+    const float yx = fmaf(-wkf, Rtt[0], ax), yy = fmaf(-wkf, Rtt[1], ay);
+    const float yz = fmaf(-wkf, Rtt[2], az);
+    if (!(yz > 0.0f)) return false;
+    const float iz = 1.0f / yz;
+    const float ub = fmaf(fx * yx, iz, cx), vb = fmaf(fy * yy, iz, cy);
+    if (!(ub >= -0.5f && ub < (float)w - 0.5f && vb >= -0.5f && vb < (float)h - 0.5f)) return false;
+    const float fu = floorf(ub), fv = floorf(vb);
+    const float al = ub - fu, be = vb - fv;
+    int x0 = (int)fu, y0 = (int)fv;
+    const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+    x0 = max(x0, 0);
+    y0 = max(y0, 0);
+    const float p00 = Wk[(long long)y0 * pitch + x0];
+    const float p10 = Wk[(long long)y0 * pitch + x1];
+    const float p01 = Wk[(long long)y1 * pitch + x0];
+    const float p11 = Wk[(long long)y1 * pitch + x1];
+    if (!(w_valid(p00) && w_valid(p10) && w_valid(p01) && w_valid(p11))) return false;
+    const float wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 +
+                     (1.0f - al) * be * p01 + al * be * p11;
+    // predicted inverse depth in frame k: 1 / Y_z = W_kf / yz
+    const float wk = wkf * iz;
+    if (!(fabsf(wb - wk) < tol)) return false;
+    const float den = fmaf(wb, Rtt[2], 1.0f);
+    const float ws = az * wb / den;
+    const float q = den * den / az;
+    const float ck = q * q;
+    if (!(w_valid(ws) && ck > 0.0f && ck < INFINITY)) return false;
+    wkf = (wkf * ckf + ck * ws) / (ckf + ck);
+    ckf = ckf + ck;
+    return true;
+}
+
+// Adds the workgroup's count of fused pixels (256 threads) to *count.
+__device__ __forceinline__ void add_count(unsigned int* wave_counts, bool fused,
+                                          unsigned long long* count)
+{
+    const unsigned long long bal = __ballot(fused);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wave_counts[wave] = (unsigned int)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int n = wave_counts[0] + wave_counts[1] + wave_counts[2] + wave_counts[3];
+        if (n) atomicAdd(count, (unsigned long long)n);
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(256) k_fuse(FuseArgs a)
 {
     __shared__ unsigned int wave_counts[4];
@@ -17,60 +79,48 @@ __global__ void __launch_bounds__(256) k_fuse(FuseArgs a)
     bool fused = false;
     if (i < a.w * a.h) {
         const int v = i / a.w, u = i - v * a.w;
-        const float wkf = a.Wkf[i];
+        float wkf = a.Wkf[i];
         if (w_valid(wkf)) {
-            const float rx = ((float)u - a.cx) / a.fx, ry = ((float)v - a.cy) / a.fy;
-            const float ax = fmaf(a.RT[0], rx, fmaf(a.RT[1], ry, a.RT[2]));
-            const float ay = fmaf(a.RT[3], rx, fmaf(a.RT[4], ry, a.RT[5]));
-            const float az = fmaf(a.RT[6], rx, fmaf(a.RT[7], ry, a.RT[8]));
-            // W_kf * Y with Y = R^T (x / W_kf - t)
-            const float yx = fmaf(-wkf, a.Rtt[0], ax), yy = fmaf(-wkf, a.Rtt[1], ay);
-            const float yz = fmaf(-wkf, a.Rtt[2], az);
-            if (yz > 0.0f) {
-                const float iz = 1.0f / yz;
-                const float ub = fmaf(a.fx * yx, iz, a.cx), vb = fmaf(a.fy * yy, iz, a.cy);
-                if (ub >= -0.5f && ub < (float)a.w - 0.5f && vb >= -0.5f && vb < (float)a.h - 0.5f) {
-                    const float fu = floorf(ub), fv = floorf(vb);
-                    const float al = ub - fu, be = vb - fv;
-                    int x0 = (int)fu, y0 = (int)fv;
-                    const int x1 = min(x0 + 1, a.w - 1), y1 = min(y0 + 1, a.h - 1);
-                    x0 = max(x0, 0);
-                    y0 = max(y0, 0);
-                    const float p00 = a.Wk[(long long)y0 * a.pitch + x0];
-                    const float p10 = a.Wk[(long long)y0 * a.pitch + x1];
-                    const float p01 = a.Wk[(long long)y1 * a.pitch + x0];
-                    const float p11 = a.Wk[(long long)y1 * a.pitch + x1];
-                    if (w_valid(p00) && w_valid(p10) && w_valid(p01) && w_valid(p11)) {
-                        const float wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 +
-                                         (1.0f - al) * be * p01 + al * be * p11;
-                        // predicted inverse depth in frame k: 1 / Y_z = W_kf / yz
-                        const float wk = wkf * iz;
-                        if (fabsf(wb - wk) < a.tol) {
-                            const float den = fmaf(wb, a.Rtt[2], 1.0f);
-                            const float ws = az * wb / den;
-                            const float q = den * den / az;
-                            const float ck = q * q;
-                            if (w_valid(ws) && ck > 0.0f && ck < INFINITY) {
-                                const float ckf = a.Ckf[i];
-                                a.Wkf[i] = (wkf * ckf + ck * ws) / (ckf + ck);
-                                a.Ckf[i] = ckf + ck;
-                                fused = true;
-                            }
-                        }
-                    }
-                }
+            float ckf = a.Ckf[i];
+            fused = fuse_step(a.Wk, a.pitch, a.w, a.h, a.fx, a.fy, a.cx, a.cy, a.RT, a.Rtt, a.tol,
+                              u, v, wkf, ckf);
+            if (fused) {
+                a.Wkf[i] = wkf;
+                a.Ckf[i] = ckf;
             }
         }
     }
-    if (a.count) {
-        const unsigned long long bal = __ballot(fused);
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        if (lane == 0) wave_counts[wave] = (unsigned int)__popcll(bal);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned int n = wave_counts[0] + wave_counts[1] + wave_counts[2] + wave_counts[3];
-            if (n) atomicAdd(a.count, (unsigned long long)n);
-        }
+    if (a.count) add_count(wave_counts, fused, a.count);
+}
+
+// Frames 0 .. n-1 in order, each keyframe pixel read and written once: the
+// same per-pixel steps as n launches of k_fuse.
+__global__ void __launch_bounds__(256) k_fuse_batch(FuseBatchArgs a)
+{
+    __shared__ unsigned int wave_counts[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < a.w * a.h;
+    int u = 0, v = 0;
+    float wkf = 0.0f, ckf = 0.0f;
+    if (in) {
+        v = i / a.w;
+        u = i - v * a.w;
+        wkf = a.Wkf[i];
+        ckf = a.Ckf[i];
+    }
+    bool any = false;
+    for (int f = 0; f < a.n; ++f) {
+        const FuseFrame& F = a.frames[f];
+        bool fused = false;
+        if (in && w_valid(wkf))
+            fused = fuse_step(F.Wk, a.pitch, a.w, a.h, a.fx, a.fy, a.cx, a.cy, F.RT, F.Rtt, a.tol, u,
+                              v, wkf, ckf);
+        any = any || fused;
+        if (a.count) add_count(wave_counts, fused, a.count + f);
+    }
+    if (any) {
+        a.Wkf[i] = wkf;
+        a.Ckf[i] = ckf;
     }
 }
 
@@ -81,6 +131,14 @@ hipError_t launch_fuse(hipStream_t s, const FuseArgs& a)
     const int n = a.w * a.h;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fuse, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse_batch(hipStream_t s, const FuseBatchArgs& a)
+{
+    const int n = a.w * a.h;
+    if (n <= 0 || a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fuse_batch, dim3((n + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

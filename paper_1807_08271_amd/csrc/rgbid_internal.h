@@ -151,6 +151,26 @@ struct FuseArgs {
     unsigned long long* count;
 };
 hipError_t launch_fuse(hipStream_t s, const FuseArgs& a);
+
+// A frame of a batched fusion (device-side table).
+struct FuseFrame {
+    const float* Wk;
+    float RT[9];
+    float Rtt[3];
+};
+constexpr int kMaxFuseBatch = 256;
+struct FuseBatchArgs {
+    float* Wkf;
+    float* Ckf;
+    const FuseFrame* frames;      // n entries in device memory
+    int n;
+    long long pitch;              // of every W_k
+    int w, h;
+    float fx, fy, cx, cy;
+    float tol;
+    unsigned long long* count;    // n counters, or NULL
+};
+hipError_t launch_fuse_batch(hipStream_t s, const FuseBatchArgs& a);
 hipError_t launch_fill(hipStream_t s, float* p, int n, float v);
 
 struct CovisArgs {

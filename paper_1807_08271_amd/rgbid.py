@@ -161,6 +161,7 @@ _SIGS = {
                                              C.c_double, C.POINTER(C.c_double)]),
     "rgbid_autotune": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
                                  C.POINTER(rgbid_align_params), C.c_int, C.POINTER(C.c_double)]),
+    "rgbid_fuse_batch": (C.c_int, [_P, _P, C.c_int, _P, C.c_size_t, _P, C.c_double, _P]),
     "rgbid_tune_save": (C.c_int, [_P, C.c_char_p]),
     "rgbid_tune_load": (C.c_int, [_P, C.c_char_p]),
     "rgbid_covisibility": (C.c_int, [_P, _P, _P, C.c_int, C.POINTER(rgbid_pose), C.c_double,
@@ -425,6 +426,28 @@ def rgbid_fuse(ctx, kf, Wk, T, tol: float, count: bool = True):
     _check(ctx, lib().rgbid_fuse(ctx, kf, pW, pitch, C.byref(pose), float(tol),
                                  C.byref(n) if count else None))
     return n.value if count else None
+
+
+def rgbid_fuse_batch(ctx, kf, Wks, Ts, tol: float, count: bool = False):
+    """Fuses the maps Wks (FP32 device tensors of one pitch) with poses Ts
+    ((R, t) each) in order in one launch; returns the per-frame counts when
+    count is set."""
+    n = len(Wks)
+    if n != len(Ts):
+        raise ValueError("one pose per map")
+    ptrs = (C.c_void_p * n)()
+    pitch = None
+    for i, w in enumerate(Wks):
+        p, pt = _img(w)
+        if pitch is not None and pt != pitch:
+            raise ValueError("all maps need the same row pitch")
+        pitch = pt
+        ptrs[i] = p.value
+    poses = (rgbid_pose * n)(*[make_pose(*T) for T in Ts])
+    cnt = (C.c_longlong * n)()
+    _check(ctx, lib().rgbid_fuse_batch(ctx, kf, n, ptrs, pitch or 0, poses, float(tol),
+                                       cnt if count else None))
+    return list(cnt) if count else None
 
 
 def rgbid_keyframe_read(ctx, kf, shape, device=None):

@@ -305,6 +305,36 @@ def test_argument_errors(ctx):
 # ----------------------------------------------------------------- fusion
 
 
+def test_fuse_batch_equals_sequential(ctx):
+    # One launch over 20 frames gives the maps of 20 single-frame calls bit for
+    # bit (the same per-pixel steps in the same order), and the same counts;
+    # a batch of one is one call.
+    rg = _rg()
+    import torch
+    cam, kf, frames, poses = synth.keyframe_sequence(20, seed=1, ss=2)
+    Ws = [torch.from_numpy(f.W).cuda() for f in frames]
+    K1 = rg.rgbid_keyframe_init(ctx, cam, torch.from_numpy(kf.W).cuda())
+    K2 = rg.rgbid_keyframe_init(ctx, cam, torch.from_numpy(kf.W).cuda())
+    n1 = [rg.rgbid_fuse(ctx, K1, w, T, 0.01) for w, T in zip(Ws, poses)]
+    n2 = rg.rgbid_fuse_batch(ctx, K2, Ws, poses, 0.01, count=True)
+    assert n1 == n2 and sum(n1) > 0
+    W1, C1 = rg.rgbid_keyframe_read(ctx, K1, (cam.h, cam.w))
+    W2, C2 = rg.rgbid_keyframe_read(ctx, K2, (cam.h, cam.w))
+    assert torch.equal(W1, W2) and torch.equal(C1, C2)
+    m1 = rg.rgbid_fuse(ctx, K1, Ws[3], poses[3], 0.01)
+    m2 = rg.rgbid_fuse_batch(ctx, K2, Ws[3:4], poses[3:4], 0.01, count=True)
+    assert [m1] == m2
+    W1, C1 = rg.rgbid_keyframe_read(ctx, K1, (cam.h, cam.w))
+    W2, C2 = rg.rgbid_keyframe_read(ctx, K2, (cam.h, cam.w))
+    assert torch.equal(W1, W2) and torch.equal(C1, C2)
+    with pytest.raises(rg.RgbidError):
+        rg.rgbid_fuse_batch(ctx, K2, [], [], 0.01)
+    with pytest.raises(rg.RgbidError):
+        rg.rgbid_fuse_batch(ctx, K2, Ws[:2], poses[:2], 0.0)
+    rg.rgbid_keyframe_free(K1)
+    rg.rgbid_keyframe_free(K2)
+
+
 def test_fuse_20_frames_matches_oracle(ctx):
     # Decisions are compared frame by frame (a pixel was fused iff its C grew);
     # W is compared on the pixels whose 20 decisions all agree.  A decision
