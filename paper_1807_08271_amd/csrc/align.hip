@@ -82,6 +82,24 @@ __device__ __forceinline__ float2 load_iw_at(const void* p, unsigned off)
     }
 }
 
+// Two consecutive (I, W) texels at byte offset off.
+template <bool F16>
+__device__ __forceinline__ void load_iw2_at(const void* p, unsigned off, float2& t0, float2& t1)
+{
+    const RGBID_GLOBAL char* b = (const RGBID_GLOBAL char*)p + off;
+    if constexpr (F16) {
+        typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+        const h4v h = *(const RGBID_GLOBAL h4v*)b;
+        t0 = make_float2((float)h.x, (float)h.y);
+        t1 = make_float2((float)h.z, (float)h.w);
+    } else {
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        const f4v f = *(const RGBID_GLOBAL f4v*)b;
+        t0 = make_float2(f.x, f.y);
+        t1 = make_float2(f.z, f.w);
+    }
+}
+
 // floor(x) as an integer (v_cvt_flr_i32_f32) for |x| < 2^31.
 __device__ __forceinline__ int floor_i(float x)
 {
@@ -283,14 +301,20 @@ __device__ __forceinline__ void warp_fetch(const Geom& G, const Ray3& a, float w
     // the image: the second tap is one texel on iff 0 <= x0 < w - 1
     const int xf = floor_i(ub), yf = floor_i(vb);
     const unsigned x0 = (unsigned)max(xf, 0), y0 = (unsigned)max(yf, 0);
-    const unsigned dx = (unsigned)xf < (unsigned)(G.w - 1) ? G.texb : 0u;
+    const bool dx = (unsigned)xf < (unsigned)(G.w - 1);
     const unsigned dy = (unsigned)yf < (unsigned)(G.h - 1) ? G.rowb : 0u;
     const unsigned o00 = __umul24(y0, G.rowb) + x0 * G.texb;
     const unsigned o01 = o00 + dy;
-    T.p00 = load_iw_at<F16>(G.Biw, o00);
-    T.p10 = load_iw_at<F16>(G.Biw, o00 + dx);
-    T.p01 = load_iw_at<F16>(G.Biw, o01);
-    T.p11 = load_iw_at<F16>(G.Biw, o01 + dx);
+    // both taps of a row in one load (the texel after the last of the plane
+    // is still inside the pyramid's allocation); a clamped second tap is the
+    // first one
+    float2 a0, a1, b0, b1;
+    load_iw2_at<F16>(G.Biw, o00, a0, a1);
+    load_iw2_at<F16>(G.Biw, o01, b0, b1);
+    T.p00 = a0;
+    T.p10 = dx ? a1 : a0;
+    T.p01 = b0;
+    T.p11 = dx ? b1 : b0;
 }
 
 __device__ __forceinline__ bool warp_finish(const Geom& G, const WarpTaps& T, float& Io, float& Wo)
