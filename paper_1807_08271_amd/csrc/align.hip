@@ -20,6 +20,7 @@
 // wavefront split the children, reduce them with cross-lane shuffles, and in
 // the end every lane owns one level-l pixel.
 #include "rgbid_internal.h"
+#include <type_traits>
 
 namespace rgbid {
 namespace {
@@ -949,48 +950,141 @@ __device__ __forceinline__ double nu_equation_const(double n, double nud)
                 log(0.5 * (nud + 1.0)));
 }
 
-// A sample entry that takes no part: +inf, whose weight is exactly 0 under
-// both rules (1/inf = 0), and whose residual is clamped to a finite value in
-// the sums (v_med3), so its terms are 0 * finite.
+// Entries of the sample that take no part (undefined residuals) are dropped
+// before the fixed point: the block compacts the n defined residuals through
+// LDS into F = n / 1024 full slots and a remainder of n mod 1024 entries in
+// the last slot (PER - 1), so the steps run without a per-entry validity
+// test.  Dead slots hold kNoSample.
 constexpr float kNoSample = __builtin_inff();
-constexpr float kResClamp = 3.0e38f;
+
+// Which slots of a thread hold sample entries after the compaction.
+struct LiveSlots {
+    int full;     // slots 0 .. full-1 (full < PER) are live in every thread (uniform)
+    bool tail;    // slot PER - 1 is live in this thread
+};
+
+// f(q) for the slots q = Q .. N-1 in order, up to the first q >= n (n
+// uniform); expanded at compile time, so that every slot stays in its
+// register and a dead slot costs one scalar branch.
+template <int Q, int N, class Fn>
+__device__ __forceinline__ void for_live(int n, Fn&& f)
+{
+    if constexpr (Q < N) {
+        if (Q >= n) return;
+        f(std::integral_constant<int, Q>{});
+        for_live<Q + 1, N>(n, f);
+    }
+}
+
+// Inclusive scan of an integer over the 64 lanes of a wave, in DPP steps:
+// row_shr 1, 2, 4, 8 inside every row of 16 lanes (zero fill), then the
+// totals of rows 0 and 2 into rows 1 and 3, then the total of rows 0-1
+// into rows 2-3.
+__device__ __forceinline__ int wave_scan_i(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+// Moves the defined entries of r (those below kNoSample) to the front of
+// the block's sample, in thread order and, inside a thread, slot order, then
+// reloads them: with F = n / 1024, entry j < 1024 F goes to thread j mod
+// 1024, slot j / 1024, and entry 1024 F + t to thread t, slot PER - 1.
+// cmp holds 1024 PER floats; wcnt 16 ints.  Returns the live slots.
+template <int PER>
+__device__ __forceinline__ LiveSlots compact_sample(float (&r)[PER], float* cmp, int* wcnt)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cnt += r[q] < kNoSample ? 1 : 0;
+    const int incl = wave_scan_i(cnt);
+    if (lane == 63) wcnt[wave] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int c = wcnt[w];
+        before += w < wave ? c : 0;
+        total += c;
+    }
+    int off = before + incl - cnt;
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (r[q] < kNoSample) cmp[off++] = r[q];
+    __syncthreads();
+    const int F = __builtin_amdgcn_readfirstlane(total / kScaleThreads);
+    const int t = (int)threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER - 1; ++q) r[q] = q < F ? cmp[t + q * kScaleThreads] : kNoSample;
+    LiveSlots ls;
+    ls.full = min(F, PER - 1);
+    ls.tail = F == PER || t < total % kScaleThreads;
+    r[PER - 1] = ls.tail ? cmp[t + ls.full * kScaleThreads] : kNoSample;
+    return ls;
+}
 
 // The location / scale fixed point with nu = 5 (Student-t) or the Huber
 // threshold k: every step sums w, w d and w d^2 (d = r - mu, weights from
 // the previous estimate) over the block and moves mu by S1/S0, sigma^2 to
-// (S2 - S1^2/S0)/n.  Sums in FP32 per lane (two partial sums in a fixed
-// order), FP64 across the block; mu is kept in FP64, S1/S0 and sigma are
-// formed in FP32 from the FP64 sums.  bcd / bcf broadcast mu and sigma.
+// (S2 - S1^2/S0)/n.  The per-entry terms are written so that a constant
+// factor of the weight is applied to the block totals instead:
+//   Huber      w = hk min(1/hk, 1/|d|), w d = clamp(d, -hk, hk),
+//              w d^2 = clamp(d, -hk, hk) d               (hk = k sigma)
+//   Student-t  w = 6 sigma^2 w' with w' = 1 / (d^2 + 5 sigma^2).
+// Sums in FP32 per lane (two partial sums in a fixed order), FP64 across
+// the block; mu is kept in FP64, S1/S0 and sigma are formed in FP32 from
+// the FP64 sums.  bcd / bcf broadcast mu and sigma.
 template <int KIND, int PER>
-__device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], float inv_n,
+__device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], LiveSlots ls, float inv_n,
                                                   float floor_s, float k, int iters, float* part,
                                                   double* bcd, float* bcf, double& mu,
                                                   float& sigma)
 {
     float fmu = (float)mu, sg = sigma;
     for (int it = 0; it < iters; ++it) {
-        // the weight of x = d / sigma written in d: Huber min(1, k sigma / |d|),
-        // Student-t (nu + 1) sigma^2 / (nu sigma^2 + d^2) with nu = 5
-        const float hk = k * sg, tA = 6.0f * sg * sg, tB = 5.0f * sg * sg;
+        const float hk = k * sg, ihk = 1.0f / hk, tB = 5.0f * sg * sg;
         float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const float d = r[q] - fmu;
-            float w;
-            if constexpr (KIND == RGBID_W_HUBER) w = fminf(1.0f, hk * rcp(fabsf(d)));
-            else w = tA * rcp(fmaf(d, d, tB));
-            const float dd = __builtin_amdgcn_fmed3f(d, -kResClamp, kResClamp);
-            s0[q & 1] += w;
-            s1[q & 1] = fmaf(w, dd, s1[q & 1]);
-            s2[q & 1] = fmaf(w * dd, dd, s2[q & 1]);
-        }
+        auto term = [&](float x, int h) {
+            const float d = x - fmu;
+            if constexpr (KIND == RGBID_W_HUBER) {
+                s0[h] += fminf(ihk, rcp(fabsf(d)));
+                const float c = __builtin_amdgcn_fmed3f(d, -hk, hk);
+                s1[h] += c;
+                s2[h] = fmaf(c, d, s2[h]);
+            } else {
+                const float w = rcp(fmaf(d, d, tB));
+                const float t = w * d;
+                s0[h] += w;
+                s1[h] += t;
+                s2[h] = fmaf(t, d, s2[h]);
+            }
+        };
+        for_live<0, PER - 1>(ls.full, [&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            term(r[q], q & 1);
+        });
+        if (ls.tail) term(r[PER - 1], (PER - 1) & 1);
         const float acc[3] = {s0[0] + s0[1], s1[0] + s1[1], s2[0] + s2[1]};
         double tot[3];
         block_totals<3>(acc, part, tot);
         if (threadIdx.x == kTotalsLane) {
+            double S0 = tot[0], S1 = tot[1], S2 = tot[2];
+            if constexpr (KIND == RGBID_W_HUBER) {
+                S0 *= (double)hk;
+            } else {
+                const double f = (double)(6.0f * sg * sg);
+                S0 *= f;
+                S1 *= f;
+                S2 *= f;
+            }
             // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
-            const float dm = (float)tot[1] / (float)tot[0];
-            const double ss = tot[2] - tot[1] * (double)dm;
+            const float dm = (float)S1 / (float)S0;
+            const double ss = S2 - S1 * (double)dm;
             const float var = fmaxf((float)ss * inv_n, 0.0f);
             bcd[0] = mu + (double)dm;
             bcf[0] = fmaxf(sqrtf(var), floor_s);
@@ -1009,13 +1103,15 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], float i
 // mu = 0, sigma^2 = mean r^2, with nu = 5 for Student-t; then (Student-t with
 // estimation) nu by bisection of the nu equation on [2, 10] with the
 // normalised residuals frozen: f(10) > 0 gives 10, f(2) < 0 gives 2, else 30
-// halvings of [2, 10] and the midpoint.  Thread t holds entries t + 1024 q,
+// halvings of [2, 10] and the midpoint.  Thread t loads entries t + 1024 q,
 // q < PER, of the sample (PER * 1024 at least the largest sample of the
-// launch); undefined residuals and entries past the sample are kNoSample.
+// launch); the defined ones are then compacted.
 template <int PER>
 __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
 {
+    __shared__ float cmp[kScaleThreads * PER];
     __shared__ float part[16 * 3];
+    __shared__ int wcnt[16];
     __shared__ double bcd[2];
     __shared__ float bcf[2];
     const int p = blockIdx.x, ch = blockIdx.y;
@@ -1054,19 +1150,20 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     float sigma = bcf[0];
     float nu = 5.0f;
     if (n > 0.0) {
+        const LiveSlots ls = compact_sample<PER>(r, cmp, wcnt);
         const float inv_n = (float)(1.0 / n);
         if (L.ip.weight == RGBID_W_HUBER)
-            scale_fixed_point<RGBID_W_HUBER, PER>(r, inv_n, floor_s, L.ip.huber_k,
+            scale_fixed_point<RGBID_W_HUBER, PER>(r, ls, inv_n, floor_s, L.ip.huber_k,
                                                   L.ip.scale_iters, part, bcd, bcf, mu, sigma);
         else
-            scale_fixed_point<RGBID_W_STUDENT_T, PER>(r, inv_n, floor_s, L.ip.huber_k,
+            scale_fixed_point<RGBID_W_STUDENT_T, PER>(r, ls, inv_n, floor_s, L.ip.huber_k,
                                                       L.ip.scale_iters, part, bcd, bcf, mu, sigma);
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
             const float fmu = (float)mu, isg = 1.0f / sigma;
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
                 const float x = (r[q] - fmu) * isg;
-                r[q] = x * x;     // r now holds x^2 (kNoSample stays +inf)
+                r[q] = x * x;     // r now holds x^2
             }
             // evaluations f(10), f(2), then up to 30 bisection steps; the
             // bracket lives in the totals lane, the next nu and the stop flag
@@ -1075,12 +1172,15 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
             for (int ev = 0;; ++ev) {
                 const float nf = (float)nud;
                 float e2[2] = {0.0f, 0.0f};
-#pragma unroll
-                for (int q = 0; q < PER; ++q) {
-                    // an entry without a residual takes w = 1, whose term 1 + ln 1 - 1 is 0
-                    const float w = r[q] < kNoSample ? (nf + 1.0f) / (nf + r[q]) : 1.0f;
-                    e2[q & 1] += 1.0f + logf(w) - w;
-                }
+                auto term = [&](float x2, int h) {
+                    const float w = (nf + 1.0f) / (nf + x2);
+                    e2[h] += 1.0f + logf(w) - w;
+                };
+                for_live<0, PER - 1>(ls.full, [&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    term(r[q], q & 1);
+                });
+                if (ls.tail) term(r[PER - 1], (PER - 1) & 1);
                 const float acc[1] = {e2[0] + e2[1]};
                 double tot[1];
                 block_totals<1>(acc, part, tot);
