@@ -528,6 +528,21 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             }
             key.append(reinterpret_cast<const char*>(&ip), sizeof ip);
             key.append(reinterpret_cast<const char*>(tune), sizeof(LevelTune) * L);
+            // everything else a captured launch holds: the sample length per
+            // thread and the table layout (both follow sample_max as well as
+            // the sizes) and the partials offset of every chain
+            snprintf(buf, sizeof buf, "|s%d|", P->sample_max);
+            key += buf;
+            for (int k = 0; k < nch; ++k) {
+                for (int l = 0; l < L; ++l) {
+                    const LevelTables& t = lt[k][l];
+                    snprintf(buf, sizeof buf, "%d,%zu,%zu,%zu,%d,%d;", scale_per[k][l], t.warp_off,
+                             t.red_off, t.begin_off, t.n_warp, t.n_red);
+                    key += buf;
+                }
+                snprintf(buf, sizeof buf, "p%zu|", poff[k]);
+                key += buf;
+            }
         }
         if ((st = ensure_chain_streams(c, nch)) != RGBID_OK) return st;
         auto it = c->graphs.find(key);

@@ -98,6 +98,60 @@ def test_normal_equations_c2_all_levels(ctx, c2_pairs, weight, warp):
     rg.rgbid_pyramid_free(B)
 
 
+# (crop, sample_max) giving level-0 samples of 4800, 8560, 12288, 19200 and
+# 22400 entries: every length the scale kernel is built for (5, 10, 15, 19
+# and 24 entries per thread), with a partly filled last slot after the
+# undefined residuals are dropped.
+_SAMPLE_CASES = [((480, 640), 5000), ((480, 640), 9000), ((480, 640), 15000),
+                 ((480, 640), 19200), ((420, 480), 24576)]
+
+
+@pytest.mark.parametrize("weight", ["huber", "student_t"])
+@pytest.mark.parametrize("case", range(len(_SAMPLE_CASES)))
+def test_scale_every_sample_length(ctx, c2_pairs, weight, case):
+    rg = _rg()
+    (h, w), smax = _SAMPLE_CASES[case]
+    p = c2_pairs[0]
+    crop = lambda a: np.ascontiguousarray(a[:h, :w])
+    IA, WA, IB, WB = crop(p.A.I), crop(p.A.W), crop(p.B.I), crop(p.B.W)
+    cam = (w, h) + p.cam.as_tuple()[2:]
+    A = rg.rgbid_pyramid(ctx, cam, 1, 0, *upload(IA, WA))
+    B = rg.rgbid_pyramid(ctx, cam, 1, 0, *upload(IB, WB))
+    th = oracle.log_so3(p.R) * 0.6
+    R, t = oracle.exp_so3(th), p.t * 0.6
+    g = rg.rgbid_normal_equations(ctx, A, B, 0, (R, t), _params(1, [1], weight, sample_max=smax))
+    r = oracle.normal_equations_at(cam, IA, WA, IB, WB, 0, R, t,
+                                   _oparams(1, [1], weight, sample_max=smax))
+    what = "%s %dx%d sample_max %d" % (weight, w, h, smax)
+    check_normal_equations(g, r, what=what)
+    assert g["sigma_I"] == pytest.approx(r["sigma_I"], rel=1e-4), what
+    assert g["sigma_W"] == pytest.approx(r["sigma_W"], rel=1e-4), what
+    if weight == "student_t":
+        assert g["nu_I"] == pytest.approx(r["nu_I"], abs=1e-3), what
+        assert g["nu_W"] == pytest.approx(r["nu_W"], abs=1e-3), what
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
+def test_graph_cache_follows_sample_max(ctx, c2_pairs):
+    # Same sizes and schedule, different sample_max, one context: every call
+    # must use launch tables and a scale kernel for its own sample length
+    # (a captured graph holds both).
+    rg = _rg()
+    p = c2_pairs[1]
+    A = _pyr(ctx, p.cam, 2, p.A)
+    B = _pyr(ctx, p.cam, 2, p.B)
+    R, t = oracle.exp_so3(oracle.log_so3(p.R) * 0.5), p.t * 0.5
+    for smax in (19200, 9000, 5000, 19200, 9000):
+        g = rg.rgbid_normal_equations(ctx, A, B, 0, (R, t), _params(2, [1, 1], sample_max=smax))
+        r = oracle.normal_equations_at(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, 0, R, t,
+                                       _oparams(2, [1, 1], sample_max=smax))
+        check_normal_equations(g, r, what="sample_max %d" % smax)
+        assert g["sigma_I"] == pytest.approx(r["sigma_I"], rel=1e-4)
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
 def test_normal_equations_identity_zero_gradient(ctx, c1_pairs):
     # B = A at the identity: residuals vanish, so g ~ 0 and the step is ~0.
     rg = _rg()
