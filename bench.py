@@ -490,6 +490,9 @@ def main():
                 "avg_launch_us": round(avg_us, 2), "hbm": hbm, "alu": alu}
     if traffic:
         hbm["measured_GBs"] = round(traffic / (avg_us * 1e-6) / 1e9, 1)
+    if ent and ent.get("trace_avg_us"):
+        # the same kernel's average duration in the committed rocprofv3 kernel trace
+        roofline["profile_avg_launch_us"] = ent["trace_avg_us"]
     if ent and ent.get("valu_insts_per_launch"):
         # executed VALU wave instructions against one per SIMD every 4 cycles
         alu["valu_issue_frac"] = round(ent["valu_insts_per_launch"] / (avg_us * 1e-6) /

@@ -4,6 +4,7 @@ and per-dispatch counters (--pmc passes), the HBM counters scaled by what
 the same counters read for a plain copy of known size.
 
     python -m paper_1807_08271_amd.profsum --stats kernel_stats.csv \\
+        [--trace kernel_trace.csv] \\
         --pmc pmc1.csv pmc2.csv ... --copy cpy1.csv cpy2.csv ... \\
         --copy-bytes 1073741824 --cmd "<profiled command>" --workload "<text>" \\
         --out profiles/<name>.md
@@ -43,9 +44,24 @@ def load_pmc(path, keep):
     return rows
 
 
+def load_trace(path):
+    """Durations (us) per (kernel name, grid size) from a --kernel-trace CSV."""
+    out = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if "Grid_Size" in r and r["Grid_Size"]:
+            grid = int(r["Grid_Size"])
+        else:
+            grid = (int(r.get("Grid_Size_X") or 1) * int(r.get("Grid_Size_Y") or 1) *
+                    int(r.get("Grid_Size_Z") or 1))
+        out[(r["Kernel_Name"], grid)].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
+    ap.add_argument("--trace", default=None, help="kernel_trace.csv of the same run")
     ap.add_argument("--pmc", nargs="*", default=[])
     ap.add_argument("--copy", nargs="*", default=[])
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
@@ -81,6 +97,18 @@ def main(argv=None):
             if k in avg:
                 gbs = b / (avg[k] * 1e-6) / 1e9
                 lines.append("| %s | %.0f | %.2f | %.1f | %.4f |" % (k, b, avg[k], gbs, gbs / 8000.0))
+    trace = {}
+    if a.trace:
+        lines += ["", "## Kernel trace per launch shape (`--kernel-trace`), library kernels", "",
+                  "| kernel | template args | grid | calls | average us |", "|---|---|---|---|---|"]
+        for (name, grid), d in sorted(load_trace(a.trace).items(),
+                                      key=lambda x: (kernel_key(x[0][0]) or ("",))[0:1] + (x[0][1],)):
+            kk = kernel_key(name)
+            if not kk or "rgbid" not in name:
+                continue
+            avg = sum(d) / len(d)
+            trace[(kk[0], kk[1], kk[2], grid)] = (avg, len(d))
+            lines.append("| k_%s | %s | %d | %d | %.2f |" % (kk[0], kk[2], grid, len(d), avg))
     # copy calibration: counters of the copy kernel against the known bytes
     cal = {}
     for path in a.copy:
@@ -125,6 +153,9 @@ def main(argv=None):
                 kernels[key] = {"grid": grid, "hbm_bytes_per_launch": round(hbm),
                                 "fetch_kib": round(f, 1), "write_kib": round(w, 1),
                                 "valu_insts_per_launch": round(valu), "template_args": targs}
+                if (k, lvl, targs, grid) in trace:
+                    kernels[key]["trace_avg_us"] = round(trace[(k, lvl, targs, grid)][0], 2)
+                    kernels[key]["trace_calls"] = trace[(k, lvl, targs, grid)][1]
     blob = {"source_sha": source_sha(), "fetch_factor": round(factors.get("FETCH_SIZE", 0), 4),
             "write_factor": round(factors.get("WRITE_SIZE", 0), 4), "kernels": kernels}
     lines += ["", "Machine-readable (read by bench.py; valid only while the kernel sources "
