@@ -867,19 +867,13 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
 
 // ------------------------------------------------------------------ k_scale
 
-// psi(x), x > 0: upward recurrence to x >= 12 then the Stirling-type series
-// psi(x) ~ ln x - 1/(2x) - sum_k B_2k / (2k x^2k) (Abramowitz & Stegun 6.3.18).
-__device__ double digamma_d(double x)
+// The asymptotic series of psi without its ln x term, -1/(2x) - sum_k B_2k /
+// (2k x^2k) (Abramowitz & Stegun 6.3.18), for x >= 12, from ix = 1/x.
+__device__ __forceinline__ double psi_tail(double ix)
 {
-    double r = 0.0;
-    while (x < 12.0) {
-        r -= 1.0 / x;
-        x += 1.0;
-    }
-    const double z = 1.0 / (x * x);
-    const double series =
-        z * (1.0 / 12 + z * (-1.0 / 120 + z * (1.0 / 252 + z * (-1.0 / 240 + z * (1.0 / 132)))));
-    return r + log(x) - 0.5 / x - series;
+    const double z = ix * ix;
+    return -0.5 * ix -
+           z * (1.0 / 12 + z * (-1.0 / 120 + z * (1.0 / 252 + z * (-1.0 / 240 + z * (1.0 / 132)))));
 }
 
 // Sum of v over the 64 lanes of a wave, left in lane 63, with DPP: a scan
@@ -941,13 +935,27 @@ __device__ __forceinline__ void block_totals(const float (&x)[NV], float* part, 
     }
 }
 
-// n f_c(nu) with f_c(nu) = -psi(nu/2) + ln(nu/2) + psi((nu+1)/2) - ln((nu+1)/2):
+// n f_c(nu), f_c(nu) = psi(b) - psi(a) - ln(b/a) with a = nu/2, b = a + 1/2:
 // the data-free part of the left side of the nu equation of sec. 6.3
-// (eq:robustnessValue); the data part is sum_i (1 + ln w_i - w_i).
-__device__ __forceinline__ double nu_equation_const(double n, double nud)
+// (eq:robustnessValue); the data part is sum_i (1 + ln w_i - w_i).  Both
+// digammas move up the same k steps (psi(x) = psi(x + 1) - 1/x) until
+// a + k >= 12, where the series holds; with 1/(a+j) - 1/(b+j) =
+// 1/(2 (a+j)(b+j)) and T the series without ln x,
+//   f_c = sum_{j<k} 1/(2 (a+j)(b+j)) + ln(a (b+k) / (b (a+k))) + T(b+k) - T(a+k),
+// the k terms summed as one fraction p/q: four divisions and one logarithm.
+__device__ double nu_equation_const(double n, double nud)
 {
-    return n * (-digamma_d(0.5 * nud) + log(0.5 * nud) + digamma_d(0.5 * (nud + 1.0)) -
-                log(0.5 * (nud + 1.0)));
+    const double a = 0.5 * nud, b = a + 0.5;
+    double p = 0.0, q = 1.0, x = a;
+    while (x < 12.0) {
+        const double d = 2.0 * x * (x + 0.5);
+        p = fma(p, d, q);
+        q *= d;
+        x += 1.0;
+    }
+    const double fc = p / q + log(a * (x + 0.5) / (b * x)) + psi_tail(1.0 / (x + 0.5)) -
+                      psi_tail(1.0 / x);
+    return n * fc;
 }
 
 // Entries of the sample that take no part (undefined residuals) are dropped
@@ -1170,11 +1178,18 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
             // reach every wave through LDS
             double lo = 2.0, hi = 10.0, nud = 10.0;
             for (int ev = 0;; ++ev) {
-                const float nf = (float)nud;
+                // the data-free part for this nu, formed in wave 0 (whose
+                // lane kTotalsLane needs it) while the other waves sum
+                double fcn = 0.0;
+                if (threadIdx.x < 64) fcn = nu_equation_const(n, nud);
+                const float nf = (float)nud, nf1 = nf + 1.0f;
                 float e2[2] = {0.0f, 0.0f};
+                // 1 + ln w - w with w = (nu + 1) / (nu + x^2) in (0, 1.5]: a
+                // hardware reciprocal and base-2 logarithm (1 ulp each; w is
+                // never denormal since x^2 is finite), ln w = ln 2 log2 w
                 auto term = [&](float x2, int h) {
-                    const float w = (nf + 1.0f) / (nf + x2);
-                    e2[h] += 1.0f + logf(w) - w;
+                    const float w = nf1 * rcp(nf + x2);
+                    e2[h] += fmaf(0.693147180559945f, __builtin_amdgcn_logf(w), 1.0f - w);
                 };
                 for_live<0, PER - 1>(ls.full, [&](auto qc) {
                     constexpr int q = decltype(qc)::value;
@@ -1185,7 +1200,7 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
                 double tot[1];
                 block_totals<1>(acc, part, tot);
                 if (threadIdx.x == kTotalsLane) {
-                    const double f = nu_equation_const(n, nud) + tot[0];
+                    const double f = fcn + tot[0];
                     double next = nud;
                     bool stop = false;
                     if (ev == 0) {
