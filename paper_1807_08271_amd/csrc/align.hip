@@ -362,8 +362,8 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 // Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
-// children at the warp level; each lane warps CPL = min(C, 4) of them (four
-// independent load chains per lane), LPP = C / CPL lanes share one pixel and
+// children at the warp level; each lane warps CPL of them (1, 4 or 8 by
+// level: independent load chains per lane), LPP = C / CPL lanes share one pixel and
 // combine their sums across lanes, and GPP = 64 / LPP pixels are warped per
 // pass.  Lane j of a group takes children c = j + LPP m (m < CPL), child c at
 // offset (c % B, c / B) from the pixel's first child; du(m), dv(m) are the
@@ -1055,7 +1055,7 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], LiveSlo
 {
     float fmu = (float)mu, sg = sigma;
     for (int it = 0; it < iters; ++it) {
-        const float hk = k * sg, ihk = 1.0f / hk, tB = 5.0f * sg * sg;
+        const float hk = k * sg, ihk = rcp(hk), tB = 5.0f * sg * sg;
         float s0[2] = {0.0f, 0.0f}, s1[2] = {0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
         auto term = [&](float x, int h) {
             const float d = x - fmu;
@@ -1091,11 +1091,11 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], LiveSlo
                 S2 *= f;
             }
             // mu' = mu + S1/S0; sum w (r - mu')^2 = S2 - S1^2 / S0
-            const float dm = (float)S1 / (float)S0;
+            const float dm = (float)S1 * rcp((float)S0);
             const double ss = S2 - S1 * (double)dm;
             const float var = fmaxf((float)ss * inv_n, 0.0f);
             bcd[0] = mu + (double)dm;
-            bcf[0] = fmaxf(sqrtf(var), floor_s);
+            bcf[0] = fmaxf(__builtin_amdgcn_sqrtf(var), floor_s);
         }
         __syncthreads();
         mu = bcd[0];
