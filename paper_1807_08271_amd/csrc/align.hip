@@ -1321,14 +1321,20 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         int tile = ch.first + wave;
         int idx = tile * 64 + lane, u, v;
         split_index(idx, gd.gw, gd.inv_gw, gd.half_inv, u, v);
-        RefPx r;
-        load_ref<F16>(A, R, gd.n, idx, u, v, r);
-        for (; tile < end; tile += waves) {
+        // two tiles per trip, the prefetch alternating between ra and rb, so
+        // the reference values are never copied from one to the other
+        RefPx ra, rb;
+        load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+        while (tile < end) {
             advance(idx, u, v, step, su, sv, gd.gw);
-            RefPx nxt;
-            load_ref<F16>(A, R, gd.n, idx, u, v, nxt);
-            own_pixel<F16>(G, R, r, gd.n, W, na, st, lane, cI, cW);
-            r = nxt;
+            load_ref<F16>(A, R, gd.n, idx, u, v, rb);
+            own_pixel<F16>(G, R, ra, gd.n, W, na, st, lane, cI, cW);
+            tile += waves;
+            if (tile >= end) break;
+            advance(idx, u, v, step, su, sv, gd.gw);
+            load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+            own_pixel<F16>(G, R, rb, gd.n, W, na, st, lane, cI, cW);
+            tile += waves;
         }
     } else {
         for (int tile = ch.first + wave; tile < end; tile += waves) {
