@@ -264,6 +264,27 @@ def test_align_is_deterministic(ctx, c2_pairs):
     rg.rgbid_pyramid_free(B)
 
 
+def test_bench_workload_sampled_against_oracle(ctx):
+    # The timed step's alignment as the bench runs it: 64 pairs of 640x480
+    # (room + boxes, 10% holes), 4 levels x 10 Huber iterations, FULLRES, FP32,
+    # autotuned launch shapes, the default launch chains, one batch.  Four
+    # pairs spread over the batch (so over both chains) against the oracle.
+    rg = _rg()
+    pairs = [synth.pair_c2(i, ss=2, device="cuda") for i in range(64)]
+    As = [_pyr(ctx, p.cam, 4, p.A) for p in pairs]
+    Bs = [_pyr(ctx, p.cam, 4, p.B) for p in pairs]
+    prm = _params(4, [10] * 4)
+    rg.rgbid_autotune(ctx, As, Bs, prm, reps=1)
+    got, stats = rg.rgbid_align_batch(ctx, As, Bs, prm)
+    for i in (0, 21, 42, 63):
+        p = pairs[i]
+        Ro, to, so = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(4, [10] * 4))
+        assert stats[i]["status"] == 0 and so["status"] == 0, i
+        assert rot_err(got[i][0], Ro) <= 1e-5 and np.linalg.norm(got[i][1] - to) <= 1e-5, i
+    for P in As + Bs:
+        rg.rgbid_pyramid_free(P)
+
+
 def test_align_batch_async_matches_sync(ctx, c2_pairs):
     # the asynchronous batch writes the same poses and statistics to device
     # memory, bit for bit, including a degenerate pair and two calls in a row
