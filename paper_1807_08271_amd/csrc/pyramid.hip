@@ -95,24 +95,52 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return x * q + min(x, r) + k;
 }
 
+// A thread flags four consecutive pixels of a row.  Every W the four flags
+// need (the row segment with one pixel on each side, and the segments of the
+// rows above and below, all at clamped in-image positions) is loaded before
+// any is tested, so a wave waits for one round of loads; one pixel per thread
+// with the neighbours loaded after the centre test took two.
 template <bool F16>
 __global__ void __launch_bounds__(256) k_mask(const PyrFrame* __restrict__ frames, int level)
 {
     const PyrFrame& f = frames[blockIdx.y];
     if (level >= f.levels) return;
     const int w = f.w[level], h = f.h[level];
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= w * h) return;
-    const int v = i / w, u = i - v * w;
+    const int qw = (w + 3) >> 2;   // quads per row
+    const int q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (q >= qw * h) return;
+    const int v = q / qw, u0 = (q - v * qw) * 4;
     const void* wp = f.wp[level];
-    unsigned char m = 0;
-    if (u >= 1 && v >= 1 && u <= w - 2 && v <= h - 2 && w_valid(load_wp<F16>(wp, i))) {
-        m = 1;
-        if (w_valid(load_wp<F16>(wp, i - 1)) && w_valid(load_wp<F16>(wp, i + 1)) &&
-            w_valid(load_wp<F16>(wp, i - w)) && w_valid(load_wp<F16>(wp, i + w)))
-            m = 3;
+    const int rc = v * w, ru = max(v - 1, 0) * w, rd = min(v + 1, h - 1) * w;
+    float c[6], up[4], dn[4];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[k] = load_wp<F16>(wp, rc + min(max(u0 - 1 + k, 0), w - 1));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int uk = min(u0 + k, w - 1);
+        up[k] = load_wp<F16>(wp, ru + uk);
+        dn[k] = load_wp<F16>(wp, rd + uk);
     }
-    static_cast<unsigned char*>(f.gm[level])[i] = m;
+    unsigned char m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int u = u0 + k;
+        m[k] = 0;
+        if (u >= 1 && v >= 1 && u <= w - 2 && v <= h - 2 && w_valid(c[k + 1])) {
+            m[k] = 1;
+            if (w_valid(c[k]) && w_valid(c[k + 2]) && w_valid(up[k]) && w_valid(dn[k])) m[k] = 3;
+        }
+    }
+    unsigned char* gm = static_cast<unsigned char*>(f.gm[level]) + rc + u0;
+    if ((w & 3) == 0) {
+        // the quad is whole and its first byte 4-aligned
+        *reinterpret_cast<unsigned*>(gm) =
+            m[0] | (unsigned)m[1] << 8 | (unsigned)m[2] << 16 | (unsigned)m[3] << 24;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (u0 + k < w) gm[k] = m[k];
+    }
 }
 
 template <bool F16>
@@ -145,7 +173,7 @@ hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes
         else hipLaunchKernelGGL(k_down<false>, grid, dim3(256), 0, s, frames_dev, l);
     }
     for (int l = 0; l < levels; ++l) {
-        const int n = max_w[l] * max_h[l];
+        const int n = ((max_w[l] + 3) / 4) * max_h[l];   // quads
         if (n <= 0) break;
         dim3 grid((n + 255) / 256, nframes);
         if (f16) hipLaunchKernelGGL(k_mask<true>, grid, dim3(256), 0, s, frames_dev, l);
