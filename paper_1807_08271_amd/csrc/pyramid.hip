@@ -49,6 +49,43 @@ __global__ void __launch_bounds__(256) k_level0(const PyrFrame* __restrict__ fra
     store_level<F16>(f.iw[0], f.wp[0], i, I, W);
 }
 
+// Level 0, four pixels of a row per thread (rows a multiple of 4 wide, the
+// caller's rows 16-byte aligned): 16-byte loads of I and W, 16-byte stores of
+// both planes; the values of k_level0.
+template <bool F16>
+__global__ void __launch_bounds__(256) k_level0_quad(const PyrFrame* __restrict__ frames)
+{
+    const PyrFrame& f = frames[blockIdx.y];
+    const int w = f.w[0], h = f.h[0], qw = w >> 2;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= qw * h) return;
+    const int v = q / qw, u0 = (q - v * qw) << 2;
+    const long long src = (long long)v * f.pitch + u0;
+    const float4 I = *reinterpret_cast<const float4*>(f.I + src);
+    float4 W = *reinterpret_cast<const float4*>(f.W + src);
+    W.x = w_valid(W.x) ? W.x : 0.0f;
+    W.y = w_valid(W.y) ? W.y : 0.0f;
+    W.z = w_valid(W.z) ? W.z : 0.0f;
+    W.w = w_valid(W.w) ? W.w : 0.0f;
+    const int i = v * w + u0;
+    if constexpr (F16) {
+        const __half2 h0 = __floats2half2_rn(I.x, W.x), h1 = __floats2half2_rn(I.y, W.y);
+        const __half2 h2 = __floats2half2_rn(I.z, W.z), h3 = __floats2half2_rn(I.w, W.w);
+        auto bits = [](__half2 x) { return *reinterpret_cast<const unsigned*>(&x); };
+        *reinterpret_cast<uint4*>(static_cast<__half2*>(f.iw[0]) + i) =
+            make_uint4(bits(h0), bits(h1), bits(h2), bits(h3));
+        // the W halves are the high halves of the (I, W) pairs
+        *reinterpret_cast<uint2*>(static_cast<__half*>(f.wp[0]) + i) =
+            make_uint2((bits(h0) >> 16) | (bits(h1) & 0xffff0000u),
+                       (bits(h2) >> 16) | (bits(h3) & 0xffff0000u));
+    } else {
+        float4* o = reinterpret_cast<float4*>(static_cast<float2*>(f.iw[0]) + i);
+        o[0] = make_float4(I.x, W.x, I.y, W.y);
+        o[1] = make_float4(I.z, W.z, I.w, W.w);
+        *reinterpret_cast<float4*>(static_cast<float*>(f.wp[0]) + i) = W;
+    }
+}
+
 template <bool F16>
 __global__ void __launch_bounds__(256) k_down(const PyrFrame* __restrict__ frames, int level)
 {
@@ -156,10 +193,15 @@ __global__ void __launch_bounds__(256) k_read(const void* __restrict__ iw, int n
 }  // namespace
 
 hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes, int levels,
-                          int f16, const int* max_w, const int* max_h)
+                          int f16, const int* max_w, const int* max_h, bool quad)
 {
     if (nframes <= 0) return hipSuccess;
-    {
+    if (quad) {
+        const int n = (max_w[0] / 4) * max_h[0];
+        dim3 grid((n + 255) / 256, nframes);
+        if (f16) hipLaunchKernelGGL(k_level0_quad<true>, grid, dim3(256), 0, s, frames_dev);
+        else hipLaunchKernelGGL(k_level0_quad<false>, grid, dim3(256), 0, s, frames_dev);
+    } else {
         const int n = max_w[0] * max_h[0];
         dim3 grid((n + 255) / 256, nframes);
         if (f16) hipLaunchKernelGGL(k_level0<true>, grid, dim3(256), 0, s, frames_dev);

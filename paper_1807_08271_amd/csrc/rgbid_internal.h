@@ -107,8 +107,10 @@ struct PyrFrame {
     int levels;
     int pad;
 };
+// quad: every frame is a multiple of 4 wide, its pitch a multiple of 4 and its
+// I and W 16-byte aligned (level 0 then moves four pixels per thread)
 hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes, int levels,
-                          int f16, const int* max_w, const int* max_h);
+                          int f16, const int* max_w, const int* max_h, bool quad);
 hipError_t launch_level_read(hipStream_t s, const void* iw, int n, int f16, float* I, float* W);
 
 // One Gauss-Newton iteration (or one linearisation without update) for all
