@@ -119,6 +119,28 @@ __device__ __forceinline__ float load_wp(const void* p, int i)
     else return static_cast<const float*>(p)[i];
 }
 
+// Four consecutive W values from element i (i a multiple of 4, the plane
+// 16-byte aligned).
+template <bool F16>
+__device__ __forceinline__ void load_wp4(const void* p, int i, float* o)
+{
+    if constexpr (F16) {
+        const uint2 b = *reinterpret_cast<const uint2*>(static_cast<const __half*>(p) + i);
+        const __half2 lo = *reinterpret_cast<const __half2*>(&b.x);
+        const __half2 hi = *reinterpret_cast<const __half2*>(&b.y);
+        o[0] = __low2float(lo);
+        o[1] = __high2float(lo);
+        o[2] = __low2float(hi);
+        o[3] = __high2float(hi);
+    } else {
+        const float4 f = *reinterpret_cast<const float4*>(static_cast<const float*>(p) + i);
+        o[0] = f.x;
+        o[1] = f.y;
+        o[2] = f.z;
+        o[3] = f.w;
+    }
+}
+
 // Validity flags of a level used by the residuals (sec. 6.2): bit 0 = the
 // pixel is interior (one pixel from every border) with a valid W, bit 1 =
 // bit 0 and the four W neighbours valid, i.e. the central-difference gradient
@@ -150,13 +172,21 @@ __global__ void __launch_bounds__(256) k_mask(const PyrFrame* __restrict__ frame
     const void* wp = f.wp[level];
     const int rc = v * w, ru = max(v - 1, 0) * w, rd = min(v + 1, h - 1) * w;
     float c[6], up[4], dn[4];
+    c[0] = load_wp<F16>(wp, rc + max(u0 - 1, 0));
+    c[5] = load_wp<F16>(wp, rc + min(u0 + 4, w - 1));
+    if ((w & 3) == 0) {
+        // whole, aligned quads: one 16-byte (8 with FP16) load per row
+        load_wp4<F16>(wp, rc + u0, c + 1);
+        load_wp4<F16>(wp, ru + u0, up);
+        load_wp4<F16>(wp, rd + u0, dn);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) c[k] = load_wp<F16>(wp, rc + min(max(u0 - 1 + k, 0), w - 1));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int uk = min(u0 + k, w - 1);
-        up[k] = load_wp<F16>(wp, ru + uk);
-        dn[k] = load_wp<F16>(wp, rd + uk);
+        for (int k = 0; k < 4; ++k) {
+            const int uk = min(u0 + k, w - 1);
+            c[k + 1] = load_wp<F16>(wp, rc + uk);
+            up[k] = load_wp<F16>(wp, ru + uk);
+            dn[k] = load_wp<F16>(wp, rd + uk);
+        }
     }
     unsigned char m[4];
 #pragma unroll
