@@ -463,8 +463,8 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         }
     }
     // the whole schedule of chain k on stream s
-    // part 0: everything; part 1: the first level start and the warp and
-    // scale kernels of the first iteration; part 2: the rest
+    // part 0: everything; part 1: the first level start and the warp kernel
+    // of the first iteration; part 2: the rest
     auto enqueue = [&](hipStream_t s, int k, int part) -> hipError_t {
         hipError_t e = hipSuccess;
         int ev_base = 0;
@@ -498,7 +498,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
             for (int it = 0; it < stp.iters; ++it) {
                 const hipEvent_t* ev = c->profiling ? &c->events[5 * (ev_base + it)] : nullptr;
                 il.kernels = 15;
-                if (first && it == 0) il.kernels = part == 1 ? 3 : part == 2 ? 12 : 15;
+                if (first && it == 0) il.kernels = part == 1 ? 1 : part == 2 ? 14 : 15;
                 else if (part == 1) break;
                 if ((e = launch_iteration(s, il, ev)) != hipSuccess) return e;
             }
@@ -548,7 +548,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             // with several chains, chain 0 is captured in two parts (graphs 0
-            // and nch) so the other chains can start half an iteration later
+            // and nch) so the other chains start one kernel later
             std::vector<hipGraphExec_t> execs;
             for (int gi = 0; gi < nch + (nch > 1 ? 1 : 0); ++gi) {
                 const int k = gi < nch ? gi : 0;
