@@ -69,6 +69,40 @@ def test_pyramid_matches_oracle(ctx, c2_pairs, storage):
     rg.rgbid_pyramid_free(pyr)
 
 
+def test_pyramid_row_pitch_and_alignment(ctx, c2_pairs):
+    # Level 0 moves four pixels per thread when the rows allow it (width and
+    # pitch multiples of 4, 16-byte aligned rows), one otherwise: a contiguous
+    # image, the same image inside wider rows, and inside rows whose start is
+    # 4 bytes off 16-byte alignment give identical pyramids (all planes: I and
+    # W read back, W_A and the flags through the normal equations).
+    rg = _rg()
+    import torch
+    p = c2_pairs[0]
+    I0, W0 = upload(p.A.I, p.A.W)
+    h, w = I0.shape
+    wide = lambda t, extra, off: torch.zeros((h, w + extra), device="cuda").copy_(
+        torch.nn.functional.pad(t, (off, extra - off)))[:, off:off + w]
+    views = [(I0, W0), (wide(I0, 8, 0), wide(W0, 8, 0)), (wide(I0, 5, 1), wide(W0, 5, 1))]
+    assert views[1][0].stride(0) == w + 8 and views[2][0].data_ptr() % 16 == 4
+    prm = _params(4, [1] * 4)
+    R, t = oracle.exp_so3(oracle.log_so3(p.R) * 0.5), p.t * 0.5
+    for storage in (0, 1):
+        pyrs = [rg.rgbid_pyramid(ctx, p.cam, 4, storage, I, W) for I, W in views]
+        Bs = _pyr(ctx, p.cam, 4, p.B, storage)
+        for level in range(4):
+            ref = rg.rgbid_pyramid_read(ctx, pyrs[0], level)
+            for P in pyrs[1:]:
+                got = rg.rgbid_pyramid_read(ctx, P, level)
+                assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (storage, level)
+        ne = [rg.rgbid_normal_equations(ctx, P, Bs, 0, (R, t), prm) for P in pyrs]
+        for g in ne[1:]:
+            np.testing.assert_array_equal(g["H"], ne[0]["H"])
+            np.testing.assert_array_equal(g["g"], ne[0]["g"])
+            assert g["n_valid_I"] == ne[0]["n_valid_I"] and g["n_valid_W"] == ne[0]["n_valid_W"]
+        for P in pyrs + [Bs]:
+            rg.rgbid_pyramid_free(P)
+
+
 # ----------------------------------------------------------------- normal equations
 
 
