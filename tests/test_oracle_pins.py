@@ -397,6 +397,45 @@ def test_nu_estimate():
     assert oracle.estimate_nu(rg, mg, sgg) == 10.0
 
 
+@pytest.mark.parametrize("df", [3.0, 4.0, 6.0])
+def test_nu_estimate_is_student_t_likelihood_argmax(df):
+    # The nu equation of sec. 6.3 is twice the derivative in nu of the
+    # Student-t log-likelihood with location and scale held at (mu, sigma).
+    # Its bisection root must therefore be the argmax over [2, 10] of the
+    # summed scipy.stats.t log-density, found here by bounded Brent search on
+    # that library function (no digamma, no oracle arithmetic).  A wrong
+    # factor on the data-free digamma/log term, or on the per-sample term,
+    # moves the root by far more than 1e-6.
+    from scipy.optimize import minimize_scalar
+    from scipy.stats import t as student_t
+    rng = np.random.default_rng(int(df * 10))
+    r = 0.7 + 2.5 * rng.standard_t(df, size=20000)
+    mu, sg = oracle.scale(r, kind="student_t", nu=5.0, iters=50, floor=1e-9)
+    nu = oracle.estimate_nu(r, mu, sg)
+    nll = lambda v: -float(np.sum(student_t.logpdf(r, df=v, loc=mu, scale=sg)))
+    best = minimize_scalar(nll, bounds=(2.0, 10.0), method="bounded",
+                           options={"xatol": 1e-10, "maxiter": 500})
+    assert 2.0 < best.x < 10.0
+    assert nu == pytest.approx(best.x, abs=1e-6)
+
+
+def test_nu_estimate_clamps_where_likelihood_is_monotone():
+    # Gaussian residuals: the likelihood still rises at nu = 10, so nu = 10;
+    # very heavy tails (t with 1.2 degrees of freedom): it already falls at
+    # nu = 2, so nu = 2.  Checked on the scipy log-density, not the oracle.
+    from scipy.stats import t as student_t
+    rng = np.random.default_rng(5)
+    for r, want in ((rng.normal(size=20000), 10.0), (rng.standard_t(1.2, size=20000), 2.0)):
+        mu, sg = oracle.scale(r, kind="student_t", nu=5.0, iters=50, floor=1e-9)
+        ll = lambda v: float(np.sum(student_t.logpdf(r, df=v, loc=mu, scale=sg)))
+        grid = [ll(v) for v in np.linspace(2.0, 10.0, 17)]
+        if want == 10.0:
+            assert all(b > a for a, b in zip(grid, grid[1:]))
+        else:
+            assert all(b < a for a, b in zip(grid, grid[1:]))
+        assert oracle.estimate_nu(r, mu, sg) == want
+
+
 def test_sample_strides():
     # N = 19200 gives integer strides over the 640x480 pyramid (sec. 6.3).
     assert [oracle.sample_stride(640 >> l, 480 >> l) for l in range(4)] == [4, 2, 1, 1]
@@ -608,6 +647,144 @@ def test_covisibility_occluder_and_holes():
     nH, nV = oracle.covisibility(cam, WA, WB, np.eye(3), np.zeros(3), 0.01)
     assert nH == (h - 5) * w
     assert nV == (h - 5) * 30           # columns 30.. see the occluder
+
+
+# A plane n.X = d seen from the keyframe / reference camera, and a second
+# camera with pose (R, t) in it (X_ref = R X_2 + t).  Inverse depth is linear
+# in the pixel coordinates in both views, so bilinear sampling is exact and
+# the geometry is consistent: every transferred pixel meets the other view's
+# surface.  The transfer below is written independently of the oracle with
+# explicit matrix products.
+_ROT_CAM = (64, 48, 60.0, 60.0, 31.5, 23.5)
+_ROT_N = np.array([0.12, -0.08, 1.0]) / np.linalg.norm([0.12, -0.08, 1.0])
+_ROT_D = 2.0
+_ROT_R = Rotation.from_rotvec(np.deg2rad(4.0) * np.array([0.3, 0.8, 0.5]) /
+                              np.linalg.norm([0.3, 0.8, 0.5])).as_matrix()
+_ROT_T = np.array([0.06, -0.035, 0.045])
+
+
+def _second_view_plane(cam, n, d, R, t):
+    """Inverse depth of the plane in the second camera: (R^T n).X_2 = d - n.t."""
+    return plane_field(cam, R.T @ n, d - n @ t)
+
+
+def _transfer(cam, W, R, t):
+    """Pixel positions and 1/Y_z of every pixel of W in the second camera:
+    Y = R^T (K^-1 p / W - t)."""
+    w, h, fx, fy, cx, cy = cam
+    v, u = np.mgrid[0:h, 0:w].astype(np.float64)
+    ray = np.stack([(u - cx) / fx, (v - cy) / fy, np.ones_like(u)], axis=-1)
+    X = ray / W[..., None] - t
+    Y = X @ R            # row vector times R = (R^T X^T)^T
+    Rray = ray @ R
+    ub = fx * Y[..., 0] / Y[..., 2] + cx
+    vb = fy * Y[..., 1] / Y[..., 2] + cy
+    return ub, vb, Y[..., 2], Rray[..., 2]
+
+
+def _inside(cam, ub, vb):
+    w, h = cam[:2]
+    ins = (ub >= -0.5) & (ub < w - 0.5) & (vb >= -0.5) & (vb < h - 0.5)
+    # no transfer within rounding of the bounds, so the count is well posed
+    edge = np.minimum.reduce([np.abs(ub + 0.5), np.abs(ub - (w - 0.5)),
+                              np.abs(vb + 0.5), np.abs(vb - (h - 0.5))])
+    assert edge.min() > 1e-6
+    return ins
+
+
+def _plane_sample(cam, n, d, ub, vb):
+    """Bilinear sample of a linear inverse-depth field with the taps clamped
+    to the image: inside [0, w-1] x [0, h-1] it is the field itself; in the
+    outer half-pixel band both taps of an axis are the edge pixel, so the
+    field is taken at the clamped coordinate."""
+    w, h, fx, fy, cx, cy = cam
+    uc, vc = np.clip(ub, 0.0, w - 1.0), np.clip(vb, 0.0, h - 1.0)
+    return (n[0] * (uc - cx) / fx + n[1] * (vc - cy) / fy + n[2]) / d
+
+
+def _fuse_expected(cam, Wkf, Ckf, R, t, tol):
+    """One fusion step of a consistent plane frame, in closed form: the
+    covisibility decision |w_b - 1/Y_z| < tol, W* = (R^T x)_z w_b /
+    (1 + w_b (R^T t)_z), C_k = ((1 + w_b (R^T t)_z)^2 / (R^T x)_z)^2 and the
+    weighted mean."""
+    ub, vb, Yz, Rz = _transfer(cam, Wkf, R, t)
+    ins = _inside(cam, ub, vb) & (Yz > 0)
+    wb = _plane_sample(cam, R.T @ _ROT_N, _ROT_D - _ROT_N @ t, ub, vb)
+    gap = np.abs(wb - 1.0 / Yz)
+    assert np.all(np.abs(gap[ins] - tol) > 1e-9)
+    fused = ins & (gap < tol)
+    den = 1.0 + wb * (R.T @ t)[2]
+    Ws = Rz * wb / den
+    Ck = (den * den / Rz) ** 2
+    Wn = np.where(fused, (Wkf * Ckf + Ck * Ws) / (Ckf + Ck), Wkf)
+    Cn = np.where(fused, Ckf + Ck, Ckf)
+    interior = fused & (ub >= 0) & (ub <= cam[0] - 1) & (vb >= 0) & (vb <= cam[1] - 1)
+    return Wn, Cn, fused, interior, Rz, Yz
+
+
+def test_fuse_rotated_consistent_plane_closed_form():
+    # R != I.  Where the transfer lands between pixel centres the bilinear
+    # sample is exact, the geometry is consistent, and the warped inverse depth
+    # equals the keyframe's own (W* = W_kf): W stays as it was and C grows by
+    # C_k = ((R^T x)_z / (W_kf Y_z)^2)^2 (the weight of sec. 7.2 with
+    # 1 + w_b (R^T t)_z = (R^T x)_z / (W_kf Y_z)).  In the outer half-pixel band
+    # the clamped taps give the field at the clamped coordinate; that is
+    # closed form too.  Fails with a transposed rotation in the transfer, in
+    # (R^T x)_z or in R^T t.
+    cam, tol = _ROT_CAM, 1e-3
+    Wkf = plane_field(cam, _ROT_N, _ROT_D)
+    Wk = _second_view_plane(cam, _ROT_N, _ROT_D, _ROT_R, _ROT_T)
+    assert Wkf.min() > 0 and Wk.min() > 0
+    Wn, Cn, fused, interior, Rz, Yz = _fuse_expected(cam, Wkf, np.ones_like(Wkf), _ROT_R,
+                                                     _ROT_T, tol)
+    assert 0.5 * fused.size < interior.sum() < fused.sum() < fused.size
+    W2, C2, n = oracle.fuse(cam, Wkf, np.ones_like(Wkf), Wk, _ROT_R, _ROT_T, tol=tol)
+    assert n == fused.sum()
+    np.testing.assert_allclose(W2[interior], Wkf[interior], rtol=1e-13)
+    np.testing.assert_allclose(C2[interior], 1.0 + (Rz / (Wkf * Yz) ** 2)[interior] ** 2,
+                               rtol=1e-12)
+    np.testing.assert_allclose(W2, Wn, rtol=1e-12)
+    np.testing.assert_allclose(C2, Cn, rtol=1e-12)
+    assert np.all(C2[~fused] == 1.0)
+    # a second, different frame of the same plane on the fused map
+    R2 = Rotation.from_rotvec([-0.03, 0.02, 0.05]).as_matrix()
+    t2 = np.array([-0.04, 0.05, -0.02])
+    Wk2 = _second_view_plane(cam, _ROT_N, _ROT_D, R2, t2)
+    Wn2, Cn2, fused2, interior2, _, _ = _fuse_expected(cam, W2, C2, R2, t2, tol)
+    W3, C3, n2 = oracle.fuse(cam, W2, C2, Wk2, R2, t2, tol=tol)
+    assert n2 == fused2.sum() and interior2.sum() > 0.5 * fused2.size
+    np.testing.assert_allclose(W3, Wn2, rtol=1e-12)
+    np.testing.assert_allclose(C3, Cn2, rtol=1e-12)
+
+
+def test_covisibility_rotated_plane_closed_form():
+    # R != I on a consistent plane: a pixel is visible iff its transfer lands
+    # inside the other image with the sampled inverse depth within tol of
+    # 1/Y_z, which holds everywhere except possibly in the outer half-pixel
+    # band (clamped taps).  Counted in each direction (B -> A with the inverse
+    # pose).  A transposed rotation lands elsewhere and leaves the plane,
+    # which fails these counts.
+    cam, tol = _ROT_CAM, 1e-3
+    WA = plane_field(cam, _ROT_N, _ROT_D)
+    WB = _second_view_plane(cam, _ROT_N, _ROT_D, _ROT_R, _ROT_T)
+
+    def visible(W, n, d, R, t):
+        ub, vb, Yz, _ = _transfer(cam, W, R, t)
+        ins = _inside(cam, ub, vb) & (Yz > 0)
+        gap = np.abs(_plane_sample(cam, R.T @ n, d - n @ t, ub, vb) - 1.0 / Yz)
+        assert np.all(np.abs(gap[ins] - tol) > 1e-9)
+        return int((ins & (gap < tol)).sum())
+
+    want_ab = visible(WA, _ROT_N, _ROT_D, _ROT_R, _ROT_T)
+    # B's plane is (R^T n).X_B = d - n.t; A in B is (R^T, -R^T t)
+    nB, dB = _ROT_R.T @ _ROT_N, _ROT_D - _ROT_N @ _ROT_T
+    want_ba = visible(WB, nB, dB, _ROT_R.T, -_ROT_R.T @ _ROT_T)
+    n = cam[0] * cam[1]
+    assert 0.5 * n < want_ab < n and 0.5 * n < want_ba < n
+    assert oracle.covisibility(cam, WA, WB, _ROT_R, _ROT_T, tol) == (n, want_ab)
+    r, counts = oracle.covisibility_ratio(cam, WA, WB, _ROT_R, _ROT_T, tol)
+    assert counts == (n, want_ab, n, want_ba)
+    assert r == min(want_ab, want_ba) / n
 
 
 # ----------------------------------------------------------------- covariance
