@@ -138,9 +138,16 @@ def make_inputs(npairs, device, mixed=False):
 
 
 def cpu_baseline(pairs, fusion, oparams, budget_s):
-    """The FP64 oracle on a bounded sample: whole alignments of the first
-    pairs until budget_s is spent (at least one), plus one 20-frame fusion.
-    Scaled to the step: P alignments + one fusion."""
+    """The FP64 oracle on a bounded sample of the step, two ways:
+    one core: whole alignments of the first pairs until budget_s is spent
+    (at least one), plus one 20-frame fusion, scaled to the step (P
+    alignments + one fusion);
+    all cores: one pair per worker thread (the oracle's C call runs without
+    the interpreter lock), four pairs per thread over the usable host cores
+    (at most 16, this machine class's CPU share per GPU), timed on the wall
+    clock; the step's fusion runs on one thread, as the oracle's fusion is
+    one call per frame.  value is the all-core figure."""
+    import concurrent.futures as cf
     import numpy as np
     import oracle
     oracle.build(force=False)
@@ -161,11 +168,30 @@ def cpu_baseline(pairs, fusion, oparams, budget_s):
     t_fu = time.perf_counter() - t0
     per_align = t_al / n
     P = len(pairs)
-    value = P / (P * per_align + t_fu)
-    return {"value": round(value, 3), "unit": "alignments/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of the %d step pairs aligned by the FP64 C oracle (%.2f s each, one "
-                      "thread) + one 20-frame fusion (%.2f s), scaled to one step" % (
-                          n, P, per_align, t_fu)}
+    one = P / (P * per_align + t_fu)
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    threads = max(1, min(16, usable))
+    jobs = [pairs[i % P] for i in range(4 * threads)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda p: oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, oparams), jobs))
+    t_all = time.perf_counter() - t0
+    rate = len(jobs) / t_all
+    value = P / (P / rate + t_fu)
+    log("oracle: one core %.3f alignments/s; %d threads %.3f alignments/s (%d pairs in %.1f s)" % (
+        one, threads, value, len(jobs), t_all))
+    return {"value": round(value, 3), "unit": "alignments/s", "cores": threads, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "usable_cpus": usable,
+            "one_core": {"value": round(one, 3), "cores": 1,
+                         "s_per_alignment": round(per_align, 3)},
+            "sample": "all cores: %d step pairs aligned by the FP64 C oracle, one pair per "
+                      "thread on %d threads, %.1f s wall (%.2f alignments/s), plus one 20-frame "
+                      "fusion on one thread (%.2f s), scaled to one step; one core: %d pairs at "
+                      "%.2f s each + the fusion" % (len(jobs), threads, t_all, rate, t_fu, n,
+                                                    per_align)}
 
 
 def warmstart_compare(ctx, npairs, steps):
@@ -209,6 +235,99 @@ def warmstart_compare(ctx, npairs, steps):
     res["workload"] = ("%d held-out 640x480 pairs, motion <= 10 deg / 15 cm, 4 levels x <= 10 "
                        "iterations, early stop 1e-6" % m)
     return res
+
+
+def batched_c4(ctx, steps, warmup, storage_name="f32"):
+    """The batched form at its own shapes: 24 x 320x240 + 32 x 640x480 +
+    8 x 1280x960 pairs (room + boxes, 10% holes; about 21.5 M level-0 pixels,
+    a working set of ~400 MB in FP32, above the 256 MB Infinity Cache) aligned
+    in one batch, 4 levels x 10 Huber iterations, FULLRES, autotuned launch
+    shapes.  A step rebuilds the 128 pyramids and aligns the batch
+    (asynchronous form).  Reports alignments/s and, per level, the
+    warp-reduce kernels' algorithmic bytes over their HIP-event-timed launch
+    durations against 8 TB/s."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1807_08271_amd import rgbid as rg
+    t0 = time.time()
+    pairs = synth.batch_c4(ss=2, device="cuda")
+    log("c4: generated %d mixed-size pairs in %.1fs" % (len(pairs), time.time() - t0))
+    f16 = storage_name == "f16"
+    storage = rg.RGBID_F16 if f16 else rg.RGBID_F32
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    imgs = [(up(p.A.I), up(p.A.W), up(p.B.I), up(p.B.W)) for p in pairs]
+    As = [rg.rgbid_pyramid(ctx, p.cam, 4, storage, x[0], x[1]) for p, x in zip(pairs, imgs)]
+    Bs = [rg.rgbid_pyramid(ctx, p.cam, 4, storage, x[2], x[3]) for p, x in zip(pairs, imgs)]
+    all_pyr = As + Bs
+    all_I = [x[0] for x in imgs] + [x[2] for x in imgs]
+    all_W = [x[1] for x in imgs] + [x[3] for x in imgs]
+    sizes = [(p.cam.w, p.cam.h) for p in pairs]
+    n = len(pairs)
+    prm = rg.rgbid_default_params(levels=4, iters=[10] * 4, weight=rg.RGBID_W_HUBER)
+    t0 = time.time()
+    tuned = [round(1e3 * b, 2) for b in rg.rgbid_autotune(ctx, As, Bs, prm, reps=3)]
+    log("c4: autotuned in %.1fs: us/iteration per level %s" % (time.time() - t0, tuned))
+    tune_txt = os.path.join("/tmp", "rgbid_bench_c4_tune_%d.txt" % os.getpid())
+    rg.rgbid_tune_save(ctx, tune_txt)
+    key = "_".join("%dx%dx%d" % (w, h, sizes.count((w, h))) for w, h in dict.fromkeys(sizes))
+    fused_level = {}
+    for line in open(tune_txt):
+        f = line.split()
+        if len(f) == 6 and f[0].split("_", 1)[1] == "m0_f%d_%s" % (int(f16), key):
+            fused_level[int(f[0].split("_")[0][1:])] = f[1] == "1"
+    os.remove(tune_txt)
+    pose_buf = torch.empty(n * rg.POSE_BYTES, dtype=torch.uint8, device="cuda")
+
+    def step():
+        rg.rgbid_pyramid_update_batch(ctx, all_pyr, all_I, all_W)
+        rg.rgbid_align_batch_async(ctx, As, Bs, prm, pose_buf)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    poses = rg.unpack_poses(pose_buf, n)
+    import oracle
+    err = max(float(np.linalg.norm(oracle.log_so3(R.T @ p.R))) for (R, _), p in zip(poses, pairs))
+    log("c4: %d steps, %.3f ms/step, %.1f alignments/s" % (steps, 1e3 * dt / steps, n * steps / dt))
+    rg.rgbid_set_profiling(ctx, True)
+    for _ in range(max(2, steps // 4)):
+        rg.rgbid_align_batch(ctx, As, Bs, prm)
+    torch.cuda.synchronize()
+    kt = rg.rgbid_kernel_times(ctx)
+    rg.rgbid_set_profiling(ctx, False)
+    levels = {}
+    for (lvl, kname), (ms, nl) in sorted(kt.items()):
+        if kname not in ("warp", "reduce"):
+            continue
+        fused = fused_level.get(lvl, lvl == 0)
+        b = algorithmic_bytes(lvl, kname, sizes, f16, True, fused)
+        us = 1e3 * ms / nl
+        e = levels.setdefault("level%d" % lvl, {"fused_warp_reduce": fused})
+        e["%s_avg_us" % kname] = round(us, 2)
+        if b is not None:
+            e["%s_bytes" % kname] = b
+            e["%s_GBs" % kname] = round(b / (us * 1e-6) / 1e9, 1)
+            e["%s_hbm_frac" % kname] = round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    for lvl, e in levels.items():
+        b = e.get("warp_bytes", 0) + e.get("reduce_bytes", 0)
+        us = (e.get("warp_avg_us", 0.0) if "warp_bytes" in e else 0.0) + e.get("reduce_avg_us", 0.0)
+        e["warp_reduce_hbm_frac"] = round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        log("c4 %s: %s" % (lvl, e))
+    for P in all_pyr:
+        rg.rgbid_pyramid_free(P)
+    return {"workload": "24 x 320x240 + 32 x 640x480 + 8 x 1280x960 pairs (room+boxes, 10%% "
+                        "holes), 4-level FULLRES warp, 10 Huber GN iterations per level, %s; "
+                        "step = 128 pyramids + the batched alignment" % storage_name,
+            "alignments_per_s": round(n * steps / dt, 1), "ms_per_step": round(1e3 * dt / steps, 4),
+            "steps": steps, "level0_pixels": int(sum(w * h for w, h in sizes)),
+            "autotuned_us_per_iteration": tuned, "max_rot_err_vs_truth_rad": err,
+            "levels": levels}
 
 
 # Synthetic Kinect-like calibration for the sensor input path (Brown
@@ -308,6 +427,9 @@ def main():
                     help="uniform: --pairs pairs at 640x480 (the headline workload); mixed: "
                          "24 x 320x240 + 32 x 640x480 + 8 x 1280x960 pairs (batched form)")
     ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the batched mixed-size block (24 x 320x240 + 32 x 640x480 + "
+                         "8 x 1280x960 pairs, per-level warp-reduce HBM fractions)")
     ap.add_argument("--no-frontend", action="store_true",
                     help="skip the per-call timings of covariance, covisibility, tracker, sensor path")
     ap.add_argument("--frontend-only", action="store_true",
@@ -527,6 +649,8 @@ def main():
         "accuracy": {"max_rot_err_vs_truth_rad": float(max(errs)),
                      "max_trans_err_vs_truth_m": float(max(terrs)), "degenerate_pairs": bad},
     }
+    if not args.no_c4 and not mixed:
+        out["batched_c4"] = batched_c4(ctx, max(5, args.steps // 2), 2, args.storage)
     if not args.no_warmstart:
         out["warmstart"] = warmstart_compare(ctx, args.ws_pairs, args.steps)
     if not args.no_frontend:

@@ -206,6 +206,17 @@ void pose_floats(const double R[9], const double t[3], float RT[9], float Rtt[3]
     }
 }
 
+// The pose for the displacement form of a transfer: D = R^T - I, formed in
+// FP64 before rounding (its entries are small for small motions and keep
+// their relative precision), and R^T t.
+void pose_flow_floats(const double R[9], const double t[3], float D[9], float Rtt[3])
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) D[3 * i + j] = (float)(R[3 * j + i] - (i == j ? 1.0 : 0.0));
+        Rtt[i] = (float)(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
+    }
+}
+
 bool params_ok(const rgbid_align_params* p, std::string& why)
 {
     if (!p) { why = "params is NULL"; return false; }
@@ -247,6 +258,11 @@ std::string tune_key(int n, const rgbid_pyr* const* A, int level, int warp, int 
 
 void clear_graphs(rgbid_ctx* c)
 {
+    // an asynchronous call may still run a graph: let every stream drain first
+    if (!c->graphs.empty()) {
+        (void)hipStreamSynchronize(c->stream);
+        for (hipStream_t s : c->chain_streams) (void)hipStreamSynchronize(s);
+    }
     for (auto& kv : c->graphs)
         for (hipGraphExec_t g : kv.second) (void)hipGraphExecDestroy(g);
     c->graphs.clear();
@@ -445,7 +461,9 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     if ((st = stage_end(c)) != RGBID_OK) return st;
 
     // ---- enqueue (directly or through a cached graph)
+    // zeroed first: the struct's padding bytes are part of the graph-cache key
     IterParams ip;
+    std::memset(&ip, 0, sizeof ip);
     ip.weight = P->weight;
     ip.huber_k = (float)P->huber_k;
     ip.estimate_nu = P->estimate_nu;
@@ -1126,7 +1144,7 @@ rgbid_status rgbid_fuse(rgbid_ctx* c, rgbid_kf* kf, const float* Wk_dev, size_t 
     a.fy = (float)kf->cam.fy;
     a.cx = (float)kf->cam.cx;
     a.cy = (float)kf->cam.cy;
-    pose_floats(T->R, T->t, a.RT, a.Rtt);
+    pose_flow_floats(T->R, T->t, a.D, a.Rtt);
     a.tol = (float)tol;
     a.count = n_fused ? kf->count : nullptr;
     if (n_fused) HIPCHK(c, hipMemsetAsync(kf->count, 0, sizeof(unsigned long long), c->stream));
@@ -1165,7 +1183,7 @@ rgbid_status rgbid_fuse_batch(rgbid_ctx* c, rgbid_kf* kf, int n, const float* co
     FuseFrame* fr = reinterpret_cast<FuseFrame*>(stage);
     for (int i = 0; i < n; ++i) {
         fr[i].Wk = Wk_dev[i];
-        pose_floats(T[i].R, T[i].t, fr[i].RT, fr[i].Rtt);
+        pose_flow_floats(T[i].R, T[i].t, fr[i].D, fr[i].Rtt);
     }
     HIPCHK(c, hipMemcpyAsync(c->fuse.p, stage, (size_t)n * sizeof(FuseFrame), hipMemcpyHostToDevice,
                              c->stream));
@@ -1240,8 +1258,8 @@ rgbid_status rgbid_covisibility(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_py
         a.fy = (float)A->fy[level];
         a.cx = (float)A->cx[level];
         a.cy = (float)A->cy[level];
-        if (dir == 0) pose_floats(T->R, T->t, a.RT, a.Rtt);
-        else pose_floats(Ri, ti, a.RT, a.Rtt);
+        if (dir == 0) pose_flow_floats(T->R, T->t, a.D, a.Rtt);
+        else pose_flow_floats(Ri, ti, a.D, a.Rtt);
         a.tol = (float)tol;
         a.count = cnt + 2 * dir;
         HIPCHK(c, launch_covis(c->stream, a));

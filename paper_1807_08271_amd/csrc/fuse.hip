@@ -10,46 +10,75 @@ namespace {
 
 __device__ __forceinline__ bool w_valid(float w) { return w > 0.0f && w < INFINITY; }
 
-// One frame's fusion step at keyframe pixel (u, v) (sec. 7.2): the pixel
-// with fused inverse depth wkf (valid) is transferred into frame k with the
-// pose (RT = R^T, Rtt = R^T t), W_k is sampled bilinearly, and if it passes
-// the covisibility test the warped inverse depth is merged into (wkf, ckf).
-// Returns whether the pixel fused.
-__device__ __forceinline__ bool fuse_step(const float* __restrict__ Wk, long long pitch, int w,
-                                          int h, float fx, float fy, float cx, float cy,
-                                          const float* RT, const float* Rtt, float tol, int u,
-                                          int v, float& wkf, float& ckf)
+// Transfer of pixel (u, v) with inverse depth wa into the other camera of
+// the pose (D = R^T - I, Rtt = R^T t), in displacement form: with the ray x,
+// W Y = R^T (x - W t) = x + d and d = D x - W Rtt, so Y_z W = 1 + d_z and
+// the transferred position is p + (f_x (d_x - x_u d_z), f_y (d_y - x_v d_z)) /
+// (1 + d_z).  The displacement is formed from small terms and keeps its
+// relative precision, where an absolute position of hundreds of pixels would
+// round to ~6e-5 px in FP32 (enough to move a bilinear sample across a depth
+// edge).  Fills the bilinear taps of the other camera's W and returns whether
+// the transfer is in front, inside [-0.5, w-0.5) x [-0.5, h-0.5) and has four
+// valid taps.
+struct Transfer {
+    float wb;    // bilinear W at the transferred position
+    float iz;    // 1 / (W Y_z)
+    float az;    // (R^T x)_z
+};
+
+template <class LoadW>
+__device__ __forceinline__ bool transfer(LoadW ld, int w, int h, float fx, float fy, float cx,
+                                         float cy, const float* D, const float* Rtt, int u, int v,
+                                         float wa, Transfer& o)
 {
     const float rx = ((float)u - cx) / fx, ry = ((float)v - cy) / fy;
-    const float ax = fmaf(RT[0], rx, fmaf(RT[1], ry, RT[2]));
-    const float ay = fmaf(RT[3], rx, fmaf(RT[4], ry, RT[5]));
-    const float az = fmaf(RT[6], rx, fmaf(RT[7], ry, RT[8]));
-    // W_kf * Y with Y = R^T (x / W_kf - t)
-    const float yx = fmaf(-wkf, Rtt[0], ax), yy = fmaf(-wkf, Rtt[1], ay);
-    const float yz = fmaf(-wkf, Rtt[2], az);
+    const float dz0 = fmaf(D[6], rx, fmaf(D[7], ry, D[8]));
+    const float dx = fmaf(D[0], rx, fmaf(D[1], ry, fmaf(-wa, Rtt[0], D[2])));
+    const float dy = fmaf(D[3], rx, fmaf(D[4], ry, fmaf(-wa, Rtt[1], D[5])));
+    const float dz = fmaf(-wa, Rtt[2], dz0);
+    const float yz = 1.0f + dz;
     if (!(yz > 0.0f)) return false;
     const float iz = 1.0f / yz;
-    const float ub = fmaf(fx * yx, iz, cx), vb = fmaf(fy * yy, iz, cy);
+    const float du = fx * fmaf(-rx, dz, dx) * iz, dv = fy * fmaf(-ry, dz, dy) * iz;
+    const float ub = (float)u + du, vb = (float)v + dv;
     if (!(ub >= -0.5f && ub < (float)w - 0.5f && vb >= -0.5f && vb < (float)h - 0.5f)) return false;
-    const float fu = floorf(ub), fv = floorf(vb);
-    const float al = ub - fu, be = vb - fv;
-    int x0 = (int)fu, y0 = (int)fv;
+    // taps floor(p) = p + floor(displacement) (p integer) and the next ones,
+    // clamped to the image; the weights are the displacement's fractions
+    const float fu = floorf(du), fv = floorf(dv);
+    const float al = du - fu, be = dv - fv;
+    int x0 = u + (int)fu, y0 = v + (int)fv;
     const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
     x0 = max(x0, 0);
     y0 = max(y0, 0);
-    const float p00 = Wk[(long long)y0 * pitch + x0];
-    const float p10 = Wk[(long long)y0 * pitch + x1];
-    const float p01 = Wk[(long long)y1 * pitch + x0];
-    const float p11 = Wk[(long long)y1 * pitch + x1];
+    const float p00 = ld(x0, y0), p10 = ld(x1, y0), p01 = ld(x0, y1), p11 = ld(x1, y1);
     if (!(w_valid(p00) && w_valid(p10) && w_valid(p01) && w_valid(p11))) return false;
-    const float wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 +
-                     (1.0f - al) * be * p01 + al * be * p11;
-    // predicted inverse depth in frame k: 1 / Y_z = W_kf / yz
-    const float wk = wkf * iz;
-    if (!(fabsf(wb - wk) < tol)) return false;
-    const float den = fmaf(wb, Rtt[2], 1.0f);
-    const float ws = az * wb / den;
-    const float q = den * den / az;
+    o.wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 + (1.0f - al) * be * p01 +
+           al * be * p11;
+    o.iz = iz;
+    o.az = 1.0f + dz0;
+    return true;
+}
+
+// One frame's fusion step at keyframe pixel (u, v) (sec. 7.2): the pixel
+// with fused inverse depth wkf (valid) is transferred into frame k, W_k is
+// sampled bilinearly, and if it passes the covisibility test the warped
+// inverse depth W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) is merged into
+// (wkf, ckf) with C_k = ((1 + w_b (R^T t)_z)^2 / (R^T x)_z)^2.  Returns
+// whether the pixel fused.
+__device__ __forceinline__ bool fuse_step(const float* __restrict__ Wk, long long pitch, int w,
+                                          int h, float fx, float fy, float cx, float cy,
+                                          const float* D, const float* Rtt, float tol, int u,
+                                          int v, float& wkf, float& ckf)
+{
+    Transfer t;
+    auto ld = [&](int x, int y) { return Wk[(long long)y * pitch + x]; };
+    if (!transfer(ld, w, h, fx, fy, cx, cy, D, Rtt, u, v, wkf, t)) return false;
+    // predicted inverse depth in frame k: 1 / Y_z = W_kf / (W_kf Y_z)
+    const float wk = wkf * t.iz;
+    if (!(fabsf(t.wb - wk) < tol)) return false;
+    const float den = fmaf(t.wb, Rtt[2], 1.0f);
+    const float ws = t.az * t.wb / den;
+    const float q = den * den / t.az;
     const float ck = q * q;
     if (!(w_valid(ws) && ck > 0.0f && ck < INFINITY)) return false;
     wkf = (wkf * ckf + ck * ws) / (ckf + ck);
@@ -82,7 +111,7 @@ __global__ void __launch_bounds__(256) k_fuse(FuseArgs a)
         float wkf = a.Wkf[i];
         if (w_valid(wkf)) {
             float ckf = a.Ckf[i];
-            fused = fuse_step(a.Wk, a.pitch, a.w, a.h, a.fx, a.fy, a.cx, a.cy, a.RT, a.Rtt, a.tol,
+            fused = fuse_step(a.Wk, a.pitch, a.w, a.h, a.fx, a.fy, a.cx, a.cy, a.D, a.Rtt, a.tol,
                               u, v, wkf, ckf);
             if (fused) {
                 a.Wkf[i] = wkf;
@@ -113,7 +142,7 @@ __global__ void __launch_bounds__(256) k_fuse_batch(FuseBatchArgs a)
         const FuseFrame& F = a.frames[f];
         bool fused = false;
         if (in && w_valid(wkf))
-            fused = fuse_step(F.Wk, a.pitch, a.w, a.h, a.fx, a.fy, a.cx, a.cy, F.RT, F.Rtt, a.tol, u,
+            fused = fuse_step(F.Wk, a.pitch, a.w, a.h, a.fx, a.fy, a.cx, a.cy, F.D, F.Rtt, a.tol, u,
                               v, wkf, ckf);
         any = any || fused;
         if (a.count) add_count(wave_counts, fused, a.count + f);
@@ -204,33 +233,10 @@ __global__ void __launch_bounds__(256) k_covis(CovisArgs a)
         const float wa = load_wp<F16>(a.WA, i);
         if (w_valid(wa)) {
             inH = true;
-            const float rx = ((float)u - a.cx) / a.fx, ry = ((float)v - a.cy) / a.fy;
-            const float ax = fmaf(a.RT[0], rx, fmaf(a.RT[1], ry, a.RT[2]));
-            const float ay = fmaf(a.RT[3], rx, fmaf(a.RT[4], ry, a.RT[5]));
-            const float az = fmaf(a.RT[6], rx, fmaf(a.RT[7], ry, a.RT[8]));
-            const float yx = fmaf(-wa, a.Rtt[0], ax), yy = fmaf(-wa, a.Rtt[1], ay);
-            const float yz = fmaf(-wa, a.Rtt[2], az);
-            if (yz > 0.0f) {
-                const float iz = 1.0f / yz;
-                const float ub = fmaf(a.fx * yx, iz, a.cx), vb = fmaf(a.fy * yy, iz, a.cy);
-                if (ub >= -0.5f && ub < (float)a.w - 0.5f && vb >= -0.5f && vb < (float)a.h - 0.5f) {
-                    const float fu = floorf(ub), fv = floorf(vb);
-                    const float al = ub - fu, be = vb - fv;
-                    int x0 = (int)fu, y0 = (int)fv;
-                    const int x1 = min(x0 + 1, a.w - 1), y1 = min(y0 + 1, a.h - 1);
-                    x0 = max(x0, 0);
-                    y0 = max(y0, 0);
-                    const float p00 = load_wp<F16>(a.WB, (long long)y0 * a.w + x0);
-                    const float p10 = load_wp<F16>(a.WB, (long long)y0 * a.w + x1);
-                    const float p01 = load_wp<F16>(a.WB, (long long)y1 * a.w + x0);
-                    const float p11 = load_wp<F16>(a.WB, (long long)y1 * a.w + x1);
-                    if (w_valid(p00) && w_valid(p10) && w_valid(p01) && w_valid(p11)) {
-                        const float wb = (1.0f - al) * (1.0f - be) * p00 + al * (1.0f - be) * p10 +
-                                         (1.0f - al) * be * p01 + al * be * p11;
-                        inV = fabsf(wb - wa * iz) < a.tol;
-                    }
-                }
-            }
+            Transfer t;
+            auto ld = [&](int x, int y) { return load_wp<F16>(a.WB, (long long)y * a.w + x); };
+            if (transfer(ld, a.w, a.h, a.fx, a.fy, a.cx, a.cy, a.D, a.Rtt, u, v, wa, t))
+                inV = fabsf(t.wb - wa * t.iz) < a.tol;
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -148,7 +148,7 @@ struct FuseArgs {
     long long pitch;
     int w, h;
     float fx, fy, cx, cy;
-    float RT[9];          // R^T of the pose of frame k in the keyframe
+    float D[9];           // R^T - I for the pose of frame k in the keyframe (formed in FP64)
     float Rtt[3];         // R^T t
     float tol;
     unsigned long long* count;
@@ -158,8 +158,8 @@ hipError_t launch_fuse(hipStream_t s, const FuseArgs& a);
 // A frame of a batched fusion (device-side table).
 struct FuseFrame {
     const float* Wk;
-    float RT[9];
-    float Rtt[3];
+    float D[9];     // R^T - I (formed in FP64)
+    float Rtt[3];   // R^T t
 };
 constexpr int kMaxFuseBatch = 256;
 struct FuseBatchArgs {
@@ -182,7 +182,7 @@ struct CovisArgs {
     int f16;
     int w, h;
     float fx, fy, cx, cy;
-    float RT[9];          // R^T of the pose of B in A
+    float D[9];           // R^T - I for the pose of B in A (formed in FP64)
     float Rtt[3];         // R^T t
     float tol;
     unsigned long long* count;   // [0] += |S_H|, [1] += |S_V|

@@ -60,8 +60,16 @@ def test_pyramid_matches_oracle(ctx, c2_pairs, storage):
         assert Ig.shape == Ir.shape
         np.testing.assert_array_equal(Wg > 0, Wr > 0)
         if storage == 0:
-            np.testing.assert_allclose(Ig, Ir, rtol=5e-7, atol=0)   # FP32 vs FP64 sum order
-            np.testing.assert_allclose(Wg, Wr, rtol=5e-7, atol=0)
+            # A level is the mean of up to four non-negative FP32 values of
+            # the level below: the sum rounds at most three times (each
+            # <= u = 2^-24 of the partial sum, so <= 3u of the total) and the
+            # division by 4 is exact, by 2 exact, by 3 rounds once after two
+            # additions: <= 3u per level.  The inputs of level l carry level
+            # l-1's relative error, which a mean of positives keeps, so level
+            # l is within 3 l u of the FP64 recursion (level 0 is the input).
+            rtol = 3 * l * 2.0 ** -24
+            np.testing.assert_allclose(Ig, Ir, rtol=rtol, atol=0)
+            np.testing.assert_allclose(Wg, Wr, rtol=rtol, atol=0)
         else:
             # FP16 levels: identical rounding except rare double-rounding ties
             assert np.mean(Ig != Ir) < 1e-3 and np.mean(Wg != Wr) < 1e-3
@@ -302,7 +310,8 @@ def test_bench_workload_sampled_against_oracle(ctx):
     # The timed step's alignment as the bench runs it: 64 pairs of 640x480
     # (room + boxes, 10% holes), 4 levels x 10 Huber iterations, FULLRES, FP32,
     # autotuned launch shapes, the default launch chains, one batch.  Four
-    # pairs spread over the batch (so over both chains) against the oracle.
+    # pairs spread over the batch (0, 21, 42, 63: every default launch chain
+    # holds at least one) against the oracle.
     rg = _rg()
     pairs = [synth.pair_c2(i, ss=2, device="cuda") for i in range(64)]
     As = [_pyr(ctx, p.cam, 4, p.A) for p in pairs]
@@ -312,6 +321,31 @@ def test_bench_workload_sampled_against_oracle(ctx):
     got, stats = rg.rgbid_align_batch(ctx, As, Bs, prm)
     for i in (0, 21, 42, 63):
         p = pairs[i]
+        Ro, to, so = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(4, [10] * 4))
+        assert stats[i]["status"] == 0 and so["status"] == 0, i
+        assert rot_err(got[i][0], Ro) <= 1e-5 and np.linalg.norm(got[i][1] - to) <= 1e-5, i
+    for P in As + Bs:
+        rg.rgbid_pyramid_free(P)
+
+
+def test_mixed_batch_c4_sampled_against_oracle(ctx):
+    # The batched form at its own shapes: 24 x 320x240 + 32 x 640x480 +
+    # 8 x 1280x960 pairs (room + boxes, 10% holes) aligned in one batch, 4
+    # levels x 10 Huber iterations, FULLRES, FP32, autotuned launch shapes,
+    # the default launch chains.  Two pairs of every size (the first and the
+    # last of each group, so sample strides 1..8 and the largest chunk tables
+    # are all exercised) against the oracle.
+    rg = _rg()
+    pairs = synth.batch_c4(ss=2, device="cuda")
+    assert [p.cam.w for p in pairs] == [320] * 24 + [640] * 32 + [1280] * 8
+    As = [_pyr(ctx, p.cam, 4, p.A) for p in pairs]
+    Bs = [_pyr(ctx, p.cam, 4, p.B) for p in pairs]
+    prm = _params(4, [10] * 4)
+    rg.rgbid_autotune(ctx, As, Bs, prm, reps=1)
+    got, stats = rg.rgbid_align_batch(ctx, As, Bs, prm)
+    for i in (0, 23, 24, 55, 56, 63):
+        p = pairs[i]
+        print("c4 pair %d (%dx%d) against the oracle" % (i, p.cam.w, p.cam.h), flush=True)
         Ro, to, so = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(4, [10] * 4))
         assert stats[i]["status"] == 0 and so["status"] == 0, i
         assert rot_err(got[i][0], Ro) <= 1e-5 and np.linalg.norm(got[i][1] - to) <= 1e-5, i
@@ -444,11 +478,46 @@ def test_fuse_batch_equals_sequential(ctx):
     rg.rgbid_keyframe_free(K2)
 
 
+def _fuse_margins(cam, Wkf, Wk, R, t, tol):
+    """Per keyframe pixel, in FP64: the covisibility margin |W_k(p_w) - 1/Y_z|
+    - tol of the fusion test (sec. 7.2, sec. 6.4) where the transfer reaches
+    it (NaN elsewhere), and the distance of p_w to the bilinear bounds
+    [-0.5, w - 0.5) x [-0.5, h - 0.5) (inf where Y_z <= 0)."""
+    h, w = Wkf.shape
+    v, u = np.mgrid[0:h, 0:w].astype(np.float64)
+    ok = Wkf > 0
+    wa = np.where(ok, Wkf, 1.0)
+    ray = np.stack([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy, np.ones_like(u)], -1)
+    Y = (ray / wa[..., None] - np.asarray(t)) @ np.asarray(R)     # R^T (X - t), row form
+    front = ok & (Y[..., 2] > 0)
+    z = np.where(front, Y[..., 2], 1.0)
+    ub = cam.fx * Y[..., 0] / z + cam.cx
+    vb = cam.fy * Y[..., 1] / z + cam.cy
+    dist = np.minimum.reduce([np.abs(ub + 0.5), np.abs(ub - (w - 0.5)),
+                              np.abs(vb + 0.5), np.abs(vb - (h - 0.5))])
+    dist = np.where(front, dist, np.inf)
+    inb = front & (ub >= -0.5) & (ub < w - 0.5) & (vb >= -0.5) & (vb < h - 0.5)
+    x0 = np.floor(np.where(inb, ub, 0)).astype(int)
+    y0 = np.floor(np.where(inb, vb, 0)).astype(int)
+    a, b = np.where(inb, ub, 0) - x0, np.where(inb, vb, 0) - y0
+    xa, xb = np.clip(x0, 0, w - 1), np.clip(x0 + 1, 0, w - 1)
+    ya, yb = np.clip(y0, 0, h - 1), np.clip(y0 + 1, 0, h - 1)
+    taps = [Wk[ya, xa], Wk[ya, xb], Wk[yb, xa], Wk[yb, xb]]
+    good = inb & np.all([(x > 0) & np.isfinite(x) for x in taps], axis=0)
+    wb = (1 - a) * (1 - b) * taps[0] + a * (1 - b) * taps[1] + (1 - a) * b * taps[2] + a * b * taps[3]
+    margin = np.where(good, np.abs(wb - 1.0 / z) - tol, np.nan)
+    return margin, dist
+
+
 def test_fuse_20_frames_matches_oracle(ctx):
-    # Decisions are compared frame by frame (a pixel was fused iff its C grew);
-    # W is compared on the pixels whose 20 decisions all agree.  A decision
-    # can flip only for a pixel whose |W_k(p_w) - 1/Y_z| lies within FP32
-    # rounding of tol.
+    # Decisions are compared frame by frame (a pixel was fused iff its C grew).
+    # A decision may differ only where FP32 can legitimately take it the other
+    # way: the oracle's covisibility margin |W_k(p_w) - 1/Y_z| - tol within
+    # 1e-6 (a few FP32 ulps of inverse depths up to 2 m^-1: both sides carry
+    # about four roundings of such values), or p_w within 1e-4 px of the image
+    # bounds.  W and C are compared on every pixel whose 20 decisions agree at
+    # 1e-5 relative, occlusion edges included (the transfer is formed as a
+    # displacement, so its sample position is exact to ~3e-6 px).
     rg = _rg()
     import torch
     cam, kf, frames, poses = synth.keyframe_sequence(20, seed=0, ss=2)
@@ -460,36 +529,31 @@ def test_fuse_20_frames_matches_oracle(ctx):
     agree = np.ones(Wkf0.shape, dtype=bool)
     Cg_prev = np.ones_like(Wkf0)
     total_fused = 0
-    for f, (R, t) in zip(frames, poses):
+    for k, (f, (R, t)) in enumerate(zip(frames, poses)):
         n = rg.rgbid_fuse(ctx, K, torch.from_numpy(f.W).cuda(), (R, t), tol)
-        Cr_prev = Cr
+        Cr_prev, Wr_prev = Cr, Wr
         Wr, Cr, nr = oracle.fuse(cam, Wr, Cr, f.W, R, t, tol)
         _, Cg = rg.rgbid_keyframe_read(ctx, K, (cam.h, cam.w))
         Cg = Cg.cpu().numpy().astype(np.float64)
         dec_g, dec_r = Cg > Cg_prev, Cr > Cr_prev
-        flips = int((dec_g != dec_r).sum())
-        assert flips <= 20, flips
+        flip = dec_g != dec_r
         assert int(dec_g.sum()) == n and int(dec_r.sum()) == nr
-        agree &= dec_g == dec_r
+        if flip.any():
+            margin, dist = _fuse_margins(cam, Wr_prev, f.W.astype(np.float64), R, t, tol)
+            vv, uu = np.nonzero(flip)
+            print("frame %d: %d decision(s) differ:" % (k, len(vv)),
+                  [(int(a), int(b), float(margin[a, b]), float(dist[a, b])) for a, b in zip(vv, uu)])
+            near = (np.abs(np.nan_to_num(margin, nan=np.inf)) <= 1e-6) | (dist <= 1e-4)
+            assert np.all(near[flip]), "a decision differs away from the threshold"
+        assert int(flip.sum()) <= 20
+        agree &= ~flip
         Cg_prev = Cg
         total_fused += n
     assert total_fused > 20 * 0.5 * cam.w * cam.h
     Wg, Cg = rg.rgbid_keyframe_read(ctx, K, (cam.h, cam.w))
     Wg, Cg = Wg.cpu().numpy().astype(np.float64), Cg.cpu().numpy().astype(np.float64)
     assert agree.mean() > 0.999
-    # Occlusion edges of the keyframe: bilinear taps there straddle a depth
-    # jump, so an FP32 position error of ~3e-5 px moves W* by slope x 3e-5.
-    # Those pixels get 1e-4; all others 1e-5.
-    Wp = np.pad(Wkf0, 1, mode="edge")
-    edge = np.zeros_like(agree)
-    for dv in (-1, 0, 1):
-        for du in (-1, 0, 1):
-            nb = Wp[1 + dv:1 + dv + cam.h, 1 + du:1 + du + cam.w]
-            edge |= np.abs(nb - Wkf0) > 0.05 * np.maximum(Wkf0, 1e-9)
-    flat = agree & ~edge
-    assert flat.sum() > 0.8 * (Wkf0 > 0).sum()
-    np.testing.assert_allclose(Wg[flat], Wr[flat], rtol=1e-5)
-    np.testing.assert_allclose(Wg[agree], Wr[agree], rtol=1e-4)
+    np.testing.assert_allclose(Wg[agree], Wr[agree], rtol=1e-5)
     np.testing.assert_allclose(Cg[agree], Cr[agree], rtol=1e-5)
     assert np.all((Wg > 0) == (Wkf0 > 0))       # keyframe holes stay holes
     rg.rgbid_keyframe_free(K)
