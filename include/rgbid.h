@@ -190,6 +190,28 @@ rgbid_status rgbid_align(rgbid_ctx* ctx, const rgbid_pyr* A, const rgbid_pyr* B,
                          const rgbid_pose* init, const rgbid_align_params* params,
                          rgbid_pose* out, rgbid_align_stats* stats);
 
+/* rgbid_align for callers that cannot allocate memory: code under HIP graph
+   capture of the surrounding work, tight serving loops, harnesses that
+   forbid hipMalloc.  Same arguments, results and errors as rgbid_align for
+   one pair with the library's default launch shapes (the ones rgbid_align
+   uses for a pair shape it has not tuned), and the same poses bit for bit
+   in that case.  It calls no device or host allocation routine and no graph:
+   every device buffer (pair descriptor, state, chunk tables, partial sums,
+   sample residuals, stored warped level images) lies in one static device
+   array of 8 MiB per device, which the library reaches through the address
+   rgbid_create looks up for its device and holds until the process ends;
+   tables are written by a set-up kernel from its arguments, and the results
+   are read back into the call's own stack memory.  A pair whose buffers
+   need more than 8 MiB is refused with E_ARG (a 1280x960 pair needs under
+   3 MiB with FULLRES, its largest stored warped level being 640x480).
+   Every call on a device shares that device's array and leaves its contents
+   behind: calls that overlap on one device (two host threads, or two
+   contexts on different streams) race and must be serialised by the caller.
+   Synchronises the context's stream. */
+rgbid_status rgbid_align_noalloc(rgbid_ctx* ctx, const rgbid_pyr* A, const rgbid_pyr* B,
+                                 const rgbid_pose* init, const rgbid_align_params* params,
+                                 rgbid_pose* out, rgbid_align_stats* stats);
+
 /* Aligns n independent pairs (A[i], B[i]) of possibly different sizes in one
    schedule: every iteration of every level is a fixed sequence of launches
    that covers all pairs, replayed from a cached HIP graph when the batch

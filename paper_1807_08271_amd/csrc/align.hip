@@ -1634,6 +1634,37 @@ hipError_t launch_export(hipStream_t s, const PairState* states, int n, rgbid_po
     return hipGetLastError();
 }
 
+namespace {
+
+// One thread per chunk of the tables; thread 0 also writes the descriptor,
+// the state and the per-level chunk ranges.
+__global__ void __launch_bounds__(256) k_noalloc_setup(NoAllocSetup a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *a.desc_dev = a.desc;
+        *a.state_dev = a.state;
+        for (int l = 0; l < a.levels; ++l) {
+            a.begins[2 * l] = 0;
+            a.begins[2 * l + 1] = a.n_red[l];
+        }
+    }
+    if (i >= a.seg_first[a.nseg]) return;
+    int k = 0;
+    while (i >= a.seg_first[k + 1]) ++k;
+    const int t = (i - a.seg_first[k]) * a.seg_per[k];
+    a.chunks[i] = Chunk{0, t, min(a.seg_per[k], a.seg_tiles[k] - t)};
+}
+
+}  // namespace
+
+hipError_t launch_noalloc_setup(hipStream_t s, const NoAllocSetup& a)
+{
+    const int n = a.seg_first[a.nseg];
+    hipLaunchKernelGGL(k_noalloc_setup, dim3(((n > 0 ? n : 1) + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs)
 {
     hipLaunchKernelGGL(k_level_start, dim3((npairs + 63) / 64), dim3(64), 0, s, states, npairs);

@@ -85,10 +85,20 @@ struct rgbid_ctx {
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
     bool profiling = false;
+    void* scratch_dev = nullptr;     // this device's copy of `scratch` (allocation-free call)
     std::vector<hipEvent_t> events;  // timing events, grown on demand
     double prof_ms[kMaxLevels * 4] = {};
     long long prof_n[kMaxLevels * 4] = {};
 };
+
+// Device memory of the allocation-free alignment (rgbid_align_noalloc):
+// descriptor, state, chunk tables, partial sums, sample residuals and the
+// stored warped level images of one pair.  Each device holds its own copy
+// for the life of the process; kernels reach it only through the address
+// hipGetSymbolAddress returns on that device (the array's name in host code
+// is a host-side stand-in).
+constexpr size_t kScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -217,20 +227,28 @@ void pose_flow_floats(const double R[9], const double t[3], float D[9], float Rt
     }
 }
 
+// NULL if the parameters are usable, else a static description.
+const char* params_problem(const rgbid_align_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->levels < 1 || p->levels > kMaxLevels) return "levels outside 1..8";
+    for (int l = 0; l < p->levels; ++l)
+        if (p->iters[l] < 0 || p->iters[l] > 10000) return "iters outside 0..10000";
+    if (p->weight != RGBID_W_STUDENT_T && p->weight != RGBID_W_HUBER) return "unknown weight";
+    if (!(p->huber_k > 0.0)) return "huber_k must be > 0";
+    if (p->sample_max < 1 || p->sample_max > kMaxSample) return "sample_max outside 1..24576";
+    if (p->scale_iters < 0 || p->scale_iters > 1000) return "scale_iters outside 0..1000";
+    if (p->warp != RGBID_WARP_FULLRES && p->warp != RGBID_WARP_PER_LEVEL) return "unknown warp mode";
+    if (p->warp == RGBID_WARP_FULLRES && p->levels > 5) return "FULLRES warp supports at most 5 levels";
+    if (p->stop_eps_t < 0 || p->stop_eps_r < 0) return "negative stop epsilon";
+    return nullptr;
+}
+
 bool params_ok(const rgbid_align_params* p, std::string& why)
 {
-    if (!p) { why = "params is NULL"; return false; }
-    if (p->levels < 1 || p->levels > kMaxLevels) { why = "levels outside 1..8"; return false; }
-    for (int l = 0; l < p->levels; ++l)
-        if (p->iters[l] < 0 || p->iters[l] > 10000) { why = "iters outside 0..10000"; return false; }
-    if (p->weight != RGBID_W_STUDENT_T && p->weight != RGBID_W_HUBER) { why = "unknown weight"; return false; }
-    if (!(p->huber_k > 0.0)) { why = "huber_k must be > 0"; return false; }
-    if (p->sample_max < 1 || p->sample_max > kMaxSample) { why = "sample_max outside 1..24576"; return false; }
-    if (p->scale_iters < 0 || p->scale_iters > 1000) { why = "scale_iters outside 0..1000"; return false; }
-    if (p->warp != RGBID_WARP_FULLRES && p->warp != RGBID_WARP_PER_LEVEL) { why = "unknown warp mode"; return false; }
-    if (p->warp == RGBID_WARP_FULLRES && p->levels > 5) { why = "FULLRES warp supports at most 5 levels"; return false; }
-    if (p->stop_eps_t < 0 || p->stop_eps_r < 0) { why = "negative stop epsilon"; return false; }
-    return true;
+    const char* e = params_problem(p);
+    if (e) why = e;
+    return !e;
 }
 
 struct Step {
@@ -738,6 +756,16 @@ rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream)
         delete c;
         return RGBID_E_DEVICE;
     }
+    // this device's copy of the allocation-free call's scratch array
+    if (hipGetSymbolAddress(&c->scratch_dev, HIP_SYMBOL(scratch)) != hipSuccess || !c->scratch_dev) {
+        (void)hipStreamDestroy(c->cap);
+        (void)hipEventDestroy(c->stage_done);
+        (void)hipEventDestroy(c->tev[0]);
+        (void)hipEventDestroy(c->tev[1]);
+        delete c;
+        return RGBID_E_DEVICE;
+    }
+    c->err.reserve(512);   // error texts never reallocate (allocation-free call)
     const char* g = std::getenv("RGBID_NO_GRAPH");
     c->use_graphs = !(g && g[0] == '1');
     if (const char* ch = std::getenv("RGBID_CHAINS")) c->chains = std::max(1, std::min(8, std::atoi(ch)));
@@ -931,6 +959,177 @@ rgbid_status rgbid_align(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B,
     if (stats) *stats = s;
     if (s.status != RGBID_OK)
         return set_err(c, (rgbid_status)s.status, "alignment stopped: degenerate normal equations");
+    return RGBID_OK;
+}
+
+// The single-pair alignment of rgbid_align with every device buffer carved
+// from this device's `scratch` array and the tables written by a set-up
+// kernel: no device or host allocation, no graph, default launch shapes
+// (the ones rgbid_align uses for a pair it has not tuned).
+rgbid_status rgbid_align_noalloc(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_pyr* B,
+                                 const rgbid_pose* init, const rgbid_align_params* P,
+                                 rgbid_pose* out, rgbid_align_stats* stats)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!out || !A || !B) return set_err(c, RGBID_E_ARG, "NULL pyramid or output");
+    if (const char* e = params_problem(P)) return set_err(c, RGBID_E_ARG, "%s", e);
+    if (A->device != c->device || B->device != c->device)
+        return set_err(c, RGBID_E_ARG, "pyramid lives on another device");
+    if (A->w[0] != B->w[0] || A->h[0] != B->h[0] || A->f16 != B->f16)
+        return set_err(c, RGBID_E_SHAPE, "A and B differ in size or format");
+    if (A->cam.fx != B->cam.fx || A->cam.fy != B->cam.fy || A->cam.cx != B->cam.cx ||
+        A->cam.cy != B->cam.cy)
+        return set_err(c, RGBID_E_SHAPE, "A and B have different cameras");
+    if (A->levels < P->levels || B->levels < P->levels)
+        return set_err(c, RGBID_E_SHAPE, "pyramid has fewer levels than params");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int L = P->levels;
+    const bool fullres = P->warp == RGBID_WARP_FULLRES;
+
+    // ---- launch shapes, chunk segments and the scratch layout
+    NoAllocSetup su;
+    std::memset(&su, 0, sizeof su);
+    LevelTune tune[kMaxLevels];
+    int nwarp[kMaxLevels], scale_per[kMaxLevels];
+    size_t warped_px = 0;
+    int nch = 0;
+    for (int l = 0; l < L; ++l) {
+        const int b = fullres ? l : 0;
+        tune[l] = default_tune(b);
+        const int w = A->w[l], h = A->h[l];
+        const int s = sample_stride(w, h, P->sample_max);
+        su.desc.stride[l] = s;
+        su.desc.sw[l] = (w + s - 1) / s;
+        su.desc.sh[l] = (h + s - 1) / s;
+        scale_per[l] = (su.desc.sw[l] * su.desc.sh[l] + kScaleThreads - 1) / kScaleThreads;
+        const long long ngrid =
+            tune[l].fused ? (long long)su.desc.sw[l] * su.desc.sh[l] : (long long)w * h;
+        const int gpp = warp_pixels_per_pass(b);
+        const int wper = tune[l].waves * tune[l].warp_passes;
+        const int rper = tune[l].waves * tune[l].tiles_per_wave;
+        const int wt = (int)((ngrid + gpp - 1) / gpp), rt = (int)(((long long)w * h + 63) / 64);
+        nwarp[l] = (wt + wper - 1) / wper;
+        su.n_red[l] = (rt + rper - 1) / rper;
+        su.seg_first[2 * l] = nch;
+        su.seg_tiles[2 * l] = wt;
+        su.seg_per[2 * l] = wper;
+        nch += nwarp[l];
+        su.seg_first[2 * l + 1] = nch;
+        su.seg_tiles[2 * l + 1] = rt;
+        su.seg_per[2 * l + 1] = rper;
+        nch += su.n_red[l];
+        if (!tune[l].fused) warped_px = std::max(warped_px, (size_t)w * h);
+    }
+    su.levels = L;
+    su.nseg = 2 * L;
+    su.seg_first[2 * L] = nch;
+    int max_red = 0;
+    for (int l = 0; l < L; ++l) max_red = std::max(max_red, su.n_red[l]);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_desc = carve(sizeof(PairDesc)), o_state = carve(sizeof(PairState));
+    const size_t o_chunks = carve((size_t)nch * sizeof(Chunk));
+    const size_t o_begins = carve((size_t)2 * L * sizeof(int));
+    const size_t o_part = carve((size_t)std::max(max_red, 1) * kNSum * sizeof(float2));
+    const size_t o_sample = carve((size_t)P->sample_max * sizeof(float2));
+    const size_t o_warped = carve(std::max<size_t>(warped_px, 1) * sizeof(float2));
+    if (off > kScratchBytes)
+        return set_err(c, RGBID_E_ARG,
+                       "pair needs %zu bytes of scratch, the allocation-free call has %zu", off,
+                       kScratchBytes);
+    char* base = static_cast<char*>(c->scratch_dev);
+
+    // ---- descriptor, initial state, tables: written on the device
+    for (int l = 0; l < L; ++l) {
+        su.desc.A[l] = LevelView{A->iw[l], A->wp[l], static_cast<const unsigned char*>(A->gm[l]),
+                                 A->w[l], A->h[l], (float)A->fx[l], (float)A->fy[l],
+                                 (float)A->cx[l], (float)A->cy[l]};
+        su.desc.B[l] = LevelView{B->iw[l], B->wp[l], static_cast<const unsigned char*>(B->gm[l]),
+                                 B->w[l], B->h[l], (float)B->fx[l], (float)B->fy[l],
+                                 (float)B->cx[l], (float)B->cy[l]};
+    }
+    su.desc.warped = reinterpret_cast<float2*>(base + o_warped);
+    su.desc.sample = reinterpret_cast<float2*>(base + o_sample);
+    PairState& s0 = su.state;
+    if (init) {
+        std::memcpy(s0.R, init->R, sizeof s0.R);
+        std::memcpy(s0.t, init->t, sizeof s0.t);
+    } else {
+        s0.R[0] = s0.R[4] = s0.R[8] = 1.0;
+    }
+    pose_floats(s0.R, s0.t, s0.RT, s0.Rtt);
+    s0.status = RGBID_OK;
+    s0.active = 1;
+    s0.sigma[0] = s0.sigma[1] = 1.0f;
+    s0.nu[0] = s0.nu[1] = 5.0f;
+    su.desc_dev = reinterpret_cast<PairDesc*>(base + o_desc);
+    su.state_dev = reinterpret_cast<PairState*>(base + o_state);
+    su.chunks = reinterpret_cast<Chunk*>(base + o_chunks);
+    su.begins = reinterpret_cast<int*>(base + o_begins);
+    HIPCHK(c, launch_noalloc_setup(c->stream, su));
+
+    // ---- the schedule: levels L-1 .. 0, plain launches
+    IterParams ip;
+    std::memset(&ip, 0, sizeof ip);
+    ip.weight = P->weight;
+    ip.huber_k = (float)P->huber_k;
+    ip.estimate_nu = P->estimate_nu;
+    ip.scale_iters = P->scale_iters;
+    ip.warp_mode = P->warp;
+    ip.stop_eps_t = P->stop_eps_t;
+    ip.stop_eps_r = P->stop_eps_r;
+    for (int l = L - 1; l >= 0; --l) {
+        if (P->iters[l] <= 0) continue;
+        HIPCHK(c, launch_level_start(c->stream, su.state_dev, 1));
+        IterLaunch il;
+        std::memset(&il, 0, sizeof il);
+        il.pairs = su.desc_dev;
+        il.states = su.state_dev;
+        il.npairs = 1;
+        il.level = l;
+        il.ip = ip;
+        il.tune = tune[l];
+        il.f16 = A->f16;
+        il.block_log2 = fullres ? l : 0;
+        il.warp_chunks = su.chunks + su.seg_first[2 * l];
+        il.n_warp_chunks = nwarp[l];
+        il.red_chunks = su.chunks + su.seg_first[2 * l + 1];
+        il.n_red_chunks = su.n_red[l];
+        il.pair_red_begin = su.begins + 2 * l;
+        il.partials = reinterpret_cast<float2*>(base + o_part);
+        il.update = 1;
+        il.scale_per = scale_per[l];
+        il.kernels = 15;
+        for (int it = 0; it < P->iters[l]; ++it) HIPCHK(c, launch_iteration(c->stream, il, nullptr));
+    }
+
+    // ---- results: the state into host memory the call owns on its stack
+    PairState r;
+    HIPCHK(c, hipMemcpyAsync(&r, su.state_dev, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(out->R, r.R, sizeof r.R);
+    std::memcpy(out->t, r.t, sizeof r.t);
+    if (stats) {
+        std::memcpy(stats->H, r.H, sizeof r.H);
+        std::memcpy(stats->g, r.g, sizeof r.g);
+        stats->mu_I = r.mu[0];
+        stats->sigma_I = r.sigma[0];
+        stats->nu_I = r.nu[0];
+        stats->mu_W = r.mu[1];
+        stats->sigma_W = r.sigma[1];
+        stats->nu_W = r.nu[1];
+        stats->cost = r.cost;
+        stats->n_valid_I = r.nI;
+        stats->n_valid_W = r.nW;
+        for (int l = 0; l < 8; ++l) stats->iters_done[l] = l < kMaxLevels ? r.iters_done[l] : 0;
+        stats->status = r.status;
+    }
+    if (r.status != RGBID_OK)
+        return set_err(c, (rgbid_status)r.status, "alignment stopped: degenerate normal equations");
     return RGBID_OK;
 }
 

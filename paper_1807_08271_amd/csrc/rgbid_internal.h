@@ -141,6 +141,29 @@ hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs);
 hipError_t launch_export(hipStream_t s, const PairState* states, int n, rgbid_pose* out,
                          rgbid_align_stats* stats);
 
+// Device-side set-up of the allocation-free single-pair alignment: the pair
+// descriptor, its initial state and the chunk tables are written from the
+// kernel arguments into device memory the caller provides (no host-to-device
+// copy, no staging buffer).  The chunk tables are nseg segments back to back:
+// segment k covers seg_tiles[k] tiles in chunks of seg_per[k] tiles, chunks
+// seg_first[k] .. seg_first[k + 1] - 1 (seg_first[nseg] = all chunks).
+constexpr int kNoAllocSegs = 2 * kMaxLevels;
+struct NoAllocSetup {
+    PairDesc desc;
+    PairState state;
+    PairDesc* desc_dev;
+    PairState* state_dev;
+    Chunk* chunks;
+    int* begins;                         // per level: {0, reduction chunks}
+    int levels;
+    int nseg;
+    int seg_first[kNoAllocSegs + 1];
+    int seg_tiles[kNoAllocSegs];
+    int seg_per[kNoAllocSegs];
+    int n_red[kMaxLevels];
+};
+hipError_t launch_noalloc_setup(hipStream_t s, const NoAllocSetup& a);
+
 struct FuseArgs {
     float* Wkf;
     float* Ckf;

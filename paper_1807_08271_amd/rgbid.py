@@ -130,6 +130,9 @@ _SIGS = {
     "rgbid_pyramid_free": (None, [_P]),
     "rgbid_align": (C.c_int, [_P, _P, _P, C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
                               C.POINTER(rgbid_pose), C.POINTER(rgbid_align_stats)]),
+    "rgbid_align_noalloc": (C.c_int, [_P, _P, _P, C.POINTER(rgbid_pose),
+                                      C.POINTER(rgbid_align_params), C.POINTER(rgbid_pose),
+                                      C.POINTER(rgbid_align_stats)]),
     "rgbid_align_batch": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P),
                                     C.POINTER(rgbid_pose), C.POINTER(rgbid_align_params),
                                     C.POINTER(rgbid_pose), C.POINTER(rgbid_align_stats)]),
@@ -349,6 +352,19 @@ def rgbid_align(ctx, A, B, params: rgbid_align_params, init=None):
     ini = make_pose(*init) if init is not None else None
     rc = lib().rgbid_align(ctx, A, B, C.byref(ini) if ini is not None else None, C.byref(params),
                            C.byref(out), C.byref(st))
+    _check(ctx, rc, allow=(RGBID_E_DEGENERATE,))
+    R, t = pose_tuple(out)
+    return R, t, st.as_dict(), rc
+
+
+def rgbid_align_noalloc(ctx, A, B, params: rgbid_align_params, init=None):
+    """rgbid_align without any allocation (scratch in the library's static
+    device array); returns (R, t, stats dict, status)."""
+    out = rgbid_pose()
+    st = rgbid_align_stats()
+    ini = make_pose(*init) if init is not None else None
+    rc = lib().rgbid_align_noalloc(ctx, A, B, C.byref(ini) if ini is not None else None,
+                                   C.byref(params), C.byref(out), C.byref(st))
     _check(ctx, rc, allow=(RGBID_E_DEGENERATE,))
     R, t = pose_tuple(out)
     return R, t, st.as_dict(), rc
