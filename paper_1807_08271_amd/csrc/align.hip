@@ -519,30 +519,34 @@ __device__ __forceinline__ void warp_tile(const Geom& G, int tile_first, const G
     Vo = mV;
 }
 
-// Residuals (and Jacobians) of one level pixel (sec. 6.2).  r_I needs an
-// interior pixel, a valid W_A and warped values; r_W additionally the four
-// W_A neighbours (central-difference gradient).
+// Residuals of one level pixel (sec. 6.2) and whether they are defined: r_I
+// needs an interior pixel, a valid W_A and warped values; r_W additionally
+// the four W_A neighbours (central-difference gradient).
 struct Terms {
     bool vI, vW;
-    float rI, rW, lam;
-    float JI[6], JW[6];
+    float rI, rW;
 };
 
 struct Nbrs {
     float2 l, r, t, b;
 };
 
-// The four neighbours of pixel i of A.  Only interior pixels use them; the
-// clamped raster indices keep the loads of every other pixel in bounds.
+// The four neighbours of pixel i of A, read at the pixel's own byte offset
+// from shifted bases.  Every (I, W) plane of a pyramid has a guard of one row
+// and one texel (zeros) before and after it inside its allocation, so the
+// reads of border pixels (which take no part: their flags say so) stay in
+// bounds without clamping, and the four reads share the centre's address.
 template <bool F16>
 __device__ __forceinline__ Nbrs load_nbrs(const LevelView& A, unsigned i)
 {
-    const unsigned w = (unsigned)A.w, last = (unsigned)(A.w * A.h - 1);
+    constexpr unsigned tb = F16 ? 4u : 8u;
+    const unsigned off = i * tb, rowb = tb * (unsigned)A.w;
+    const char* base = static_cast<const char*>(A.iw);
     Nbrs n;
-    n.l = load_iw<F16>(A.iw, i > 0u ? i - 1u : 0u);
-    n.r = load_iw<F16>(A.iw, min(i + 1u, last));
-    n.t = load_iw<F16>(A.iw, i >= w ? i - w : 0u);
-    n.b = load_iw<F16>(A.iw, min(i + w, last));
+    n.l = load_iw_at<F16>(base - tb, off);
+    n.r = load_iw_at<F16>(base + tb, off);
+    n.t = load_iw_at<F16>(base - rowb, off);
+    n.b = load_iw_at<F16>(base + rowb, off);
     return n;
 }
 
@@ -551,122 +555,64 @@ __device__ __forceinline__ unsigned load_mask(const LevelView& A, unsigned i)
     return ld_at<unsigned char>(A.gm, i);
 }
 
-// Residuals of one level pixel (sec. 6.2) with ray x = (xu, xv, 1), c = A's
-// (I, W) at the pixel and m its validity flags (bit 0: interior with valid
-// W, bit 1: also the W gradient defined): r_I needs the warp and bit 0, r_W
-// the warp and bit 1.  JAC: also the Jacobians J = (a, X x a) of eq:res_int /
-// eq:res_depth and lambda_n.  With g = (fx dI/du, fy dI/dv) from central
-// differences, a_I = W_A (g_u, g_v, -(xu g_u + xv g_v)) (the third entry is
-// g_u (cx - u) + g_v (cy - v) written in the ray), and since X = x / W_A,
-// X x a_I = x x (a_I / W_A); likewise for a_W from the W_A gradient, whose
-// third entry adds W*.
-template <bool JAC>
-__device__ __forceinline__ void terms_core(const LevelRay& R, float xu, float xv, float2 c,
-                                           const Nbrs& n, unsigned m, float Is, float Ws, bool wv,
-                                           Terms& T)
+// Residuals of one level pixel (sec. 6.2): c = A's (I, W) at the pixel and m
+// its validity flags (bit 0: interior with valid W, bit 1: also the W
+// gradient defined): r_I needs the warp and bit 0, r_W the warp and bit 1.
+__device__ __forceinline__ void residuals(float2 c, unsigned m, float Is, float Ws, bool wv,
+                                          Terms& T)
 {
     T.vI = wv & ((m & 1u) != 0u);
     T.vW = wv & ((m & 2u) != 0u);
     T.rI = Is - c.x;
     T.rW = Ws - c.y;
-    if constexpr (JAC) {
-        const float wa = c.y;
-        const float g0 = (n.r.x - n.l.x) * R.hfx, g1 = (n.b.x - n.t.x) * R.hfy;
-        const float g2 = -fmaf(xu, g0, xv * g1);
-        T.JI[0] = wa * g0;
-        T.JI[1] = wa * g1;
-        T.JI[2] = wa * g2;
-        T.JI[3] = fmaf(xv, g2, -g1);
-        T.JI[4] = fmaf(-xu, g2, g0);
-        T.JI[5] = fmaf(xu, g1, -(xv * g0));
-        const float k0 = (n.r.y - n.l.y) * R.hfx, k1 = (n.b.y - n.t.y) * R.hfy;
-        const float k2 = -fmaf(xu, k0, xv * k1);
-        const float kw = k2 + Ws;
-        T.JW[0] = wa * k0;
-        T.JW[1] = wa * k1;
-        T.JW[2] = wa * kw;
-        T.JW[3] = fmaf(xv, kw, -k1);
-        T.JW[4] = fmaf(-xu, kw, k0);
-        T.JW[5] = fmaf(xu, k1, -(xv * k0));
-        // n~ = Z grad W (K - p e_z^T) + e_z = Z (k0, k1, k2) + e_z (Z = 1 / W_A),
-        // lambda = 1 / (|n~| |x|)
-        const float Z = rcp(wa);
-        const float n0 = Z * k0, n1 = Z * k1, n2 = fmaf(Z, k2, 1.0f);
-        const float nn = fmaf(n0, n0, fmaf(n1, n1, n2 * n2));
-        const float xx = fmaf(xu, xu, fmaf(xv, xv, 1.0f));
-        T.lam = rsq(nn * xx);
-    }
 }
 
-template <bool F16, bool JAC>
-__device__ __forceinline__ void pixel_terms(const LevelView& A, const LevelRay& R, int u, int v,
-                                            float Is, float Ws, bool wv, Terms& T)
-{
-    const unsigned i = __umul24(v, A.w) + u;
-    const float2 c = load_iw<F16>(A.iw, i);
-    const unsigned m = load_mask(A, i);
-    Nbrs n;
-    if constexpr (JAC) n = load_nbrs<F16>(A, i);
-    else n.l = n.r = n.t = n.b = c;
-    terms_core<JAC>(R, ray_x(R, u), ray_y(R, v), c, n, m, Is, Ws, wv, T);
-}
-
-// Robust weighting of one iteration: the channels' location, inverse scale
-// and nu, sqrt(k) and sqrt(nu + 1) for the square-rooted weights, and
-// whether a channel takes part.
-struct RobustW {
-    int kind;
-    float sqk;
-    float muI, isI, nuI, sqnuI;
-    float muW, isW, nuW, sqnuW;
+// Robust weighting of one iteration, folded for the per-pixel code.  With
+// d = r - mu and x = d / sigma, the square-rooted weight over sigma is
+//   Huber      sqrt(w) / sigma = min(1, sqrt(k / |x|)) / sigma
+//                              = min(1 / sigma, a rsqrt|d|),   a = sqrt(k / sigma);
+//   Student-t  sqrt(w) / sigma = sqrt((nu + 1) / (nu + x^2)) / sigma
+//                              = a rsqrt(d^2 + c),  a = sqrt(nu + 1), c = nu sigma^2
+// (sec. 6.3).  A channel with an empty sample takes no part.
+struct RobustF {
+    float muI, isI, aI, cI;
+    float muW, isW, aW, cW;
     bool enI, enW;
 };
 
-__device__ __forceinline__ RobustW robust_w(const IterLaunch& L, const PairState& S)
+__device__ __forceinline__ RobustF robust_f(const IterLaunch& L, const PairState& S)
 {
-    RobustW W;
-    W.kind = L.ip.weight;
-    W.sqk = sqrtf(L.ip.huber_k);
-    W.enI = S.ns[0] > 0;
-    W.enW = S.ns[1] > 0;
-    W.muI = S.mu[0];
-    W.isI = 1.0f / S.sigma[0];
-    W.muW = S.mu[1];
-    W.isW = 1.0f / S.sigma[1];
-    W.nuW = S.nu[1];
-    W.nuI = (W.kind == RGBID_W_STUDENT_T && L.ip.estimate_nu) ? fmaxf(S.nu[0], W.nuW) : S.nu[0];
-    W.sqnuI = sqrtf(W.nuI + 1.0f);
-    W.sqnuW = sqrtf(W.nuW + 1.0f);
-    return W;
+    RobustF F;
+    F.enI = S.ns[0] > 0;
+    F.enW = S.ns[1] > 0;
+    F.muI = S.mu[0];
+    F.muW = S.mu[1];
+    const float sgI = S.sigma[0], sgW = S.sigma[1];
+    F.isI = 1.0f / sgI;
+    F.isW = 1.0f / sgW;
+    if (L.ip.weight == RGBID_W_HUBER) {
+        F.aI = sqrtf(L.ip.huber_k * F.isI);
+        F.aW = sqrtf(L.ip.huber_k * F.isW);
+        F.cI = F.cW = 0.0f;
+    } else {
+        const float nuW = S.nu[1];
+        const float nuI = L.ip.estimate_nu ? fmaxf(S.nu[0], nuW) : S.nu[0];
+        F.aI = sqrtf(nuI + 1.0f);
+        F.aW = sqrtf(nuW + 1.0f);
+        F.cI = nuI * sgI * sgI;
+        F.cW = nuW * sgW * sgW;
+    }
+    return F;
 }
 
-// sqrt of the robust weight of a normalised residual x (sec. 6.3): Huber
-// min(1, sqrt(k / |x|)), Student-t sqrt(nu + 1) / sqrt(nu + x^2).
-__device__ __forceinline__ float sqrt_omega(int kind, float x, float nu, float sqk, float sqnu1)
+template <int KIND>
+__device__ __forceinline__ float sqrt_weight(float d, float is, float a, float c)
 {
-    return kind == RGBID_W_HUBER ? fminf(1.0f, sqk * rsq(fabsf(x))) : sqnu1 * rsq(fmaf(x, x, nu));
+    if constexpr (KIND == RGBID_W_HUBER) return fminf(is, a * rsq(fabsf(d)));
+    else return a * rsq(fmaf(d, d, c));
 }
 
-// The normal equations on the matrix cores.  The sums over pixels of w J J^T,
-// w J r and w r^2 (2eq:minimisationIRLS) are the upper blocks of the sum of
-// the outer products of v = sqrt(w) (J_0 .. J_5, r, 0) with themselves: rows
-// and columns 0-3 (TL), rows 0-3 x columns 4-7 (TR) and rows and columns 4-7
-// (BR).  Per tile a wave stages its 128 vectors (the I and W terms of 64
-// pixels) in LDS as two planes of float4, (v0, v4, v1, v5) and (v2, v6, v3,
-// v7), each plane in vector order (a lane's stores are consecutive 16-byte
-// words: no bank conflicts), and feeds them 16 at a time to
-// v_mfma_f32_4x4x1_16b_f32: block b takes vector 16 q + b, lane 4 b + i
-// supplying (v_i, v_4+i), and block b's 4x4 product accumulates in lanes
-// 4 b + j, register i.  Scaling uses the legacy multiply (0 x anything = 0),
-// so a term that takes no part stages exact zeros.
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-struct NeAcc {
-    v4f tl, tr, br;
-};
-
-constexpr int kStageFloat4PerWave = 256;   // 128 vectors x 8 floats
-
+// The legacy multiply: 0 x anything (inf, NaN) = 0.
 __device__ __forceinline__ float lmul(float a, float b)
 {
     float r;
@@ -674,37 +620,49 @@ __device__ __forceinline__ float lmul(float a, float b)
     return r;
 }
 
-__device__ __forceinline__ void stage_vector(float4* st, int slot, float s, const float* J, float r)
+// The normal equations (2eq:minimisationIRLS) are the sums over pixels of
+// w J J^T, w J r and w r^2: the upper blocks of the sum of the outer products
+// of v = sqrt(w) (J_0 .. J_5, r, 0) with themselves, rows and columns 0-3
+// (TL), rows 0-3 x columns 4-7 (TR) and rows and columns 4-7 (BR), a dense
+// contraction over pixels that runs on the matrix cores.  Per tile a wave
+// stages its 128 vectors (the I and W terms of 64 pixels) in LDS as two
+// planes of float4, (v0, v4, v1, v5) and (v2, v6, v3, v7), each plane in
+// vector order (a lane's stores are consecutive 16-byte words: no bank
+// conflicts), and feeds them 16 at a time to v_mfma_f32_4x4x1_16b_f32: block
+// b takes vector 16 q + b, lane 4 b + i supplying (v_i, v_4+i), and block b's
+// 4x4 product accumulates in lanes 4 b + j, register i.
+//
+// Precision: the accumulators of a group of kNeGroupTiles tiles add at most
+// 8 kNeGroupTiles terms per block in FP32; the group's 16 blocks are then
+// added in order and the result joins a compensated (hi, lo) FP32 total
+// (two-sum) per sum, in lanes 0..27; waves and chunks follow in (hi, lo)
+// pairs and FP64.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kStageFloat4PerWave = 256;   // 128 vectors x 8 floats
+constexpr int kNeGroupTiles = 8;
+
+struct NeAcc {
+    v4f tl, tr, br;   // the current group's MFMA accumulators
+    float hi, lo;     // lanes 0..27: compensated total of sum k = lane
+    int tiles;        // tiles in the current group (uniform)
+};
+
+__device__ __forceinline__ void ne_init(NeAcc& na)
 {
-    st[slot] = make_float4(lmul(s, J[0]), lmul(s, J[4]), lmul(s, J[1]), lmul(s, J[5]));
-    st[128 + slot] = make_float4(lmul(s, J[2]), lmul(s, r), lmul(s, J[3]), 0.0f);
+    na.tl = na.tr = na.br = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    na.hi = na.lo = 0.0f;
+    na.tiles = 0;
 }
 
-// One tile's terms of the 64 lanes into the accumulators; the counts of
-// contributing pixels go to the wave-uniform counters cI, cW.
-__device__ __forceinline__ void ne_add(NeAcc& na, float4* st, int lane, const Terms& T,
-                                       const RobustW& W, unsigned& cI, unsigned& cW)
+// Knuth's two-sum: hi + lo + x = hi' + lo' with the rounding error of
+// hi + x carried in lo.
+__device__ __forceinline__ void two_sum_add(float& hi, float& lo, float x)
 {
-    const bool tI = T.vI & W.enI, tW = T.vW & W.enW;
-    cI += (unsigned)__popcll(__ballot(tI));
-    cW += (unsigned)__popcll(__ballot(tW));
-    const float xI = (T.rI - W.muI) * W.isI, xW = (T.rW - W.muW) * W.isW;
-    const float sI = tI ? sqrt_omega(W.kind, xI, W.nuI, W.sqk, W.sqnuI) * W.isI : 0.0f;
-    const float sW =
-        tW ? sqrt_omega(W.kind, xW, W.nuW, W.sqk, W.sqnuW) * W.isW * __builtin_amdgcn_sqrtf(T.lam)
-           : 0.0f;
-    stage_vector(st, lane, sI, T.JI, T.rI);
-    stage_vector(st, 64 + lane, sW, T.JW, T.rW);
-    // lane 4 b + i: plane i / 2, vector b (+ 16 q), half i % 2 of the float4
-    const float2* rd = reinterpret_cast<const float2*>(st) + 256 * ((lane & 3) >> 1) +
-                       2 * (lane >> 2) + (lane & 1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float2 e = rd[32 * q];
-        na.tl = __builtin_amdgcn_mfma_f32_4x4x1f32(e.x, e.x, na.tl, 0, 0, 0);
-        na.tr = __builtin_amdgcn_mfma_f32_4x4x1f32(e.x, e.y, na.tr, 0, 0, 0);
-        na.br = __builtin_amdgcn_mfma_f32_4x4x1f32(e.y, e.y, na.br, 0, 0, 0);
-    }
+    const float s = hi + x;
+    const float bp = s - hi;
+    lo += (hi - (s - bp)) + (x - bp);
+    hi = s;
 }
 
 // Where sum k of the 28 (H upper triangle row-major, g, cost) sits in the
@@ -713,11 +671,10 @@ __device__ __forceinline__ void ne_add(NeAcc& na, float4* st, int lane, const Te
 __constant__ unsigned char kNeMap[28] = {0,  1,  2,  3,  16, 17, 5,  6,  7,  20, 21, 10, 11, 24,
                                          25, 15, 28, 29, 32, 33, 37, 18, 22, 26, 30, 34, 38, 42};
 
-// The wave's totals of the 28 sums and the two counts into out[0 .. 29]
-// (LDS), through the wave's staging area; sum k is added over the 16 blocks
-// in block order.
-__device__ __forceinline__ void ne_wave_totals(const NeAcc& na, float4* st, int lane, unsigned cI,
-                                               unsigned cW, float* out)
+// Ends a group: the 16 blocks of every sum are added in block order through
+// the wave's staging area and the result joins (hi, lo); the accumulators
+// restart from zero.
+__device__ __forceinline__ void ne_flush(NeAcc& na, float4* st, int lane)
 {
     float* sc = reinterpret_cast<float*>(st);
 #pragma unroll
@@ -730,13 +687,90 @@ __device__ __forceinline__ void ne_wave_totals(const NeAcc& na, float4* st, int 
         const unsigned c = kNeMap[lane];
         const float* src = sc + (c >> 2) * 64 + (c & 3);
         float t = 0.0f;
+#pragma unroll
         for (int b = 0; b < 16; ++b) t += src[4 * b];
-        out[lane] = t;
-    } else if (lane == 28) {
-        out[28] = (float)cI;
-    } else if (lane == 29) {
-        out[29] = (float)cW;
+        two_sum_add(na.hi, na.lo, t);
     }
+    na.tl = na.tr = na.br = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    na.tiles = 0;
+}
+
+// The staged tile of the wave into the accumulators (the staging area is
+// free again when this returns: LDS operations of a wave complete in order).
+__device__ __forceinline__ void ne_feed(NeAcc& na, float4* st, int lane)
+{
+    // lane 4 b + i: plane i / 2, vector b (+ 16 q), half i % 2 of the float4
+    const float2* rd = reinterpret_cast<const float2*>(st) + 256 * ((lane & 3) >> 1) +
+                       2 * (lane >> 2) + (lane & 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float2 e = rd[32 * q];
+        na.tl = __builtin_amdgcn_mfma_f32_4x4x1f32(e.x, e.x, na.tl, 0, 0, 0);
+        na.tr = __builtin_amdgcn_mfma_f32_4x4x1f32(e.x, e.y, na.tr, 0, 0, 0);
+        na.br = __builtin_amdgcn_mfma_f32_4x4x1f32(e.y, e.y, na.br, 0, 0, 0);
+    }
+    na.tiles = __builtin_amdgcn_readfirstlane(na.tiles + 1);
+    if (na.tiles == kNeGroupTiles) ne_flush(na, st, lane);
+}
+
+// The wave's compensated totals of the 28 sums and the two counts into
+// out[0 .. 29] (LDS, as (hi, lo) pairs).
+__device__ __forceinline__ void ne_wave_totals(NeAcc& na, float4* st, int lane, unsigned cI,
+                                               unsigned cW, float2* out)
+{
+    if (na.tiles > 0) ne_flush(na, st, lane);
+    if (lane < 28) out[lane] = make_float2(na.hi, na.lo);
+    else if (lane == 28) out[28] = make_float2((float)cI, 0.0f);
+    else if (lane == 29) out[29] = make_float2((float)cW, 0.0f);
+}
+
+// The two staged vectors of one level pixel (sec. 6.2): v_I = sqrt(w_I)
+// (J_I, r_I, 0) and v_W = sqrt(w_W) (J_W, r_W, 0), in the staging slots of
+// lane `lane`.  The Jacobians of eq:res_int / eq:res_depth are formed in the
+// ray x = (xu, xv, 1): with X = x / W_A, J = (a, X x a) = (a, x x (a / W_A)),
+//   a_I = W_A (g_u, g_v, g_3),  g_3 = -(xu g_u + xv g_v),
+//   a_W = W_A (k_u, k_v, k_3 + W*),  k_3 = -(xu k_u + xv k_v),
+// where (g_u, g_v) and (k_u, k_v) are the central differences of I_A and
+// W_A times (f_x / 2, f_y / 2) (the third entries are g (c - p) written in
+// the ray).  The square-rooted weights multiply the gradients before the
+// Jacobians are formed.  w_W carries lambda_n = 1 / (|n~| |x|) (sec. 6.2):
+// n~ = Z (k_u, k_v, k_3) + e_z with Z = 1 / W_A, so |n~| W_A = sqrt(q),
+// q = k_u^2 + k_v^2 + (k_3 + W_A)^2, and lambda_n = W_A / sqrt(q |x|^2).
+// A term that takes no part (invalid pixel, or its channel without a sample)
+// stages zeros: its weight is 0 and the legacy multiply gives 0 x anything
+// = 0.  The counts of contributing pixels go to the wave-uniform cI, cW.
+template <int KIND>
+__device__ __forceinline__ void pixel_vectors(const LevelRay& R, float xu, float xv, float2 c,
+                                              const Nbrs& n, unsigned m, float Is, float Ws,
+                                              bool wv, const RobustF& F, float4* st, int lane,
+                                              unsigned& cI, unsigned& cW)
+{
+    const bool tI = wv & ((m & 1u) != 0u) & F.enI;
+    const bool tW = wv & ((m & 2u) != 0u) & F.enW;
+    cI += (unsigned)__popcll(__ballot(tI));
+    cW += (unsigned)__popcll(__ballot(tW));
+    const float wa = c.y;
+    const float rI = Is - c.x, rW = Ws - wa;
+    float sI = sqrt_weight<KIND>(rI - F.muI, F.isI, F.aI, F.cI);
+    sI = tI ? sI : 0.0f;
+    const float k0 = (n.r.y - n.l.y) * R.hfx, k1 = (n.b.y - n.t.y) * R.hfy;
+    const float k3 = -fmaf(xu, k0, xv * k1);
+    const float e = k3 + wa;
+    const float q = fmaf(k0, k0, fmaf(k1, k1, e * e));
+    const float xx = fmaf(xu, xu, fmaf(xv, xv, 1.0f));
+    const float sl = __builtin_amdgcn_sqrtf(wa * rsq(q * xx));   // sqrt(lambda_n)
+    float sW = sqrt_weight<KIND>(rW - F.muW, F.isW, F.aW, F.cW) * sl;
+    sW = tW ? sW : 0.0f;
+    // intensity term
+    const float g0 = lmul(sI * R.hfx, n.r.x - n.l.x), g1 = lmul(sI * R.hfy, n.b.x - n.t.x);
+    const float g3 = -fmaf(xu, g0, xv * g1);
+    st[lane] = make_float4(wa * g0, fmaf(-xu, g3, g0), wa * g1, fmaf(xu, g1, -(xv * g0)));
+    st[128 + lane] = make_float4(wa * g3, lmul(sI, rI), fmaf(xv, g3, -g1), 0.0f);
+    // inverse-depth term
+    const float K0 = lmul(sW, k0), K1 = lmul(sW, k1);
+    const float KW = lmul(sW, k3) + lmul(sW, Ws);
+    st[64 + lane] = make_float4(wa * K0, fmaf(-xu, KW, K0), wa * K1, fmaf(xu, K1, -(xv * K0)));
+    st[192 + lane] = make_float4(wa * KW, lmul(sW, rW), fmaf(xv, KW, -K1), 0.0f);
 }
 
 // ------------------------------------------------------------------ k_warp
@@ -857,9 +891,7 @@ __global__ void __launch_bounds__(512) k_warp(IterLaunch L)
         if (!fused) store_f2(warped, idx, wv ? Is : 0.0f, wv ? Ws : 0.0f);
         if (cur.sidx < 0) continue;
         Terms T;
-        Nbrs none;
-        none.l = none.r = none.t = none.b = cur.c;
-        terms_core<false>(R, cur.xu, cur.xv, cur.c, none, cur.m, Is, Ws, wv, T);
+        residuals(cur.c, cur.m, Is, Ws, wv, T);
         store_f2(sample, cur.sidx, T.vI ? T.rI : __int_as_float(0x7fc00000),
                  T.vW ? T.rW : __int_as_float(0x7fc00000));
     }
@@ -1271,25 +1303,25 @@ __device__ __forceinline__ void advance(int& idx, int& u, int& v, int step, int 
     }
 }
 
-// Level pixel that is its own warp child: warp, residuals, terms.
-template <bool F16>
+// Level pixel that is its own warp child: warp, residuals, weighted
+// Jacobians into the accumulators.
+template <bool F16, int KIND>
 __device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, const RefPx& r, int n,
-                                          const RobustW& W, NeAcc& na, float4* st, int lane,
+                                          const RobustF& F, NeAcc& na, float4* st, int lane,
                                           unsigned& cI, unsigned& cW)
 {
     float Is, Ws;
     const bool wv = warp_ray<F16>(G, r.xu, r.xv, r.c.y, Is, Ws) & (r.idx < n);
-    Terms T;
-    terms_core<true>(R, r.xu, r.xv, r.c, r.nb, r.m, Is, Ws, wv, T);
-    ne_add(na, st, lane, T, W, cI, cW);
+    pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, r.m, Is, Ws, wv, F, st, lane, cI, cW);
+    ne_feed(na, st, lane);
 }
 
 // Dynamic LDS: kStageFloat4PerWave float4 per wave (the normal-equation
 // staging area).
-template <bool F16, int LOG2B, bool FUSED>
+template <bool F16, int LOG2B, bool FUSED, int KIND>
 __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
 {
-    __shared__ float lds[8 * kNSum];
+    __shared__ float2 lds[8 * kNSum];
     extern __shared__ float4 ne_stage[];
     const int ci = chunk_of_block(blockIdx.x, L.n_red_chunks, L.tune.xcd_remap);
     const Chunk ch = L.red_chunks[ci];
@@ -1301,10 +1333,10 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const LevelRay R = level_ray(A);
     const GridDim gd = level_grid(A);
     const void* const warped = D.warped;
-    const RobustW W = robust_w(L, S);
+    const RobustF F = robust_f(L, S);
 
     NeAcc na;
-    na.tl = na.tr = na.br = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    ne_init(na);
     unsigned cI = 0, cW = 0;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1328,12 +1360,12 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         while (tile < end) {
             advance(idx, u, v, step, su, sv, gd.gw);
             load_ref<F16>(A, R, gd.n, idx, u, v, rb);
-            own_pixel<F16>(G, R, ra, gd.n, W, na, st, lane, cI, cW);
+            own_pixel<F16, KIND>(G, R, ra, gd.n, F, na, st, lane, cI, cW);
             tile += waves;
             if (tile >= end) break;
             advance(idx, u, v, step, su, sv, gd.gw);
             load_ref<F16>(A, R, gd.n, idx, u, v, ra);
-            own_pixel<F16>(G, R, rb, gd.n, W, na, st, lane, cI, cW);
+            own_pixel<F16, KIND>(G, R, rb, gd.n, F, na, st, lane, cI, cW);
             tile += waves;
         }
     } else {
@@ -1352,22 +1384,23 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
                 wv = (Ws > 0.0f) & (idx < gd.n);
                 split_index(ic, gd.gw, gd.inv_gw, gd.half_inv, u, v);
             }
-            Terms T;
-            pixel_terms<F16, true>(A, R, u, v, Is, Ws, wv, T);
-            ne_add(na, st, lane, T, W, cI, cW);
+            const unsigned i = __umul24(v, A.w) + u;
+            pixel_vectors<KIND>(R, ray_x(R, u), ray_y(R, v), load_iw<F16>(A.iw, i),
+                                load_nbrs<F16>(A, i), load_mask(A, i), Is, Ws, wv, F, st, lane,
+                                cI, cW);
+            ne_feed(na, st, lane);
         }
     }
     ne_wave_totals(na, st, lane, cI, cW, lds + wave * kNSum);
     __syncthreads();
     if (threadIdx.x < kNSum) {
-        // compensated (two-sum) FP32 sum over the waves of the workgroup
+        // the waves' (hi, lo) totals in wave order: two-sum of the high parts,
+        // the low parts added
         float hi = 0.0f, lo = 0.0f;
         for (int w = 0; w < waves; ++w) {
-            const float x = lds[w * kNSum + threadIdx.x];
-            const float s = hi + x;
-            const float bp = s - hi;
-            lo += (hi - (s - bp)) + (x - bp);
-            hi = s;
+            const float2 x = lds[w * kNSum + threadIdx.x];
+            two_sum_add(hi, lo, x.x);
+            lo += x.y;
         }
         store_f2(L.partials, (size_t)ci * kNSum + threadIdx.x, hi, lo);
     }
@@ -1552,12 +1585,15 @@ hipError_t launch_iteration_t(hipStream_t s, const IterLaunch& L, hipEvent_t con
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     if ((L.kernels & 4) && L.n_red_chunks > 0) {
         const size_t lds_bytes = sizeof(float4) * kStageFloat4PerWave * L.tune.waves;
-        if (L.tune.fused)
-            hipLaunchKernelGGL((k_reduce<F16, LOG2B, true>), dim3(L.n_red_chunks), blk, lds_bytes, s,
-                               L);
-        else
-            hipLaunchKernelGGL((k_reduce<F16, LOG2B, false>), dim3(L.n_red_chunks), blk, lds_bytes,
-                               s, L);
+        const dim3 g(L.n_red_chunks);
+        constexpr int HU = RGBID_W_HUBER, ST = RGBID_W_STUDENT_T;
+        if (L.ip.weight == HU) {
+            if (L.tune.fused) hipLaunchKernelGGL((k_reduce<F16, LOG2B, true, HU>), g, blk, lds_bytes, s, L);
+            else hipLaunchKernelGGL((k_reduce<F16, LOG2B, false, HU>), g, blk, lds_bytes, s, L);
+        } else {
+            if (L.tune.fused) hipLaunchKernelGGL((k_reduce<F16, LOG2B, true, ST>), g, blk, lds_bytes, s, L);
+            else hipLaunchKernelGGL((k_reduce<F16, LOG2B, false, ST>), g, blk, lds_bytes, s, L);
+        }
     }
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
     if (L.kernels & 8) hipLaunchKernelGGL(k_solve, dim3(L.npairs), dim3(64), 0, s, L);

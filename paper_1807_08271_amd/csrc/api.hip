@@ -829,8 +829,12 @@ rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rg
         p->h[l] = cam->height >> l;
         level_camera(*cam, l, p->fx[l], p->fy[l], p->cx[l], p->cy[l]);
         const size_t np = (size_t)p->w[l] * p->h[l];
-        off[3 * l] = total;
-        total = align_up(total + np * e_iw, 256);
+        // the (I, W) plane between guards of at least one row and one texel
+        // (zeros): the alignment kernels read the neighbours of border pixels
+        // unclamped, and a bilinear tap pair may read one texel past the end
+        const size_t guard = align_up(((size_t)p->w[l] + 1) * e_iw, 256);
+        off[3 * l] = total + guard;
+        total = align_up(off[3 * l] + np * e_iw, 256) + guard;
         off[3 * l + 1] = total;
         total = align_up(total + np * e_wp, 256);
         off[3 * l + 2] = total;
@@ -845,6 +849,12 @@ rgbid_status rgbid_pyramid(rgbid_ctx* c, const rgbid_camera* cam, int levels, rg
         p->iw[l] = static_cast<char*>(p->base) + off[3 * l];
         p->wp[l] = static_cast<char*>(p->base) + off[3 * l + 1];
         p->gm[l] = static_cast<char*>(p->base) + off[3 * l + 2];
+    }
+    e = hipMemsetAsync(p->base, 0, total, c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(p->base);
+        delete p;
+        return set_err(c, RGBID_E_DEVICE, "hipMemsetAsync failed: %s", hipGetErrorString(e));
     }
     rgbid_pyr* const arr[1] = {p};
     const float* const Is[1] = {I_dev};
