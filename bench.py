@@ -75,19 +75,26 @@ FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # VALU issue: one wave64 instruction per SIMD every 4 cycles
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
-# Algorithmic FP32 flops (an FMA counts 2) the method needs, per unit:
+# FP32 matrix-core peak (MI355X, dense FP32 MFMA): 157.3 TFLOP/s.
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+# Algorithmic FP32 flops (an FMA counts 2) the method needs, per unit, on
+# the vector ALUs:
 #   a warped full-resolution child: ray and rotation 22, projection 8,
 #   bilinear weights 6 and two 4-tap interpolations 16, W* 5  -> 57;
 #   its share of the level mean (two channels)                 -> 2;
 #   a level pixel's residual terms: residuals 2, gradients 8, two Jacobians
-#   38, lambda_n 12, two robust weights 12, two rank-one updates of the
-#   21 + 6 + 1 sums (w J, then FMAs) 124                       -> 196;
-#   a sample residual pair                                      -> 2.
-FLOPS_CHILD, FLOPS_MEAN, FLOPS_TERMS, FLOPS_SAMPLE = 57, 2, 196, 2
+#   38, lambda_n 12, two robust weights 12                     -> 72;
+#   a sample residual pair                                      -> 2;
+# and on the matrix cores: a level pixel's two rank-one updates of the
+# 21 + 6 + 1 normal-equation sums (w J, then multiply-adds)     -> 124.
+FLOPS_CHILD, FLOPS_MEAN, FLOPS_TERMS, FLOPS_SAMPLE = 57, 2, 72, 2
+FLOPS_NE_MFMA = 124
 
 
 def algorithmic_flops(level, kernel, sizes, warp_fullres, fused):
-    """FP32 flops of one launch of (level, kernel) over the batch."""
+    """FP32 vector-ALU flops of one launch of (level, kernel) over the batch
+    (the normal-equation sums, which run on the matrix cores, excluded)."""
     total = 0
     for w0, h0 in sizes:
         n0 = w0 * h0
@@ -228,7 +235,17 @@ def warmstart_compare(ctx, npairs, steps):
         iters = [sum(stats[i]["iters_done"]) for i in range(m) if rstats[i]["status"] == 0]
         res[name] = {"alignments_per_s": round(m * steps / dt, 1),
                      "success_rate": round(float(np.mean(ok)), 4),
-                     "mean_gn_iters": round(float(np.mean(iters)), 2)}
+                     "mean_gn_iters": round(float(np.mean(iters)), 2),
+                     "ms_per_batch": round(1e3 * dt / steps, 4)}
+        if name == "warm":
+            # the network's share: input assembly, forward and the initial
+            # poses, on their own
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rg.rgbid_warmstart_predict(ctx, net, st.As[:m], st.Bs[:m], st.x)
+            torch.cuda.synchronize()
+            res[name]["predict_ms_per_batch"] = round(1e3 * (time.perf_counter() - t0) / steps, 4)
         log("warm-start comparison %-5s: %s" % (name, res[name]))
     st.close()
     rg.rgbid_warmstart_free(net)
@@ -603,7 +620,14 @@ def main():
     hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4)}
     alu = {"achieved": round(tflops, 2), "peak": round(FP32_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-           "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "flops_per_launch": fl}
+           "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "flops_per_launch": fl,
+           "note": "vector-ALU flops only, against the non-packed FP32 rate"}
+    if kname == "reduce":
+        mf = FLOPS_NE_MFMA * sum((w0 >> lvl) * (h0 >> lvl) for w0, h0 in sizes)
+        mt = mf / (avg_us * 1e-6) / 1e12
+        alu["mfma"] = {"achieved": round(mt, 2), "peak": MFMA_FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(mt / MFMA_FP32_PEAK_TFLOPS, 4),
+                       "flops_per_launch": mf}
     # the roof with the larger fraction binds
     top = alu if alu["frac"] > hbm["frac"] else hbm
     roofline = {"bound": "alu" if top is alu else "hbm", "kernel": "k_%s level %d" % (kname, lvl),

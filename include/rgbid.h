@@ -521,7 +521,19 @@ rgbid_status rgbid_warmstart_input(rgbid_ctx* ctx, int n, const rgbid_pyr* const
 rgbid_status rgbid_warmstart_forward(rgbid_ctx* ctx, rgbid_net* net, int n, const float* x_dev,
                                      double* xi_out);
 
-/* Input + forward + exponential: initial poses for rgbid_align_batch. */
+/* The same forward pass on the matrix cores, reading the input from the
+   80 x 60 level of each pair's pyramids: the convolutions are implicit GEMMs
+   of the bf16 weights and the FP32 activations carried as three exact bf16
+   limbs (v_mfma_f32_32x32x16_bf16, FP32 accumulation), so the result is that
+   of rgbid_warmstart_forward up to the order of FP32 additions.  Writes xi0
+   (n x 6, metres and radians) to host memory (synchronises).  Errors: E_ARG,
+   E_SHAPE (no 80 x 60 level, mixed formats), E_NOMEM, E_DEVICE. */
+rgbid_status rgbid_warmstart_forward_pyr(rgbid_ctx* ctx, rgbid_net* net, int n,
+                                         const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                                         double* xi_out);
+
+/* Matrix-core forward + exponential: initial poses for rgbid_align_batch.
+   x_scratch_dev is not used (kept for callers of the FP32 input path). */
 rgbid_status rgbid_warmstart_predict(rgbid_ctx* ctx, rgbid_net* net, int n,
                                      const rgbid_pyr* const* A, const rgbid_pyr* const* B,
                                      float* x_scratch_dev, rgbid_pose* init_out);

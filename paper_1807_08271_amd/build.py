@@ -18,7 +18,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librgbid.so")
 ARCH = os.environ.get("RGBID_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "pyramid.hip", "align.hip", "fuse.hip", "cnn.hip", "sensor.hip"]
+SOURCES = ["api.hip", "pyramid.hip", "align.hip", "fuse.hip", "cnn.hip", "cnn_mfma.hip", "sensor.hip"]
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
@@ -48,7 +48,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -46,6 +46,9 @@ struct rgbid_net {
     void* act_base;       // activations for `cap` samples
     int cap;
     int step;
+    void* inf_base;       // matrix-core inference: GEMM-order weights, limb activations, output
+    int inf_cap;
+    int wg_step;          // training step the GEMM-order weights were made at (-1: none)
 };
 
 namespace {
@@ -1685,6 +1688,74 @@ rgbid_status net_loss(rgbid_ctx* c, rgbid_net* net, int n, double* loss)
     return RGBID_OK;
 }
 
+// The inference buffers for n samples: GEMM-order weights, then the limb
+// activations, then the n x 6 output.
+size_t net_wg_elems()
+{
+    size_t e = 0;
+    for (int l = 0; l < 4; ++l) e += (size_t)kCnnCh[l + 1] * cnn_gemm_k(l);
+    return e;
+}
+
+rgbid_status net_infer_reserve(rgbid_ctx* c, rgbid_net* net, int n)
+{
+    if (n <= net->inf_cap) return RGBID_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (net->inf_base) HIPCHK(c, hipFree(net->inf_base));
+    net->inf_base = nullptr;
+    net->inf_cap = 0;
+    net->wg_step = -1;
+    const int cap = std::max(n, 64);
+    const size_t total = align_up(net_wg_elems() * 2, 256) + align_up(cnn_limb_bytes(cap), 256) +
+                         align_up((size_t)cap * 6 * 4, 256);
+    HIPCHK(c, hipMalloc(&net->inf_base, total));
+    net->inf_cap = cap;
+    return RGBID_OK;
+}
+
+// Normalised outputs of the matrix-core forward for pairs (A[i], B[i]) in
+// device memory (n x 6 floats); enqueued, not synchronised.
+rgbid_status net_forward_pyr(rgbid_ctx* c, rgbid_net* net, int n, const rgbid_pyr* const* A,
+                             const rgbid_pyr* const* B, float** out_dev)
+{
+    rgbid_status st;
+    if ((st = net_infer_reserve(c, net, n)) != RGBID_OK) return st;
+    char* ib = static_cast<char*>(net->inf_base);
+    unsigned short* wg = reinterpret_cast<unsigned short*>(ib);
+    unsigned short* limbs = reinterpret_cast<unsigned short*>(ib + align_up(net_wg_elems() * 2, 256));
+    float* out = reinterpret_cast<float*>(ib + align_up(net_wg_elems() * 2, 256) +
+                                          align_up(cnn_limb_bytes(net->inf_cap), 256));
+    if (net->wg_step != net->step) {
+        HIPCHK(c, cnn_gemm_weights(c->stream, net->buf, wg));
+        net->wg_step = net->step;
+    }
+    if ((st = ensure(c, c->frames, std::max(n * sizeof(CnnInput), sizeof(PyrFrame)))) != RGBID_OK)
+        return st;
+    char* stage;
+    if ((st = stage_begin(c, n * sizeof(CnnInput), &stage)) != RGBID_OK) return st;
+    CnnInput* in = reinterpret_cast<CnnInput*>(stage);
+    for (int i = 0; i < n; ++i) {
+        if (!A[i] || !B[i]) return set_err(c, RGBID_E_ARG, "NULL pyramid %d", i);
+        int la = -1, lb = -1;
+        for (int l = 0; l < A[i]->levels; ++l)
+            if (A[i]->w[l] == kCnnW && A[i]->h[l] == kCnnH) la = l;
+        for (int l = 0; l < B[i]->levels; ++l)
+            if (B[i]->w[l] == kCnnW && B[i]->h[l] == kCnnH) lb = l;
+        if (la < 0 || lb < 0) return set_err(c, RGBID_E_SHAPE, "pair %d has no 80x60 level", i);
+        if (B[i]->f16 != A[i]->f16) return set_err(c, RGBID_E_SHAPE, "pair %d mixes formats", i);
+        in[i].A = A[i]->iw[la];
+        in[i].B = B[i]->iw[lb];
+        in[i].f16 = A[i]->f16;
+        in[i].pad = 0;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->frames.p, in, n * sizeof(CnnInput), hipMemcpyHostToDevice, c->stream));
+    if ((st = stage_end(c)) != RGBID_OK) return st;
+    HIPCHK(c, cnn_forward_mfma(c->stream, net->buf, wg, static_cast<const CnnInput*>(c->frames.p),
+                               n, limbs, out));
+    *out_dev = out;
+    return RGBID_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1723,6 +1794,7 @@ rgbid_status rgbid_warmstart_create(rgbid_ctx* c, const float* params, rgbid_net
     rgbid_net* net = new (std::nothrow) rgbid_net();
     if (!net) return set_err(c, RGBID_E_NOMEM, "host allocation failed");
     net->device = c->device;
+    net->wg_step = -1;
     const size_t P = kCnnParams, f = align_up(P * 4, 256);
     const size_t total = 5 * f + align_up(P * 2, 256);
     hipError_t e = hipMalloc(&net->base, total);
@@ -1759,6 +1831,7 @@ void rgbid_warmstart_free(rgbid_net* net)
     (void)hipSetDevice(net->device);
     (void)hipDeviceSynchronize();
     if (net->act_base) (void)hipFree(net->act_base);
+    if (net->inf_base) (void)hipFree(net->inf_base);
     (void)hipFree(net->base);
     delete net;
 }
@@ -1822,16 +1895,36 @@ rgbid_status rgbid_warmstart_forward(rgbid_ctx* c, rgbid_net* net, int n, const 
     return RGBID_OK;
 }
 
+rgbid_status rgbid_warmstart_forward_pyr(rgbid_ctx* c, rgbid_net* net, int n,
+                                         const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                                         double* xi_out)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!net || n < 1 || !A || !B || !xi_out) return set_err(c, RGBID_E_ARG, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    float* out = nullptr;
+    if ((st = net_forward_pyr(c, net, n, A, B, &out)) != RGBID_OK) return st;
+    if ((st = ensure_down(c, (size_t)n * 6 * sizeof(float))) != RGBID_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->h_down, out, (size_t)n * 6 * sizeof(float), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const float* o = static_cast<const float*>(c->h_down);
+    for (int i = 0; i < n * 6; ++i) xi_out[i] = (double)o[i] * kXiScale[i % 6];
+    return RGBID_OK;
+}
+
 rgbid_status rgbid_warmstart_predict(rgbid_ctx* c, rgbid_net* net, int n,
                                      const rgbid_pyr* const* A, const rgbid_pyr* const* B,
                                      float* x_scratch, rgbid_pose* init_out)
 {
+    (void)x_scratch;   // the matrix-core path reads the pyramids itself
     if (!c) return RGBID_E_ARG;
     if (!init_out) return set_err(c, RGBID_E_ARG, "NULL output");
-    rgbid_status st;
-    if ((st = rgbid_warmstart_input(c, n, A, B, x_scratch)) != RGBID_OK) return st;
+    if (n < 1) return set_err(c, RGBID_E_ARG, "bad arguments");
     std::vector<double> xi((size_t)n * 6);
-    if ((st = rgbid_warmstart_forward(c, net, n, x_scratch, xi.data())) != RGBID_OK) return st;
+    rgbid_status st;
+    if ((st = rgbid_warmstart_forward_pyr(c, net, n, A, B, xi.data())) != RGBID_OK) return st;
     for (int i = 0; i < n; ++i) rgbid_pose_exp(&xi[6 * i], &init_out[i]);
     return RGBID_OK;
 }

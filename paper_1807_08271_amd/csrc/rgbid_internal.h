@@ -302,4 +302,16 @@ hipError_t cnn_backward(hipStream_t s, const CnnBuffers& B, int N, const float* 
 hipError_t cnn_adamw(hipStream_t s, const CnnBuffers& B, float lr, float wd, int step);
 hipError_t cnn_refresh_bf16(hipStream_t s, const CnnBuffers& B);
 
+// Inference forward on the matrix cores (cnn_mfma.hip): the input assembled
+// from the pyramids' 80x60 level and the four convolutions as implicit GEMMs
+// of bf16 weights and three-limb bf16 activations with FP32 accumulation;
+// writes the normalised output (N x 6) to `out`.  wg holds the weights in
+// GEMM order (cnn_gemm_weights, sum over layers of Co x cnn_gemm_k(l)
+// elements); limbs holds cnn_limb_bytes(N) bytes.
+int cnn_gemm_k(int layer);
+size_t cnn_limb_bytes(int N);
+hipError_t cnn_gemm_weights(hipStream_t s, const CnnBuffers& B, unsigned short* wg);
+hipError_t cnn_forward_mfma(hipStream_t s, const CnnBuffers& B, const unsigned short* wg,
+                            const CnnInput* in_dev, int N, unsigned short* limbs, float* out);
+
 }  // namespace rgbid

@@ -158,6 +158,8 @@ _SIGS = {
     "rgbid_warmstart_forward": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double)]),
     "rgbid_warmstart_predict": (C.c_int, [_P, _P, C.c_int, C.POINTER(_P), C.POINTER(_P), _P,
                                           C.POINTER(rgbid_pose)]),
+    "rgbid_warmstart_forward_pyr": (C.c_int, [_P, _P, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                              C.POINTER(C.c_double)]),
     "rgbid_warmstart_gradient": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double),
                                            C.POINTER(C.c_double), C.POINTER(C.c_float)]),
     "rgbid_warmstart_train_step": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double), C.c_double,
@@ -568,6 +570,17 @@ def rgbid_warmstart_forward(ctx, net, x, n):
     xi = np.zeros(n * 6)
     _check(ctx, lib().rgbid_warmstart_forward(ctx, net, int(n), _dev(x, n),
                                               xi.ctypes.data_as(C.POINTER(C.c_double))))
+    return xi.reshape(n, 6)
+
+
+def rgbid_warmstart_forward_pyr(ctx, net, As, Bs):
+    """Matrix-core forward from the pyramids' 80x60 level: xi0 (n x 6)."""
+    n = len(As)
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    xi = np.zeros(n * 6)
+    _check(ctx, lib().rgbid_warmstart_forward_pyr(ctx, net, n, a, b,
+                                                  xi.ctypes.data_as(C.POINTER(C.c_double))))
     return xi.reshape(n, 6)
 
 

@@ -400,6 +400,53 @@ def test_degenerate_all_holes(ctx):
     rg.rgbid_pyramid_free(A)
 
 
+def test_degenerate_constant_image(ctx):
+    # Constant intensity and inverse depth (sec. 6.2): no intensity gradient
+    # and a plane without structure leave the 6x6 normal equations singular;
+    # both sides stop on the first iteration, keep the initial pose and
+    # report the degenerate system.
+    rg = _rg()
+    import torch
+    cam = (96, 72, 80.0, 80.0, 47.5, 35.5)
+    I = torch.full((72, 96), 128.0, device="cuda")
+    W = torch.full((72, 96), 0.5, device="cuda")
+    A = rg.rgbid_pyramid(ctx, cam, 2, 0, I, W)
+    R, t, st, rc = rg.rgbid_align(ctx, A, A, _params(2, [3, 3]))
+    Ro, to, so = oracle.align(cam, I.cpu().numpy(), W.cpu().numpy(), I.cpu().numpy(),
+                              W.cpu().numpy(), _oparams(2, [3, 3]))
+    assert rc == rg.RGBID_E_DEGENERATE and st["status"] == rg.RGBID_E_DEGENERATE
+    assert so["status"] == rg.RGBID_E_DEGENERATE
+    np.testing.assert_array_equal(R, np.eye(3))
+    np.testing.assert_array_equal(t, np.zeros(3))
+    np.testing.assert_array_equal(Ro, np.eye(3))
+    np.testing.assert_array_equal(to, np.zeros(3))
+    rg.rgbid_pyramid_free(A)
+
+
+def test_degenerate_out_of_view_pose(ctx, c1_pairs):
+    # An initial pose that transfers every pixel of A out of B's image (or
+    # behind the camera): no residual is defined, so the first linearisation
+    # has fewer than 6 valid residuals; both sides stop, keep the initial
+    # pose and report the degenerate system.
+    rg = _rg()
+    p = c1_pairs[0]
+    A = _pyr(ctx, p.cam, 2, p.A)
+    B = _pyr(ctx, p.cam, 2, p.B)
+    R0, t0 = np.eye(3), np.array([40.0, 0.0, 0.0])
+    R, t, st, rc = rg.rgbid_align(ctx, A, B, _params(2, [3, 3]), init=(R0, t0))
+    Ro, to, so = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, _oparams(2, [3, 3]),
+                              R0=R0, t0=t0)
+    assert rc == rg.RGBID_E_DEGENERATE and st["status"] == rg.RGBID_E_DEGENERATE
+    assert so["status"] == rg.RGBID_E_DEGENERATE
+    assert st["n_valid_I"] == 0 and st["n_valid_W"] == 0
+    np.testing.assert_array_equal(R, R0)
+    np.testing.assert_array_equal(t, t0)
+    np.testing.assert_array_equal(Ro, R0)
+    np.testing.assert_array_equal(to, t0)
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
 def test_ragged_size_and_small_sample(ctx):
     # 157x113: odd sizes (floor at every level), tiles with a ragged tail, and a
     # sample of at most 1000 pixels (stride 5 at level 0).

@@ -4,10 +4,17 @@ whole fused path from raw depth to a registered inverse-depth map, at
 640x480 on rendered room frames.
 
 The kernels decide sample bounds, tap validity, footprint coverage and the
-nearest neighbour in FP32; the oracle in FP64.  Where such a decision flips
-the value may legitimately differ by the local gradient, so each comparison
-states the share of pixels that must agree to the FP32 tolerance (intensity
-5e-3 grey levels, inverse depth 1e-5 relative) and bounds the rest."""
+nearest neighbour in FP32; the oracle in FP64.  Each comparison states the
+share of pixels that must agree to the FP32 tolerance (intensity 5e-3 grey
+levels, inverse depth 1e-5 relative) and bounds every other pixel: a hole
+decision of a sampler may flip only on a hole edge (the pixel's 3x3
+neighbourhood in the oracle's output holds both holes and values) or at
+the image border; a footprint decision of the forward registration may open
+or fill a one-pixel crack, whose value then lies within the other side's
+values around it; and a value may differ only by a stated fraction of the
+oracle's local contrast (the 3x3 range): 1e-2 for a bilinear sample whose
+position FP32 places ~1e-4 px off, the whole range for a footprint or
+nearest-neighbour decision that moves a value by one pixel."""
 import numpy as np
 import pytest
 from scipy.spatial.transform import Rotation
@@ -35,15 +42,63 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def _agree(got, want, rel=None, abs_=None, share=0.995):
+def _win(a):
+    """The 3x3 neighbourhoods of every pixel (edge-replicated), stacked."""
+    h, w = a.shape
+    p = np.pad(a, 1, mode="edge")
+    return np.stack([p[1 + dv:1 + dv + h, 1 + du:1 + du + w] for dv in (-1, 0, 1)
+                     for du in (-1, 0, 1)])
+
+
+def _nz_range(a):
+    """min and max of the non-zero values of each 3x3 neighbourhood (+inf /
+    -inf where there are none)."""
+    win = _win(a)
+    nz = win != 0
+    return np.where(nz, win, np.inf).min(0), np.where(nz, win, -np.inf).max(0)
+
+
+def _agree(got, want, rel=None, abs_=None, share=0.995, contrast=1e-2, splat=False):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    h, w = want.shape
+    tol = rel * np.abs(want) if rel is not None else np.full_like(want, abs_)
+    flip = (got != 0) != (want != 0)
+    assert flip.mean() <= 1 - share, flip.mean()
+    if splat:
+        # a footprint decision taken the other way opens or fills a one-pixel
+        # crack: the value present on one side lies within the range of the
+        # other side's values around it, or that side has a hole beside it
+        # (a hole decision of the sampler before the splat)
+        tl = tol.max()
+        lo_w, hi_w = _nz_range(want)
+        lo_g, hi_g = _nz_range(got)
+        a = flip & (got != 0)
+        b = flip & (want != 0)
+        # (the pixel itself is non-zero on that side, so a zero in its 3x3
+        # window is a neighbouring hole)
+        ok_a = ((got >= lo_w - tl) & (got <= hi_w + tl)) | _win(got == 0).any(0)
+        ok_b = ((want >= lo_g - tl) & (want <= hi_g + tl)) | _win(want == 0).any(0)
+        assert np.all(ok_a[a]) and np.all(ok_b[b]), (np.argwhere(a & ~ok_a)[:10],
+                                                      np.argwhere(b & ~ok_b)[:10])
+    else:
+        # a hole decision of a sampler flips only on a hole edge or the border
+        hole = _win(want == 0)
+        border = np.zeros((h, w), dtype=bool)
+        border[:2, :] = border[-2:, :] = border[:, :2] = border[:, -2:] = True
+        on_edge = (hole.any(0) & ~hole.all(0)) | border
+        assert np.all(on_edge[flip]), np.argwhere(flip & ~on_edge)[:10]
     both = (got != 0) & (want != 0)
-    mask_flip = np.mean((got != 0) != (want != 0))
-    assert mask_flip <= 1 - share, mask_flip
-    d = np.abs(got[both] - want[both])
-    tol = (rel * np.abs(want[both])) if rel is not None else abs_
+    d = np.abs(got - want)
     ok = d <= tol
-    assert ok.mean() >= share, (ok.mean(), d.max())
-    return ok.mean(), mask_flip
+    assert ok[both].mean() >= share, (ok[both].mean(), d[both].max())
+    win = _win(want)
+    rng = win.max(0) - win.min(0)
+    rest = both & ~ok
+    bound = tol + contrast * rng
+    assert np.all(d[rest] <= bound[rest]), (np.max(d[rest] / np.maximum(rng[rest], 1e-30)),
+                                            np.argwhere(rest & (d > bound))[:10])
+    return ok[both].mean(), flip.mean()
 
 
 def test_undistort_matches_oracle(ctx):
@@ -73,7 +128,7 @@ def test_register_matches_oracle(ctx, motion):
     camB = synth.Camera(640, 480, 520.0, 522.0, 321.0, 238.0)
     got = rg.rgbid_register(ctx, cam, _t(W), camB, (R, t)).cpu().numpy()
     want = oracle.register(cam, W, camB, R, t)
-    _agree(got, want, rel=1e-5, share=0.995)
+    _agree(got, want, rel=1e-5, share=0.995, contrast=1.0, splat=True)
 
 
 def test_register_identity_is_a_copy(ctx):
@@ -100,7 +155,7 @@ def test_preprocess_matches_oracle(ctx):
     so = oracle.Sensor(color=cam.as_tuple(), depth=depth.as_tuple(), R_dc=R_dc, t_dc=t_dc, **kw)
     oI, oW = oracle.preprocess(so, I.astype(np.float32), Z.astype(np.float32))
     _agree(gI, oI, abs_=5e-3, share=0.999)
-    _agree(gW, oW, rel=1e-5, share=0.99)
+    _agree(gW, oW, rel=1e-5, share=0.99, contrast=1.0, splat=True)
     assert (gW > 0).mean() > 0.7
 
 

@@ -82,7 +82,19 @@ def test_tracker_matches_oracle(ctx):
         valid = otrk.Wkf > 0
         assert np.array_equal(valid, Wg > 0)
         rel = np.abs(Wg[valid] - otrk.Wkf[valid]) / otrk.Wkf[valid]
-        assert np.median(rel) <= 1e-6 and np.mean(rel > 1e-4) <= 0.01, (np.median(rel), rel.max())
+        assert np.median(rel) <= 1e-6, (np.median(rel), rel.max())
+        # every pixel: the poses the fusion used agree to 1e-5 rad / m, which
+        # moves a transferred sample by at most ~5e-3 px (f = 525 px), so W
+        # may differ by that share of the keyframe's local contrast (3x3
+        # range, 2e-2 allowed) on top of 1e-4 relative
+        Wo = otrk.Wkf
+        p = np.pad(Wo, 1, mode="edge")
+        win = np.stack([p[1 + dv:1 + dv + h, 1 + du:1 + du + w] for dv in (-1, 0, 1)
+                        for du in (-1, 0, 1)])
+        bound = 1e-4 * Wo + 2e-2 * (win.max(0) - win.min(0))
+        dW = np.abs(Wg - Wo)
+        assert np.all(dW[valid] <= bound[valid]), (np.max((dW - bound)[valid]),
+                                                   np.argwhere(valid & (dW > bound))[:10])
         assert np.mean(np.abs(Cg[valid] - otrk.Ckf[valid]) > 1e-3 * otrk.Ckf[valid]) <= 0.01
     rg.rgbid_tracker_free(trk)
 

@@ -73,6 +73,32 @@ def test_forward_loss_and_gradients_match_oracle(ctx, batch):
     rg.rgbid_warmstart_free(net)
 
 
+def test_matrix_core_forward_matches_oracle(ctx, batch):
+    # The inference forward on the matrix cores (implicit-GEMM convolutions
+    # of bf16 weights and three-limb bf16 activations, FP32 accumulation)
+    # reads the pyramids itself and must give the FP32 forward's result: the
+    # oracle's within the same 1e-5 / 1e-6, and the FP32 kernels' within FP32
+    # summation-order differences.  Then a few training steps later (the
+    # GEMM-order weights follow the updated parameters).
+    rg = _rg()
+    params = cnn.init_params(11)
+    net = rg.rgbid_warmstart_create(ctx, params)
+    for step in range(2):
+        eff = cnn.effective_params(rg.rgbid_warmstart_get_params(ctx, net))
+        out_r, _ = cnn.forward(eff, batch["xr"])
+        xi_m = rg.rgbid_warmstart_forward_pyr(ctx, net, batch["As"], batch["Bs"])
+        xi_f = rg.rgbid_warmstart_forward(ctx, net, batch["x"], batch["n"])
+        np.testing.assert_allclose(xi_m, out_r * cnn.SCALE, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(xi_m, xi_f, rtol=1e-5, atol=1e-6)
+        poses = rg.rgbid_warmstart_predict(ctx, net, batch["As"], batch["Bs"], batch["x"])
+        for i, (R, t) in enumerate(poses):
+            np.testing.assert_allclose(t, xi_m[i, :3], rtol=0, atol=0)
+            np.testing.assert_allclose(oracle.log_so3(R), xi_m[i, 3:], atol=1e-12)
+        for _ in range(3):
+            rg.rgbid_warmstart_train_step(ctx, net, batch["x"], batch["labels"], lr=1e-3)
+    rg.rgbid_warmstart_free(net)
+
+
 def test_adamw_step_matches_oracle(ctx, batch):
     rg = _rg()
     params = cnn.init_params(8)
