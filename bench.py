@@ -220,9 +220,9 @@ def warmstart_compare(ctx, npairs, steps):
     res = {}
     for name in ("plain", "warm"):
         def run():
-            inits = rg.rgbid_warmstart_predict(ctx, net, st.As[:m], st.Bs[:m], st.x) \
-                if name == "warm" else None
-            return rg.rgbid_align_batch(ctx, st.As[:m], st.Bs[:m], prm, inits=inits)
+            if name == "warm":   # network, initial poses and alignment in one call
+                return rg.rgbid_align_batch_warm(ctx, net, st.As[:m], st.Bs[:m], prm)
+            return rg.rgbid_align_batch(ctx, st.As[:m], st.Bs[:m], prm)
         poses, stats = run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

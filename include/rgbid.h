@@ -538,6 +538,17 @@ rgbid_status rgbid_warmstart_predict(rgbid_ctx* ctx, rgbid_net* net, int n,
                                      const rgbid_pyr* const* A, const rgbid_pyr* const* B,
                                      float* x_scratch_dev, rgbid_pose* init_out);
 
+/* The warm-started batch alignment without a host round trip: the matrix-core
+   forward of rgbid_warmstart_forward_pyr, the initial poses T0 = (exp(theta),
+   v) formed on the device from its output, then rgbid_align_batch from T0.
+   Same outputs and errors as rgbid_align_batch; the poses equal those of
+   rgbid_warmstart_predict followed by rgbid_align_batch up to the last bits
+   of the initial poses (device versus host FP64 sin / cos).  Synchronises. */
+rgbid_status rgbid_align_batch_warm(rgbid_ctx* ctx, rgbid_net* net, int n,
+                                    const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                                    const rgbid_align_params* params, rgbid_pose* out,
+                                    rgbid_align_stats* stats);
+
 /* Loss (mean over the batch of the squared normalised twist error) and its
    gradient w.r.t. every parameter for labels xi (n x 6, host), without an
    update.  grad_host: rgbid_warmstart_param_count() floats or NULL.

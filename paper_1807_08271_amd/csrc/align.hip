@@ -1701,6 +1701,52 @@ hipError_t launch_noalloc_setup(hipStream_t s, const NoAllocSetup& a)
     return hipGetLastError();
 }
 
+namespace {
+
+struct Scale6 {
+    double s[6];
+};
+
+// R = I + a [th]x + b [th]x^2, a = sin|th| / |th|, b = (1 - cos|th|) / |th|^2
+// (a = 1, b = 1/2 below |th| = 1e-8), t = v.
+__global__ void __launch_bounds__(64) k_init_from_twist(PairState* __restrict__ states, int n,
+                                                        const float* __restrict__ o, Scale6 sc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double xi[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) xi[k] = (double)o[6 * i + k] * sc.s[k];
+    const double* th = xi + 3;
+    const double nn = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    const double S[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+    const double a = nn < 1e-8 ? 1.0 : sin(nn) / nn;
+    const double b = nn < 1e-8 ? 0.5 : (1.0 - cos(nn)) / (nn * nn);
+    PairState& st = states[i];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s2 = 0.0;
+            for (int k = 0; k < 3; ++k) s2 += S[3 * r + k] * S[3 * k + c];
+            st.R[3 * r + c] = (r == c ? 1.0 : 0.0) + a * S[3 * r + c] + b * s2;
+        }
+    for (int k = 0; k < 3; ++k) st.t[k] = xi[k];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) st.RT[3 * r + c] = (float)st.R[3 * c + r];
+        st.Rtt[r] = (float)(st.R[r] * st.t[0] + st.R[3 + r] * st.t[1] + st.R[6 + r] * st.t[2]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_init_from_twist(hipStream_t s, PairState* states, int n, const float* o,
+                                  const double scale[6])
+{
+    Scale6 sc;
+    for (int k = 0; k < 6; ++k) sc.s[k] = scale[k];
+    hipLaunchKernelGGL(k_init_from_twist, dim3((n + 63) / 64), dim3(64), 0, s, states, n, o, sc);
+    return hipGetLastError();
+}
+
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs)
 {
     hipLaunchKernelGGL(k_level_start, dim3((npairs + 63) / 64), dim3(64), 0, s, states, npairs);

@@ -175,6 +175,9 @@ rgbid_status ensure_down(rgbid_ctx* c, size_t bytes)
     return RGBID_OK;
 }
 
+// Scale of the warm-start network's normalised output: (0.15 m) x 3, (0.1745 rad) x 3.
+const double kXiScale[6] = {0.15, 0.15, 0.15, 0.1745, 0.1745, 0.1745};
+
 // Smallest stride s >= 1 whose sample grid ceil(w/s) x ceil(h/s) has at most
 // nmax pixels (systematic sample of maximum size N, sec. 6.3).
 int sample_stride(int w, int h, int nmax)
@@ -312,7 +315,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                        const rgbid_pose* init, const rgbid_align_params* P,
                        const std::vector<Step>& sched, int update, rgbid_pose* out,
                        rgbid_align_stats* stats, float* launch_ms = nullptr,
-                       bool device_out = false)
+                       bool device_out = false, const float* init_twist_dev = nullptr)
 {
     if (!c) return RGBID_E_ARG;
     if (n < 1 || !A || !B) return set_err(c, RGBID_E_ARG, "need n >= 1 and pyramid arrays");
@@ -478,6 +481,9 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
         }
     HIPCHK(c, hipMemcpyAsync(c->pairs.p, pd, pairs_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->states.p, ps, states_bytes, hipMemcpyHostToDevice, c->stream));
+    if (init_twist_dev)
+        HIPCHK(c, launch_init_from_twist(c->stream, static_cast<PairState*>(c->states.p), n,
+                                         init_twist_dev, kXiScale));
     HIPCHK(c, hipMemcpyAsync(c->tables.p, tb, tbytes, hipMemcpyHostToDevice, c->stream));
     if ((st = stage_end(c)) != RGBID_OK) return st;
 
@@ -1629,8 +1635,6 @@ void rot_exp(const double th[3], double R[9])
     for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + a * S[i] + b * S2[i];
 }
 
-const double kXiScale[6] = {0.15, 0.15, 0.15, 0.1745, 0.1745, 0.1745};
-
 rgbid_status net_reserve(rgbid_ctx* c, rgbid_net* net, int n)
 {
     if (n <= net->cap) return RGBID_OK;
@@ -1927,6 +1931,26 @@ rgbid_status rgbid_warmstart_predict(rgbid_ctx* c, rgbid_net* net, int n,
     if ((st = rgbid_warmstart_forward_pyr(c, net, n, A, B, xi.data())) != RGBID_OK) return st;
     for (int i = 0; i < n; ++i) rgbid_pose_exp(&xi[6 * i], &init_out[i]);
     return RGBID_OK;
+}
+
+rgbid_status rgbid_align_batch_warm(rgbid_ctx* c, rgbid_net* net, int n,
+                                    const rgbid_pyr* const* A, const rgbid_pyr* const* B,
+                                    const rgbid_align_params* P, rgbid_pose* out,
+                                    rgbid_align_stats* stats)
+{
+    if (!c) return RGBID_E_ARG;
+    if (!net || !out) return set_err(c, RGBID_E_ARG, "NULL network or output");
+    std::string why;
+    if (!params_ok(P, why)) return set_err(c, RGBID_E_ARG, "%s", why.c_str());
+    if (n < 1 || !A || !B) return set_err(c, RGBID_E_ARG, "need n >= 1 and pyramid arrays");
+    HIPCHK(c, hipSetDevice(c->device));
+    rgbid_status st;
+    float* twist = nullptr;
+    if ((st = net_forward_pyr(c, net, n, A, B, &twist)) != RGBID_OK) return st;
+    std::vector<Step> sched;
+    for (int l = P->levels - 1; l >= 0; --l)
+        if (P->iters[l] > 0) sched.push_back(Step{l, P->iters[l]});
+    return run_batch(c, n, A, B, nullptr, P, sched, 1, out, stats, nullptr, false, twist);
 }
 
 rgbid_status rgbid_warmstart_gradient(rgbid_ctx* c, rgbid_net* net, int n, const float* x_dev,

@@ -138,6 +138,11 @@ struct IterLaunch {
 // the four kernels (for per-kernel timing).
 hipError_t launch_iteration(hipStream_t s, const IterLaunch& L, hipEvent_t const* ev);
 hipError_t launch_level_start(hipStream_t s, PairState* states, int npairs);
+// Initial poses of n pairs from normalised twists o (n x 6, device): xi =
+// o * scale, T = (exp(theta), v), written into the states (pose, its FP32
+// copies); the rest of each state is left as uploaded.
+hipError_t launch_init_from_twist(hipStream_t s, PairState* states, int n, const float* o,
+                                  const double scale[6]);
 hipError_t launch_export(hipStream_t s, const PairState* states, int n, rgbid_pose* out,
                          rgbid_align_stats* stats);
 

@@ -160,6 +160,9 @@ _SIGS = {
                                           C.POINTER(rgbid_pose)]),
     "rgbid_warmstart_forward_pyr": (C.c_int, [_P, _P, C.c_int, C.POINTER(_P), C.POINTER(_P),
                                               C.POINTER(C.c_double)]),
+    "rgbid_align_batch_warm": (C.c_int, [_P, _P, C.c_int, C.POINTER(_P), C.POINTER(_P),
+                                         C.POINTER(rgbid_align_params), C.POINTER(rgbid_pose),
+                                         C.POINTER(rgbid_align_stats)]),
     "rgbid_warmstart_gradient": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double),
                                            C.POINTER(C.c_double), C.POINTER(C.c_float)]),
     "rgbid_warmstart_train_step": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(C.c_double), C.c_double,
@@ -582,6 +585,18 @@ def rgbid_warmstart_forward_pyr(ctx, net, As, Bs):
     _check(ctx, lib().rgbid_warmstart_forward_pyr(ctx, net, n, a, b,
                                                   xi.ctypes.data_as(C.POINTER(C.c_double))))
     return xi.reshape(n, 6)
+
+
+def rgbid_align_batch_warm(ctx, net, As, Bs, params: rgbid_align_params):
+    """Warm-started batch alignment, initial poses formed on the device;
+    returns (list of (R, t), list of stats dicts)."""
+    n = len(As)
+    a = (C.c_void_p * n)(*[p.value for p in As])
+    b = (C.c_void_p * n)(*[p.value for p in Bs])
+    out = (rgbid_pose * n)()
+    st = (rgbid_align_stats * n)()
+    _check(ctx, lib().rgbid_align_batch_warm(ctx, net, n, a, b, C.byref(params), out, st))
+    return [pose_tuple(out[i]) for i in range(n)], [st[i].as_dict() for i in range(n)]
 
 
 def rgbid_warmstart_predict(ctx, net, As, Bs, x_scratch):

@@ -99,6 +99,25 @@ def test_matrix_core_forward_matches_oracle(ctx, batch):
     rg.rgbid_warmstart_free(net)
 
 
+def test_align_batch_warm_matches_predict_then_align(ctx, batch):
+    # The one-call warm start (initial poses formed on the device) against
+    # predict + rgbid_align_batch: the same initial poses up to the last bits
+    # of FP64 sin / cos, so the same converged poses within 1e-9, and the
+    # same statuses.
+    rg = _rg()
+    from paper_1807_08271_amd import warmstart as ws
+    net = rg.rgbid_warmstart_create(ctx, ws.load_weights())
+    prm = rg.rgbid_default_params(levels=4, iters=[10] * 4)   # fixed schedule
+    inits = rg.rgbid_warmstart_predict(ctx, net, batch["As"], batch["Bs"], batch["x"])
+    p1, s1 = rg.rgbid_align_batch(ctx, batch["As"], batch["Bs"], prm, inits=inits)
+    p2, s2 = rg.rgbid_align_batch_warm(ctx, net, batch["As"], batch["Bs"], prm)
+    for i in range(batch["n"]):
+        assert s1[i]["status"] == s2[i]["status"], i
+        np.testing.assert_allclose(p2[i][0], p1[i][0], atol=1e-9)
+        np.testing.assert_allclose(p2[i][1], p1[i][1], atol=1e-9)
+    rg.rgbid_warmstart_free(net)
+
+
 def test_adamw_step_matches_oracle(ctx, batch):
     rg = _rg()
     params = cnn.init_params(8)

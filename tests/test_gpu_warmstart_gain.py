@@ -25,3 +25,39 @@ def test_warm_start_gain(ctx):
     assert warm["pairs"] >= 100
     assert warm["success_rate"] >= plain["success_rate"]
     assert warm["mean_gn_iters"] < plain["mean_gn_iters"]
+
+
+def test_success_reference_is_the_oracles():
+    # The reference a warm-start "success" is judged against (bench.py,
+    # warmstart.evaluate) is the library's Gauss-Newton started at the true
+    # pose (label schedule, 4 levels x 5 iterations).  On held-out pairs it
+    # equals the oracle's Gauss-Newton from the true pose within the parity
+    # bar, so success is judged against the method's own optimum.
+    import numpy as np
+    import torch
+    import oracle
+    from synth import batch
+    from paper_1807_08271_amd import rgbid as rg
+    from paper_1807_08271_amd import warmstart as ws
+    ctx = rg.rgbid_create(0)
+    try:
+        IA, WA, IB, WB, truth = batch.warm_pairs(0, 3, "eval")
+        import synth
+        cam = synth.camera_640()
+        As = [rg.rgbid_pyramid(ctx, cam, 4, rg.RGBID_F32, IA[i], WA[i]) for i in range(3)]
+        Bs = [rg.rgbid_pyramid(ctx, cam, 4, rg.RGBID_F32, IB[i], WB[i]) for i in range(3)]
+        ref, st = rg.rgbid_align_batch(ctx, As, Bs, ws.label_params(), inits=truth)
+        for i in range(3):
+            h = lambda t: t[i].cpu().numpy().astype(np.float32)
+            Ro, to, so = oracle.align(cam, h(IA), h(WA), h(IB), h(WB),
+                                      oracle.Params(levels=4, iters=[5] * 4, weight="huber"),
+                                      R0=truth[i][0], t0=truth[i][1])
+            assert st[i]["status"] == so["status"], i
+            if so["status"] == 0:
+                assert np.linalg.norm(oracle.log_so3(ref[i][0].T @ Ro)) <= 1e-5, i
+                assert np.linalg.norm(ref[i][1] - to) <= 1e-5, i
+        for P in As + Bs:
+            rg.rgbid_pyramid_free(P)
+        torch.cuda.synchronize()
+    finally:
+        rg.rgbid_destroy(ctx)
