@@ -439,6 +439,10 @@ def main():
     ap.add_argument("--warp", choices=["fullres", "per_level"], default="fullres")
     ap.add_argument("--weight", choices=["huber", "student_t"], default="huber")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scale-cold", action="store_true",
+                    help="every iteration's location / scale fixed point starts from mu = 0, "
+                         "sigma^2 = mean r^2 and takes all 20 steps (default: warm start from "
+                         "the previous iteration with the 2^-20 sigma convergence stop)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", choices=["uniform", "mixed"], default="uniform",
                     help="uniform: --pairs pairs at 640x480 (the headline workload); mixed: "
@@ -510,7 +514,8 @@ def main():
     params = rg.rgbid_default_params(
         levels=4, iters=[10, 10, 10, 10],
         weight=rg.RGBID_W_HUBER if args.weight == "huber" else rg.RGBID_W_STUDENT_T,
-        warp=rg.RGBID_WARP_FULLRES if args.warp == "fullres" else rg.RGBID_WARP_PER_LEVEL)
+        warp=rg.RGBID_WARP_FULLRES if args.warp == "fullres" else rg.RGBID_WARP_PER_LEVEL,
+        scale_warm=0 if args.scale_cold else 1)
     all_pyr = As + Bs
     all_I = IA + IB
     all_W = WA + WB
@@ -667,6 +672,8 @@ def main():
                    "batch": args.batch,
                    "pairs_per_step": args.pairs, "width": cam.w, "height": cam.h, "levels": 4,
                    "iters_per_level": 10, "warp": args.warp, "weight": args.weight,
+                   "scale_fixed_point": "cold, 20 steps" if args.scale_cold else
+                   "warm start, stop at 2^-20 sigma, at most 20 steps",
                    "storage": args.storage, "parallelism": "single GPU",
                    "autotuned_us_per_iteration": tuned},
         "roofline": roofline,
@@ -682,7 +689,7 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 oracle on a bounded sample ...")
         op = oracle.Params(levels=4, iters=[10] * 4, weight=args.weight, warp=args.warp,
-                           storage=args.storage)
+                           storage=args.storage, scale_warm=not args.scale_cold)
         out["cpu_baseline"] = cpu_baseline(pairs, fusion, op, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     for p in As + Bs:

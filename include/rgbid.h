@@ -90,6 +90,12 @@ typedef struct {
     int warp;                /* rgbid_warp_mode */
     double stop_eps_t;       /* early stop of a level when |v| < eps_t and |theta| < eps_r; */
     double stop_eps_r;       /*   both 0 = fixed schedule (default) */
+    int scale_warm;          /* 1 (default): the location / scale fixed point of every
+                                iteration after the first at a level starts from the
+                                previous iteration's mu, sigma, and the step that moves
+                                both by at most 2^-20 sigma is its last (at most
+                                scale_iters steps); 0: every iteration starts from mu = 0,
+                                sigma^2 = mean r^2 and takes scale_iters steps (sec. 6.3) */
 } rgbid_align_params;
 
 /* Statistics of the last linearisation of an alignment.  H is the upper

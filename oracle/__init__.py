@@ -49,7 +49,7 @@ class _Params(C.Structure):
                 ("huber_k", C.c_double), ("estimate_nu", C.c_int),
                 ("sample_max", C.c_int), ("scale_iters", C.c_int), ("warp", C.c_int),
                 ("stop_eps_t", C.c_double), ("stop_eps_r", C.c_double),
-                ("storage", C.c_int)]
+                ("storage", C.c_int), ("scale_warm", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -73,6 +73,7 @@ class Params:
     stop_eps_t: float = 0.0
     stop_eps_r: float = 0.0
     storage: str = "f32"
+    scale_warm: bool = True
 
     def _c(self) -> _Params:
         p = _Params()
@@ -89,6 +90,7 @@ class Params:
         p.stop_eps_t = self.stop_eps_t
         p.stop_eps_r = self.stop_eps_r
         p.storage = STORAGE[self.storage]
+        p.scale_warm = int(self.scale_warm)
         return p
 
 
@@ -119,7 +121,7 @@ def lib():
         L.or_digamma.restype = C.c_double
         L.or_digamma.argtypes = [C.c_double]
         L.or_scale.argtypes = [dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
-                               C.c_double, dp, dp]
+                               C.c_double, dp, C.c_double, dp, dp]
         L.or_nu_equation.restype = C.c_double
         L.or_nu_equation.argtypes = [dp, C.c_int, C.c_double, C.c_double, C.c_double]
         L.or_estimate_nu.restype = C.c_double
@@ -129,7 +131,7 @@ def lib():
         L.or_solve.restype = C.c_int
         L.or_solve.argtypes = [dp, dp, dp]
         L.or_normal_equations.argtypes = [cp, dp, dp, dp, dp, u8p, C.POINTER(_Params),
-                                          C.POINTER(_Stats)]
+                                          C.c_void_p, C.POINTER(_Stats)]
         L.or_pyramid.argtypes = [cp, C.c_int, dp, dp, C.c_int, dp, dp]
         L.or_normal_equations_at.argtypes = [cp, C.c_int, dp, dp, dp, dp, C.c_int, dp, dp,
                                              C.POINTER(_Params), C.POINTER(_Stats)]
@@ -290,10 +292,20 @@ def digamma(x: float) -> float:
     return lib().or_digamma(float(x))
 
 
-def scale(r, kind="huber", nu=5.0, k=1.345, iters=20, floor=1e-3):
+# The convergence stop of the warm-started fixed point (fraction of sigma).
+SCALE_TOL = 2.0 ** -20
+
+
+def scale(r, kind="huber", nu=5.0, k=1.345, iters=20, floor=1e-3, start=None, tol=0.0):
+    """mu, sigma by the fixed point of sec. 6.3: from start = (mu0, sigma0),
+    else mu = 0, sigma^2 = mean r^2; at most `iters` steps, the step that moves
+    both by at most tol * sigma the last."""
     r = _d(r).reshape(-1)
     mu, sg = C.c_double(), C.c_double()
-    lib().or_scale(_p(r), len(r), WEIGHTS[kind], nu, k, iters, floor, C.byref(mu), C.byref(sg))
+    s0 = None if start is None else _d(start)
+    st = None if s0 is None else _p(s0)
+    lib().or_scale(_p(r), len(r), WEIGHTS[kind], nu, k, iters, floor, st, tol, C.byref(mu),
+                   C.byref(sg))
     return mu.value, sg.value
 
 
@@ -327,7 +339,7 @@ def normal_equations(cam, IA, WA, Iw, Ww, valid, params: Params = None):
     st = _Stats()
     pc = params._c()
     lib().or_normal_equations(C.byref(c), _p(IA), _p(WA), _p(Iw), _p(Ww), _pu8(V),
-                              C.byref(pc), C.byref(st))
+                              C.byref(pc), None, C.byref(st))
     return _stats(st)
 
 

@@ -48,7 +48,20 @@ typedef struct {
     int warp;            /* OR_WARP_* */
     double stop_eps_t, stop_eps_r;
     int storage;         /* rounding applied to every stored pyramid level */
+    int scale_warm;      /* 1: warm-started fixed point with the convergence stop */
 } or_params;
+
+/* Where the mu, sigma fixed point of the next linearisation at a level
+   starts: the last estimate of each channel and its sample size (0: none
+   yet, start cold). */
+typedef struct {
+    double mu[2], sigma[2];
+    int n[2];
+} or_scale_state;
+
+/* Convergence stop of the warm-started fixed point: a step that moves mu and
+   sigma by at most this fraction of sigma is the last. */
+#define OR_SCALE_TOL 9.5367431640625e-7   /* 2^-20 */
 
 typedef struct {
     double H[36], g[6];
@@ -398,16 +411,26 @@ double or_digamma(double x)
    sec. 6.3 (sum w (r - mu) = 0, sum (1 - w (r-mu)^2/sigma^2) = 0), updating
    the weights from the previous estimate before each step:
      mu <- sum w r / sum w,   sigma^2 <- sum w (r - mu)^2 / n.
-   Start mu = 0, sigma^2 = mean r^2.  sigma is floored at sigma_floor.
-   n == 0 returns mu = 0, sigma = sigma_floor (the caller disables the channel). */
+   Start: start = {mu0, sigma0}, or mu = 0, sigma^2 = mean r^2 when start is
+   NULL.  At most iters steps; the step after which both |mu' - mu| and
+   |sigma' - sigma| are at most tol sigma' is the last (tol = 0: only a step
+   that changes nothing, after which every further step would repeat it).
+   sigma is floored at sigma_floor.  n == 0 returns mu = 0, sigma =
+   sigma_floor (the caller disables the channel). */
 void or_scale(const double* r, int n, int kind, double nu, double k, int iters,
-              double sigma_floor, double* mu_out, double* sigma_out)
+              double sigma_floor, const double* start, double tol, double* mu_out,
+              double* sigma_out)
 {
     double mu = 0.0, sigma;
     if (n == 0) { *mu_out = 0.0; *sigma_out = sigma_floor; return; }
-    double s2 = 0.0;
-    for (int i = 0; i < n; ++i) s2 += r[i] * r[i];
-    sigma = sqrt(s2 / n);
+    if (start) {
+        mu = start[0];
+        sigma = start[1];
+    } else {
+        double s2 = 0.0;
+        for (int i = 0; i < n; ++i) s2 += r[i] * r[i];
+        sigma = sqrt(s2 / n);
+    }
     if (sigma < sigma_floor) sigma = sigma_floor;
     for (int it = 0; it < iters; ++it) {
         double sw = 0.0, swr = 0.0;
@@ -421,9 +444,12 @@ void or_scale(const double* r, int n, int kind, double nu, double k, int iters,
         double sv = 0.0;
         for (int i = 0; i < n; ++i) sv += wts[i] * (r[i] - mu_new) * (r[i] - mu_new);
         free(wts);
+        double sigma_new = sqrt(sv / n);
+        if (sigma_new < sigma_floor) sigma_new = sigma_floor;
+        int last = fabs(mu_new - mu) <= tol * sigma_new && fabs(sigma_new - sigma) <= tol * sigma_new;
         mu = mu_new;
-        sigma = sqrt(sv / n);
-        if (sigma < sigma_floor) sigma = sigma_floor;
+        sigma = sigma_new;
+        if (last) break;
     }
     *mu_out = mu;
     *sigma_out = sigma;
@@ -521,7 +547,7 @@ typedef struct {
    H = sum w J J^T, g = sum w J r (uncentred r), cost = sum w r^2. */
 void or_normal_equations(const or_cam* c, const double* IA, const double* WA,
                          const double* Iw, const double* Ww, const uint8_t* wvalid,
-                         const or_params* P, or_stats* st)
+                         const or_params* P, or_scale_state* ss, or_stats* st)
 {
     const int w = c->w, h = c->h;
     size_t n = (size_t)w * h;
@@ -545,8 +571,27 @@ void or_normal_equations(const or_cam* c, const double* IA, const double* WA,
             if (vW[i]) sW[nW++] = rW[i];
         }
     double nu0 = 5.0;
-    or_scale(sI, nI, P->weight, nu0, P->huber_k, P->scale_iters, 1e-3, &st->mu_I, &st->sigma_I);
-    or_scale(sW, nW, P->weight, nu0, P->huber_k, P->scale_iters, 1e-6, &st->mu_W, &st->sigma_W);
+    /* warm start (scale_warm): from the last estimate at this level of a
+       channel whose sample was not empty, ending at the convergence stop */
+    const int warm = P->scale_warm && ss;
+    const double tol = P->scale_warm ? OR_SCALE_TOL : 0.0;
+    double s0I[2], s0W[2];
+    const double* startI = NULL;
+    const double* startW = NULL;
+    if (warm && ss->n[0] > 0) { s0I[0] = ss->mu[0]; s0I[1] = ss->sigma[0]; startI = s0I; }
+    if (warm && ss->n[1] > 0) { s0W[0] = ss->mu[1]; s0W[1] = ss->sigma[1]; startW = s0W; }
+    or_scale(sI, nI, P->weight, nu0, P->huber_k, P->scale_iters, 1e-3, startI, tol, &st->mu_I,
+             &st->sigma_I);
+    or_scale(sW, nW, P->weight, nu0, P->huber_k, P->scale_iters, 1e-6, startW, tol, &st->mu_W,
+             &st->sigma_W);
+    if (ss) {
+        ss->mu[0] = st->mu_I;
+        ss->sigma[0] = st->sigma_I;
+        ss->n[0] = nI;
+        ss->mu[1] = st->mu_W;
+        ss->sigma[1] = st->sigma_W;
+        ss->n[1] = nW;
+    }
     st->nu_I = st->nu_W = nu0;
     if (P->weight == OR_WEIGHT_STUDENT_T && P->estimate_nu) {
         st->nu_I = or_estimate_nu(sI, nI, st->mu_I, st->sigma_I);
@@ -643,7 +688,8 @@ void or_pyramid(const or_cam* c0, int levels, const double* I0, const double* W0
 /* One linearisation at a level: warp B at T (paper-literal full resolution or
    per level), then residuals, scale and normal equations. */
 void or_linearise(const or_cam* c0, const or_pyr* A, const or_pyr* B, int level,
-                  const double R[9], const double t[3], const or_params* P, or_stats* st)
+                  const double R[9], const double t[3], const or_params* P, or_scale_state* ss,
+                  or_stats* st)
 {
     const or_cam* cl = &A->cam[level];
     size_t n = (size_t)cl->w * cl->h;
@@ -654,7 +700,7 @@ void or_linearise(const or_cam* c0, const or_pyr* A, const or_pyr* B, int level,
         or_warp_fullres(c0, level, A->W[0], B->I[0], B->W[0], R, t, Iw, Ww, V);
     else
         or_warp(cl, A->W[level], B->I[level], B->W[level], R, t, Iw, Ww, V);
-    or_normal_equations(cl, A->I[level], A->W[level], Iw, Ww, V, P, st);
+    or_normal_equations(cl, A->I[level], A->W[level], Iw, Ww, V, P, ss, st);
     free(Iw); free(Ww); free(V);
 }
 
@@ -668,7 +714,7 @@ void or_normal_equations_at(const or_cam* c0, int levels, const double* IA0,
     or_pyr A, B;
     pyr_build(&A, c0, levels, IA0, WA0, P->storage);
     pyr_build(&B, c0, levels, IB0, WB0, P->storage);
-    or_linearise(c0, &A, &B, level, R, t, P, st);
+    or_linearise(c0, &A, &B, level, R, t, P, NULL, st);
     pyr_free(&A);
     pyr_free(&B);
 }
@@ -679,7 +725,10 @@ void or_normal_equations_at(const or_cam* c0, int levels, const double* IA0,
    iterations each; each iteration warps B at the current estimate, builds H, g,
    solves H xi = -g and applies T <- exp(xi)^-1 T.  Optional early stop per
    level when |v| < eps_t and |theta| < eps_r.  A degenerate system stops the
-   alignment and keeps the last estimate. */
+   alignment and keeps the last estimate.  With scale_warm, the mu, sigma
+   fixed point of every iteration after the first at a level starts from the
+   previous iteration's estimates (sec. 6.3: the weights of each step come from
+   the previous estimates). */
 int or_align(const or_cam* c0, const double* IA0, const double* WA0, const double* IB0,
              const double* WB0, const double* R_init, const double* t_init,
              const or_params* P, double R[9], double t[3], or_stats* st)
@@ -695,10 +744,12 @@ int or_align(const or_cam* c0, const double* IA0, const double* WA0, const doubl
     memset(st, 0, sizeof *st);
     st->status = OR_OK;
     for (int l = P->levels - 1; l >= 0 && st->status == OR_OK; --l) {
+        or_scale_state ss;   /* no estimate yet at this level */
+        memset(&ss, 0, sizeof ss);
         for (int it = 0; it < P->iters[l]; ++it) {
             or_stats cur;
             memset(&cur, 0, sizeof cur);
-            or_linearise(c0, &A, &B, l, R, t, P, &cur);
+            or_linearise(c0, &A, &B, l, R, t, P, &ss, &cur);
             int done[8];
             memcpy(done, st->iters_done, sizeof done);
             double xi[6];

@@ -1071,7 +1071,9 @@ __device__ __forceinline__ LiveSlots compact_sample(float (&r)[PER], float* cmp,
 // The location / scale fixed point with nu = 5 (Student-t) or the Huber
 // threshold k: every step sums w, w d and w d^2 (d = r - mu, weights from
 // the previous estimate) over the block and moves mu by S1/S0, sigma^2 to
-// (S2 - S1^2/S0)/n.  The per-entry terms are written so that a constant
+// (S2 - S1^2/S0)/n.  At most `iters` steps; the step that moves mu and sigma
+// by at most tol sigma' is the last (tol = 0: a step that changes nothing,
+// which every further step would repeat).  The per-entry terms are written so that a constant
 // factor of the weight is applied to the block totals instead:
 //   Huber      w = hk min(1/hk, 1/|d|), w d = clamp(d, -hk, hk),
 //              w d^2 = clamp(d, -hk, hk) d               (hk = k sigma)
@@ -1081,9 +1083,9 @@ __device__ __forceinline__ LiveSlots compact_sample(float (&r)[PER], float* cmp,
 // the FP64 sums.  bcd / bcf broadcast mu and sigma.
 template <int KIND, int PER>
 __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], LiveSlots ls, float inv_n,
-                                                  float floor_s, float k, int iters, float* part,
-                                                  double* bcd, float* bcf, double& mu,
-                                                  float& sigma)
+                                                  float floor_s, float k, int iters, float tol,
+                                                  float* part, double* bcd, float* bcf,
+                                                  double& mu, float& sigma)
 {
     float fmu = (float)mu, sg = sigma;
     for (int it = 0; it < iters; ++it) {
@@ -1126,21 +1128,27 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], LiveSlo
             const float dm = (float)S1 * rcp((float)S0);
             const double ss = S2 - S1 * (double)dm;
             const float var = fmaxf((float)ss * inv_n, 0.0f);
+            const float sn = fmaxf(__builtin_amdgcn_sqrtf(var), floor_s);
             bcd[0] = mu + (double)dm;
-            bcf[0] = fmaxf(__builtin_amdgcn_sqrtf(var), floor_s);
+            bcf[0] = sn;
+            bcf[1] = fabsf(dm) <= tol * sn && fabsf(sn - sg) <= tol * sn ? 1.0f : 0.0f;
         }
         __syncthreads();
         mu = bcd[0];
         sg = bcf[0];
         fmu = (float)mu;
+        if (bcf[1] != 0.0f) break;
     }
     sigma = sg;
 }
 
 // One workgroup per (pair, channel): location mu and scale sigma of the
 // channel's sample residuals by the fixed point of the two stationarity
-// equations of sec. 6.3 (weights from the previous estimate), starting at
-// mu = 0, sigma^2 = mean r^2, with nu = 5 for Student-t; then (Student-t with
+// equations of sec. 6.3 (weights from the previous estimate), with nu = 5
+// for Student-t, starting at mu = 0, sigma^2 = mean r^2 or (scale_warm, after
+// the first iteration at a level whose sample for the channel was not empty)
+// at the previous iteration's mu, sigma, with the convergence stop at
+// 2^-20 sigma; then (Student-t with
 // estimation) nu by bisection of the nu equation on [2, 10] with the
 // normalised residuals frozen: f(10) > 0 gives 10, f(2) < 0 gives 2, else 30
 // halvings of [2, 10] and the midpoint.  Thread t loads entries t + 1024 q,
@@ -1160,6 +1168,10 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     const PairDesc& D = L.pairs[p];
     const int n_all = D.sw[L.level] * D.sh[L.level];
     const float floor_s = ch == 0 ? 1e-3f : 1e-6f;
+    // the previous estimate (read before thread 0 replaces it at the end)
+    const bool warm = L.ip.scale_warm && S.ns[ch] > 0;
+    const float mu_prev = S.mu[ch], sg_prev = S.sigma[ch];
+    const float tol = L.ip.scale_warm ? 9.5367431640625e-7f : 0.0f;   // 2^-20
     float r[PER];
     float cs[2] = {0.0f, 0.0f};
 #pragma unroll
@@ -1186,18 +1198,20 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
         __syncthreads();
     }
     const double n = bcd[0];
-    double mu = 0.0;
-    float sigma = bcf[0];
+    double mu = warm ? (double)mu_prev : 0.0;
+    float sigma = warm ? sg_prev : bcf[0];
     float nu = 5.0f;
     if (n > 0.0) {
         const LiveSlots ls = compact_sample<PER>(r, cmp, wcnt);
         const float inv_n = (float)(1.0 / n);
         if (L.ip.weight == RGBID_W_HUBER)
             scale_fixed_point<RGBID_W_HUBER, PER>(r, ls, inv_n, floor_s, L.ip.huber_k,
-                                                  L.ip.scale_iters, part, bcd, bcf, mu, sigma);
+                                                  L.ip.scale_iters, tol, part, bcd, bcf, mu,
+                                                  sigma);
         else
             scale_fixed_point<RGBID_W_STUDENT_T, PER>(r, ls, inv_n, floor_s, L.ip.huber_k,
-                                                      L.ip.scale_iters, part, bcd, bcf, mu, sigma);
+                                                      L.ip.scale_iters, tol, part, bcd, bcf, mu,
+                                                      sigma);
         if (L.ip.weight == RGBID_W_STUDENT_T && L.ip.estimate_nu) {
             const float fmu = (float)mu, isg = 1.0f / sigma;
 #pragma unroll
@@ -1562,7 +1576,11 @@ __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
 __global__ void k_level_start(PairState* states, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) states[i].level_stop = 0;
+    if (i < n) {
+        states[i].level_stop = 0;
+        // no scale estimate at this level yet: the first fixed point starts cold
+        states[i].ns[0] = states[i].ns[1] = 0;
+    }
 }
 
 template <bool F16, int LOG2B>

@@ -247,6 +247,7 @@ const char* params_problem(const rgbid_align_params* p)
     if (p->warp != RGBID_WARP_FULLRES && p->warp != RGBID_WARP_PER_LEVEL) return "unknown warp mode";
     if (p->warp == RGBID_WARP_FULLRES && p->levels > 5) return "FULLRES warp supports at most 5 levels";
     if (p->stop_eps_t < 0 || p->stop_eps_r < 0) return "negative stop epsilon";
+    if (p->scale_warm != 0 && p->scale_warm != 1) return "scale_warm must be 0 or 1";
     return nullptr;
 }
 
@@ -495,6 +496,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
     ip.huber_k = (float)P->huber_k;
     ip.estimate_nu = P->estimate_nu;
     ip.scale_iters = P->scale_iters;
+    ip.scale_warm = P->scale_warm;
     ip.warp_mode = P->warp;
     ip.stop_eps_t = P->stop_eps_t;
     ip.stop_eps_r = P->stop_eps_r;
@@ -746,6 +748,7 @@ void rgbid_default_params(rgbid_align_params* p)
     p->sample_max = 19200;
     p->scale_iters = 20;
     p->warp = RGBID_WARP_FULLRES;
+    p->scale_warm = 1;
 }
 
 rgbid_status rgbid_create(rgbid_ctx** ctx, int device, void* hip_stream)
@@ -1098,6 +1101,7 @@ rgbid_status rgbid_align_noalloc(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_p
     ip.huber_k = (float)P->huber_k;
     ip.estimate_nu = P->estimate_nu;
     ip.scale_iters = P->scale_iters;
+    ip.scale_warm = P->scale_warm;
     ip.warp_mode = P->warp;
     ip.stop_eps_t = P->stop_eps_t;
     ip.stop_eps_r = P->stop_eps_r;

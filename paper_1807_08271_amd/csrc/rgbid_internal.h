@@ -80,6 +80,7 @@ struct IterParams {
     int estimate_nu;
     int scale_iters;
     int warp_mode;       // rgbid_warp_mode
+    int scale_warm;      // warm-started scale fixed point with the convergence stop
     double stop_eps_t, stop_eps_r;
 };
 

@@ -48,7 +48,7 @@ class rgbid_align_params(C.Structure):
     _fields_ = [("levels", C.c_int), ("iters", C.c_int * 8), ("weight", C.c_int),
                 ("huber_k", C.c_double), ("estimate_nu", C.c_int), ("sample_max", C.c_int),
                 ("scale_iters", C.c_int), ("warp", C.c_int), ("stop_eps_t", C.c_double),
-                ("stop_eps_r", C.c_double)]
+                ("stop_eps_r", C.c_double), ("scale_warm", C.c_int)]
 
 
 class rgbid_bilateral(C.Structure):
@@ -267,8 +267,10 @@ def rgbid_default_params(**overrides) -> rgbid_align_params:
             its = list(v) + [0] * (8 - len(v))
             for i in range(8):
                 p.iters[i] = int(its[i])
-        else:
+        elif k in dict(rgbid_align_params._fields_):
             setattr(p, k, v)
+        else:
+            raise TypeError("rgbid_align_params has no field %r" % k)
     return p
 
 

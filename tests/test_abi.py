@@ -3,6 +3,8 @@ declares (no device calls: runs without a GPU)."""
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -28,6 +30,10 @@ def test_default_params():
     assert p.levels == 4 and list(p.iters)[:4] == [10] * 4
     assert p.weight == rgbid.RGBID_W_HUBER and abs(p.huber_k - 1.345) < 1e-15
     assert p.sample_max == 19200 and p.scale_iters == 20 and p.warp == rgbid.RGBID_WARP_FULLRES
+    assert p.scale_warm == 1
+    assert rgbid.rgbid_default_params(scale_warm=0).scale_warm == 0
+    with pytest.raises(TypeError):
+        rgbid.rgbid_default_params(scale_wram=0)
 
 
 def test_pose_maps_host_functions():

@@ -246,6 +246,35 @@ def test_align_c2_matches_oracle(ctx, c2_pairs, warp, weight):
     rg.rgbid_pyramid_free(B)
 
 
+@pytest.mark.parametrize("weight", ["huber", "student_t"])
+def test_align_scale_schedules_match_oracle(ctx, c2_pairs, weight):
+    # Both schedules of the mu, sigma fixed point (sec. 6.3): warm-started
+    # with the convergence stop (default) and cold with all scale_iters
+    # steps, each against the oracle run the same way.  The two schedules end
+    # at the same fixed point to about 1e-6 of sigma, so after 10 iterations
+    # per level their poses agree within the pose bar as well.
+    rg = _rg()
+    p = c2_pairs[1]
+    A = _pyr(ctx, p.cam, 4, p.A)
+    B = _pyr(ctx, p.cam, 4, p.B)
+    got = {}
+    for warm in (1, 0):
+        R, t, st, rc = rg.rgbid_align(ctx, A, B, _params(4, [10] * 4, weight, scale_warm=warm))
+        Ro, to, sto = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W,
+                                   _oparams(4, [10] * 4, weight, scale_warm=bool(warm)))
+        what = "%s scale_warm %d" % (weight, warm)
+        assert rc == 0 and sto["status"] == 0, what
+        assert rot_err(R, Ro) <= 1e-5, (what, rot_err(R, Ro))
+        assert np.linalg.norm(t - to) <= 1e-5, (what, np.linalg.norm(t - to))
+        for k in ("sigma_I", "sigma_W"):
+            assert st[k] == pytest.approx(sto[k], rel=1e-4), (what, k)
+        got[warm] = (R, t)
+    assert rot_err(got[0][0], got[1][0]) <= 1e-5
+    assert np.linalg.norm(got[0][1] - got[1][1]) <= 1e-5
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
 def test_align_fp16_storage_matches_oracle_on_rounded_inputs(ctx, c2_pairs):
     rg = _rg()
     p = c2_pairs[1]

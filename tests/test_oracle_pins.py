@@ -370,6 +370,60 @@ def test_scale_unit_weights_is_mean_and_variance():
     assert sg == pytest.approx(r.std(), rel=1e-12)
 
 
+@pytest.mark.parametrize("kind", ["huber", "student_t"])
+def test_scale_convergence_stop_meets_stationarity(kind):
+    # The convergence stop (the step that moves mu and sigma by at most
+    # tol sigma is the last) leaves the two stationarity equations of sec. 6.3
+    # satisfied to about tol: the next step would move mu by
+    # sum w (r - mu) / sum w and sigma^2 by sigma^2 (sum w x^2 / n - 1).
+    rng = np.random.default_rng(12)
+    r = rng.standard_t(4, size=5000) * 3.0 + 0.7
+    tol = oracle.SCALE_TOL
+    for start in (None, (2.0, 9.0), (-1.0, 0.5)):
+        mu, sg = oracle.scale(r, kind=kind, nu=5.0, iters=300, floor=1e-9, start=start, tol=tol)
+        x = (r - mu) / sg
+        wts = np.array([oracle.omega(kind, xi, 5.0) for xi in x])
+        assert abs(np.sum(wts * (r - mu)) / np.sum(wts)) <= 2 * tol * sg
+        assert abs(np.mean(wts * x * x) - 1.0) <= 4 * tol
+
+
+@pytest.mark.parametrize("kind", ["huber", "student_t"])
+def test_scale_warm_start_reaches_the_cold_fixed_point(kind):
+    # The fixed point does not depend on where the iteration starts: warm
+    # starts near and far from it end within a few tol of the cold start run
+    # to exact convergence, and a start at the fixed point stops after one
+    # step that leaves it there.
+    rng = np.random.default_rng(13)
+    r = np.concatenate([rng.normal(0.3, 2.0, size=4000), rng.normal(0.0, 25.0, size=600)])
+    mu0, sg0 = oracle.scale(r, kind=kind, iters=1000, floor=1e-9)
+    tol = oracle.SCALE_TOL
+    for start in ((mu0, sg0), (mu0 + 0.5, 1.3 * sg0), (-3.0, 0.2 * sg0), (0.0, 40.0)):
+        mu, sg = oracle.scale(r, kind=kind, iters=300, floor=1e-9, start=start, tol=tol)
+        assert abs(mu - mu0) <= 4 * tol * sg0 and abs(sg - sg0) <= 4 * tol * sg0
+    mu, sg = oracle.scale(r, kind=kind, iters=1, floor=1e-9, start=(mu0, sg0), tol=tol)
+    assert abs(mu - mu0) <= 1e-12 * sg0 and abs(sg - sg0) <= 1e-12 * sg0
+    # tol = 0 keeps the fixed number of steps: 3 steps from a far start are
+    # still far from the fixed point
+    mu, sg = oracle.scale(r, kind=kind, iters=3, floor=1e-9, start=(0.0, 40.0), tol=0.0)
+    assert abs(sg - sg0) > 1e-3 * sg0
+
+
+def test_align_scale_warm_start_same_optimum():
+    # Warm-started scale (default) and the cold fixed schedule reach the same
+    # Gauss-Newton optimum on a converging pair (weights agree to about 1e-6).
+    import synth
+    p = synth.pair_c1(0)
+    kw = dict(levels=3, iters=[8, 8, 8], weight="huber")
+    Rw, tw, sw_ = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W, oracle.Params(**kw))
+    Rc, tc, sc = oracle.align(p.cam, p.A.I, p.A.W, p.B.I, p.B.W,
+                              oracle.Params(scale_warm=False, **kw))
+    assert sw_["status"] == sc["status"] == 0
+    assert np.linalg.norm(oracle.log_so3(Rw.T @ Rc)) < 1e-7
+    assert np.linalg.norm(tw - tc) < 1e-7
+    assert abs(sw_["sigma_I"] - sc["sigma_I"]) <= 1e-5 * sc["sigma_I"]
+    assert abs(sw_["sigma_W"] - sc["sigma_W"]) <= 1e-5 * sc["sigma_W"]
+
+
 def test_scale_floor_and_empty():
     mu, sg = oracle.scale(np.zeros(50), kind="huber", floor=1e-3)
     assert mu == 0.0 and sg == 1e-3
