@@ -908,30 +908,17 @@ __device__ __forceinline__ double psi_tail(double ix)
            z * (1.0 / 12 + z * (-1.0 / 120 + z * (1.0 / 252 + z * (-1.0 / 240 + z * (1.0 / 132)))));
 }
 
-// Sum of v over the 64 lanes of a wave, left in lane 63, with DPP: a scan
-// inside each row of 16 lanes (row_shr 1, 2, 4, 8, zero fill), then the
-// totals of rows 0 and 2 added into rows 1 and 3 (row_bcast:15), then the
-// total of rows 0-1 into rows 2-3 (row_bcast:31).  A fixed order.
+// One step of a DPP sum over the lanes of a wave (row mask `rows`).
 #define RGBID_DPP_ADD(v, ctrl, rows)                                                            \
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, rows, 0xf, true))
 
-__device__ __forceinline__ float wave_sum_to_last(float v)
-{
-    RGBID_DPP_ADD(v, 0x111, 0xf);   // row_shr:1
-    RGBID_DPP_ADD(v, 0x112, 0xf);   // row_shr:2
-    RGBID_DPP_ADD(v, 0x114, 0xf);   // row_shr:4
-    RGBID_DPP_ADD(v, 0x118, 0xf);   // row_shr:8
-    RGBID_DPP_ADD(v, 0x142, 0xa);   // row_bcast:15 into rows 1 and 3
-    RGBID_DPP_ADD(v, 0x143, 0xc);   // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
-// Block totals of NV per-thread FP32 values, in FP64 and valid in lane 15 of
-// wave 0 only: every wave reduces its values (lane 63 stores them to LDS);
-// after a barrier, lane j < 16 of wave 0 takes the values of wave j (zero
-// past the last wave) and an FP64 scan across the row of 16 lanes leaves the
-// totals in lane 15.  A fixed order.  The scale kernel's update runs in that
-// lane and reaches the other waves through LDS after a second barrier.
+// Block totals of NV <= 4 per-thread FP32 values, in FP64 and valid in every
+// lane of wave 0: every wave reduces its values (lane 63 stores them to LDS);
+// after a barrier, row k of wave 0 (lanes 16 k .. 16 k + 15) takes value k of
+// waves 0 .. 15 (zero past the last wave), one FP64 scan across the rows of
+// 16 lanes leaves total k in lane 16 k + 15, and the totals are read from
+// there.  A fixed order.  The scale kernel's update runs in wave 0 and
+// reaches the other waves through LDS after a second barrier.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v)
 {
@@ -942,28 +929,55 @@ __device__ __forceinline__ double dpp_d(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 constexpr int kTotalsLane = 15;
 
 template <int NV>
 __device__ __forceinline__ void block_totals(const float (&x)[NV], float* part, double (&tot)[NV])
 {
+    static_assert(NV >= 1 && NV <= 4, "one row of wave 0 per value");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // Sum of each value over the 64 lanes of the wave, left in lane 63: a
+    // scan inside each row of 16 lanes (row_shr 1, 2, 4, 8, zero fill), then
+    // the totals of rows 0 and 2 added into rows 1 and 3 (row_bcast:15), then
+    // the total of rows 0-1 into rows 2-3 (row_bcast:31); the NV values step
+    // by step, so that their DPP steps interleave.
+    float w[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const float w = wave_sum_to_last(x[k]);
-        if (lane == 63) part[wave * NV + k] = w;
+    for (int k = 0; k < NV; ++k) w[k] = x[k];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) RGBID_DPP_ADD(w[k], 0x111, 0xf);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) RGBID_DPP_ADD(w[k], 0x112, 0xf);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) RGBID_DPP_ADD(w[k], 0x114, 0xf);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) RGBID_DPP_ADD(w[k], 0x118, 0xf);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) RGBID_DPP_ADD(w[k], 0x142, 0xa);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) RGBID_DPP_ADD(w[k], 0x143, 0xc);
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) part[wave * NV + k] = w[k];
     }
     __syncthreads();
     if (wave == 0) {
+        const int k = lane >> 4, j = lane & 15;
+        double t = k < NV && j < nw ? (double)part[j * NV + k] : 0.0;
+        t += dpp_d<0x111>(t);   // row_shr:1
+        t += dpp_d<0x112>(t);   // row_shr:2
+        t += dpp_d<0x114>(t);   // row_shr:4
+        t += dpp_d<0x118>(t);   // row_shr:8
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double t = lane < nw ? (double)part[lane * NV + k] : 0.0;
-            t += dpp_d<0x111>(t);   // row_shr:1
-            t += dpp_d<0x112>(t);   // row_shr:2
-            t += dpp_d<0x114>(t);   // row_shr:4
-            t += dpp_d<0x118>(t);   // row_shr:8
-            tot[k] = t;
-        }
+        for (int q = 0; q < NV; ++q) tot[q] = readlane_d(t, 16 * q + 15);
     }
 }
 
@@ -1039,7 +1053,8 @@ __device__ __forceinline__ int wave_scan_i(int v)
 template <int PER>
 __device__ __forceinline__ LiveSlots compact_sample(float (&r)[PER], float* cmp, int* wcnt)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int nw = kScaleThreads / 64;
     int cnt = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) cnt += r[q] < kNoSample ? 1 : 0;
@@ -1047,6 +1062,7 @@ __device__ __forceinline__ LiveSlots compact_sample(float (&r)[PER], float* cmp,
     if (lane == 63) wcnt[wave] = incl;
     __syncthreads();
     int before = 0, total = 0;
+#pragma unroll
     for (int w = 0; w < nw; ++w) {
         const int c = wcnt[w];
         before += w < wave ? c : 0;
@@ -1174,15 +1190,15 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     const float tol = L.ip.scale_warm ? 9.5367431640625e-7f : 0.0f;   // 2^-20
     float r[PER];
     float cs[2] = {0.0f, 0.0f};
+    // every load is issued (past the end at the last entry, which the buffer
+    // holds) before any is used: a load under a condition would wait for the
+    // one before it
+    const int last = max(n_all - 1, 0);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int i = threadIdx.x + k * kScaleThreads;
-        float x = kNoSample;
-        if (i < n_all) {
-            const float2 e = load_f2(D.sample, i);
-            const float y = ch == 0 ? e.x : e.y;
-            x = y == y ? y : kNoSample;   // NaN: residual not defined
-        }
+        const float y = ld_at<float>(D.sample, 2u * (unsigned)min(i, last) + (unsigned)ch);
+        const float x = i < n_all && y == y ? y : kNoSample;   // NaN: residual not defined
         r[k] = x;
         const bool ok = x < kNoSample;
         cs[0] += ok ? 1.0f : 0.0f;
