@@ -1455,7 +1455,9 @@ __device__ void rot_of(const double th[3], double E[9])
         return;
     }
     const double k[3] = {th[0] / n, th[1] / n, th[2] / n};
-    const double c = cos(n), s = sin(n), oc = 1.0 - c;
+    double s, c;
+    sincos(n, &s, &c);
+    const double oc = 1.0 - c;
     E[0] = c + oc * k[0] * k[0];
     E[1] = oc * k[0] * k[1] - s * k[2];
     E[2] = oc * k[0] * k[2] + s * k[1];
@@ -1467,41 +1469,41 @@ __device__ void rot_of(const double th[3], double E[9])
     E[8] = c + oc * k[2] * k[2];
 }
 
+// One wave per pair: the FP64 sums over the pair's chunks (term k < kNSum of
+// chunk beg + j goes to lane k for even j and to lane 32 + k for odd j; each
+// lane adds its chunks in order into two sums, alternately, 16 loads in
+// flight at a time; then each lane adds its two sums and lane k adds lane
+// 32 + k), the normal equations into the state, the 6x6 Cholesky and the
+// update.
 __global__ void __launch_bounds__(64) k_solve(IterLaunch L)
 {
     const int p = blockIdx.x;
     PairState& S = L.states[p];
     if (!S.active || S.level_stop) return;
-    __shared__ double part[64 * kNSum];
     const int lane = threadIdx.x;
     const int beg = L.pair_red_begin[p], end = L.pair_red_begin[p + 1];
-    // lane j adds the chunks beg + j, beg + j + 64, ...; then lane k < kNSum
-    // adds term k of the 64 lane sums in lane order
-    {
-        double t[kNSum];
+    const int term = lane & 31;
+    double t2[2] = {0.0, 0.0};
+    if (term < kNSum) {
+        // the loads of a batch are issued at clamped (valid) chunks before
+        // any is used; chunks past the end count zero
+        constexpr int kBatch = 16;
+        for (int c = beg + (lane >> 5); c < end; c += 2 * kBatch) {
+            float2 q[kBatch];
 #pragma unroll
-        for (int k = 0; k < kNSum; ++k) t[k] = 0.0;
-        for (int c = beg + lane; c < end; c += 64) {
+            for (int j = 0; j < kBatch; ++j)
+                q[j] = load_f2(L.partials, (size_t)min(c + 2 * j, end - 1) * kNSum + term);
 #pragma unroll
-            for (int k = 0; k < kNSum; ++k) {
-                const float2 q = load_f2(L.partials, (size_t)c * kNSum + k);
-                t[k] += (double)q.x + (double)q.y;
-            }
+            for (int j = 0; j < kBatch; ++j)
+                if (c + 2 * j < end) t2[j & 1] += (double)q[j].x + (double)q[j].y;
         }
-#pragma unroll
-        for (int k = 0; k < kNSum; ++k) part[k * 64 + lane] = t[k];
     }
-    __syncthreads();
-    if (lane < kNSum) {
-        double t = 0.0;
-        for (int j = 0; j < 64; ++j) t += part[lane * 64 + j];
-        part[lane * 64] = t;
-    }
-    __syncthreads();
-    if (lane != 0) return;
+    double t = t2[0] + t2[1];
+    t += __shfl_down(t, 32);
     double s[kNSum];
 #pragma unroll
-    for (int k = 0; k < kNSum; ++k) s[k] = part[k * 64];
+    for (int q = 0; q < kNSum; ++q) s[q] = readlane_d(t, q);
+    if (lane != 0) return;
 
     for (int k = 0; k < 21; ++k) S.H[k] = s[k];
     for (int k = 0; k < 6; ++k) S.g[k] = s[21 + k];

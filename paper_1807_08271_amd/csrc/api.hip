@@ -1201,7 +1201,7 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
         std::vector<Cand> cands;
         for (int fused = 0; fused < 2; ++fused)
             for (int waves : {2, 4, 8})
-                for (int tpw : {1, 2, 4, 8, 16})
+                for (int tpw : {1, 2, 4, 8, 16, 32})
                     for (int remap = 0; remap < 2; ++remap) {
                         LevelTune t;
                         t.fused = fused;

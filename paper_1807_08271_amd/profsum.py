@@ -129,6 +129,12 @@ def main(argv=None):
                 continue
             for c, v in d.items():
                 per[(kk[0], kk[1], kk[2], grid)][c] = (sum(v) / len(v), len(v))
+    if not a.pmc:
+        # a kernel trace only: no counter section, and nothing for bench.py
+        with open(a.out, "w") as fh:
+            fh.write("\n".join(lines + [""]))
+        print("wrote", a.out)
+        return
     lines += ["", "## Counters per dispatch (`--pmc`, one counter group per run)", "",
               "Copy calibration: a copy of %d bytes reads FETCH_SIZE %s KiB and WRITE_SIZE %s KiB "
               "per dispatch; scale factors FETCH %.3f, WRITE %.3f." % (
