@@ -510,7 +510,12 @@ def main():
     fcam, kf, frames, fposes = fusion
     kfW = up(kf.W)
     fW = [up(f.W) for f in frames]
-    K = rg.rgbid_keyframe_init(ctx, fcam, kfW)
+    # The keyframe fusion does not depend on the alignments of the step, so
+    # it runs in a context of its own on a second stream (default priority)
+    # and overlaps them, as a tracking loop and a mapping loop would.
+    fuse_stream = torch.cuda.Stream(device=dev)
+    ctx_f = rg.rgbid_create(0, fuse_stream)
+    K = rg.rgbid_keyframe_init(ctx_f, fcam, kfW)
     params = rg.rgbid_default_params(
         levels=4, iters=[10, 10, 10, 10],
         weight=rg.RGBID_W_HUBER if args.weight == "huber" else rg.RGBID_W_STUDENT_T,
@@ -546,10 +551,10 @@ def main():
     os.remove(tune_txt)
 
     def step():
+        rg.rgbid_keyframe_reset(ctx_f, K, kfW)
+        rg.rgbid_fuse_batch(ctx_f, K, fW, fposes, 0.01)
         rg.rgbid_pyramid_update_batch(ctx, all_pyr, all_I, all_W)
         poses, stats = rg.rgbid_align_batch(ctx, As, Bs, params)
-        rg.rgbid_keyframe_reset(ctx, K, kfW)
-        rg.rgbid_fuse_batch(ctx, K, fW, fposes, 0.01)
         return poses, stats
 
     # The timed form enqueues a whole step without waiting: the poses land in
@@ -558,10 +563,10 @@ def main():
     pose_buf = torch.empty(args.pairs * rg.POSE_BYTES, dtype=torch.uint8, device=dev)
 
     def step_async():
+        rg.rgbid_keyframe_reset(ctx_f, K, kfW)
+        rg.rgbid_fuse_batch(ctx_f, K, fW, fposes, 0.01)
         rg.rgbid_pyramid_update_batch(ctx, all_pyr, all_I, all_W)
         rg.rgbid_align_batch_async(ctx, As, Bs, params, pose_buf)
-        rg.rgbid_keyframe_reset(ctx, K, kfW)
-        rg.rgbid_fuse_batch(ctx, K, fW, fposes, 0.01)
 
     for i in range(args.warmup):
         poses, stats = step()
@@ -695,6 +700,7 @@ def main():
     for p in As + Bs:
         rg.rgbid_pyramid_free(p)
     rg.rgbid_keyframe_free(K)
+    rg.rgbid_destroy(ctx_f)
     rg.rgbid_destroy(ctx)
 
 
