@@ -642,6 +642,27 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kStageFloat4PerWave = 256;   // 128 vectors x 8 floats
 constexpr int kNeGroupTiles = 8;
 
+// Where sum k of the 28 (H upper triangle row-major, g, cost) sits in the
+// accumulators: entry (a, b), a <= b, of the 8 x 8 sum of v v^T (H is rows
+// and columns 0-5, g column 6, the cost entry (6, 6)) is in register row
+// 4 t + i (t = 0 TL, 1 TR, 2 BR; i = a mod 4) of lanes 4 b' + (b mod 4),
+// coded 4 (4 t + i) + b mod 4.  Row a of H starts at k = a (13 - a) / 2.
+// Formed from k (no table: a load in the loop would wait for every load in
+// flight).
+__device__ __forceinline__ unsigned ne_code(int k)
+{
+    int a, b;
+    if (k < 21) {
+        a = (k >= 6) + (k >= 11) + (k >= 15) + (k >= 18) + (k >= 20);
+        b = k - a * (13 - a) / 2 + a;
+    } else {
+        a = min(k - 21, 6);
+        b = 6;
+    }
+    const int t = b < 4 ? 0 : (a < 4 ? 1 : 2);
+    return (unsigned)(4 * (4 * t + (a & 3)) + (b & 3));
+}
+
 struct NeAcc {
     v4f tl, tr, br;   // the current group's MFMA accumulators
     float hi, lo;     // lanes 0..27: compensated total of sum k = lane
@@ -665,12 +686,6 @@ __device__ __forceinline__ void two_sum_add(float& hi, float& lo, float x)
     hi = s;
 }
 
-// Where sum k of the 28 (H upper triangle row-major, g, cost) sits in the
-// accumulators: register row 4 t + i (t = 0 TL, 1 TR, 2 BR) of lanes
-// 4 b + j, coded 4 (4 t + i) + j.
-__constant__ unsigned char kNeMap[28] = {0,  1,  2,  3,  16, 17, 5,  6,  7,  20, 21, 10, 11, 24,
-                                         25, 15, 28, 29, 32, 33, 37, 18, 22, 26, 30, 34, 38, 42};
-
 // Ends a group: the 16 blocks of every sum are added in block order through
 // the wave's staging area and the result joins (hi, lo); the accumulators
 // restart from zero.
@@ -684,7 +699,7 @@ __device__ __forceinline__ void ne_flush(NeAcc& na, float4* st, int lane)
         sc[(8 + r) * 64 + lane] = na.br[r];
     }
     if (lane < 28) {
-        const unsigned c = kNeMap[lane];
+        const unsigned c = ne_code(lane);
         const float* src = sc + (c >> 2) * 64 + (c & 3);
         float t = 0.0f;
 #pragma unroll
@@ -1346,6 +1361,18 @@ __device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, cons
     ne_feed(na, st, lane);
 }
 
+// Level pixel whose warped values come from the store: residuals, weighted
+// Jacobians into the accumulators.
+template <int KIND>
+__device__ __forceinline__ void stored_pixel(const LevelRay& R, const RefPx& r, float2 e, int n,
+                                             const RobustF& F, NeAcc& na, float4* st, int lane,
+                                             unsigned& cI, unsigned& cW)
+{
+    const bool wv = (e.y > 0.0f) & (r.idx < n);
+    pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, r.m, e.x, e.y, wv, F, st, lane, cI, cW);
+    ne_feed(na, st, lane);
+}
+
 // Dynamic LDS: kStageFloat4PerWave float4 per wave (the normal-equation
 // staging area).
 template <bool F16, int LOG2B, bool FUSED, int KIND>
@@ -1365,11 +1392,11 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const void* const warped = D.warped;
     const RobustF F = robust_f(L, S);
 
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     NeAcc na;
     ne_init(na);
     unsigned cI = 0, cW = 0;
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float4* const st = ne_stage + wave * kStageFloat4PerWave;
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
@@ -1398,22 +1425,39 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             own_pixel<F16, KIND>(G, R, rb, gd.n, F, na, st, lane, cI, cW);
             tile += waves;
         }
+    } else if constexpr (!FUSED) {
+        // The warped values come from the store.  Two tiles per trip as
+        // above; the next tile's loads (warped pair, reference values) are
+        // issued before this tile's arithmetic, which has no gathers to wait
+        // for, so a wave waits for a tile's loads only when it arrives at it.
+        const int step = waves * 64, su = step % gd.gw, sv = step / gd.gw;
+        int tile = ch.first + wave;
+        int idx = tile * 64 + lane, u, v;
+        split_index(idx, gd.gw, gd.inv_gw, gd.half_inv, u, v);
+        RefPx ra, rb;
+        load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+        float2 ea = load_f2(warped, min(idx, gd.n - 1)), eb;
+        while (tile < end) {
+            advance(idx, u, v, step, su, sv, gd.gw);
+            load_ref<F16>(A, R, gd.n, idx, u, v, rb);
+            eb = load_f2(warped, min(idx, gd.n - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            stored_pixel<KIND>(R, ra, ea, gd.n, F, na, st, lane, cI, cW);
+            tile += waves;
+            if (tile >= end) break;
+            advance(idx, u, v, step, su, sv, gd.gw);
+            load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+            ea = load_f2(warped, min(idx, gd.n - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            stored_pixel<KIND>(R, rb, eb, gd.n, F, na, st, lane, cI, cW);
+            tile += waves;
+        }
     } else {
         for (int tile = ch.first + wave; tile < end; tile += waves) {
             float Is = 0.0f, Ws = 0.0f;
             bool wv = false;
             int u = 0, v = 0, idx;
-            if constexpr (FUSED) {
-                warp_tile<F16, LOG2B>(G, tile * 64, gd, lane, Is, Ws, wv, u, v, idx);
-            } else {
-                idx = tile * 64 + lane;
-                const int ic = min(idx, gd.n - 1);
-                const float2 e = load_f2(warped, ic);
-                Is = e.x;
-                Ws = e.y;
-                wv = (Ws > 0.0f) & (idx < gd.n);
-                split_index(ic, gd.gw, gd.inv_gw, gd.half_inv, u, v);
-            }
+            warp_tile<F16, LOG2B>(G, tile * 64, gd, lane, Is, Ws, wv, u, v, idx);
             const unsigned i = __umul24(v, A.w) + u;
             pixel_vectors<KIND>(R, ray_x(R, u), ray_y(R, v), load_iw<F16>(A.iw, i),
                                 load_nbrs<F16>(A, i), load_mask(A, i), Is, Ws, wv, F, st, lane,
