@@ -362,7 +362,7 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 // Lane layout of the children of level pixels: a level pixel has C = 4^LOG2B
-// children at the warp level; each lane warps CPL of them (1, 4 or 8 by
+// children at the warp level; each lane warps CPL of them (1, 2, 4 or 8 by
 // level: independent load chains per lane), LPP = C / CPL lanes share one pixel and
 // combine their sums across lanes, and GPP = 64 / LPP pixels are warped per
 // pass.  Lane j of a group takes children c = j + LPP m (m < CPL), child c at

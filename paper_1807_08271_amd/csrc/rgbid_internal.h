@@ -21,12 +21,16 @@ constexpr int kScalePerThread = 24;   // sample_max <= 24576
 constexpr int kMaxSample = kScaleThreads * kScalePerThread;
 
 // Lane layout of the full-resolution warp for level pixels with
-// C = 4^log2b children: each lane warps 1 child at log2b = 0, 4 at 1-2 and 8
-// from 3 on (independent load chains per lane: 8 measured slower at level 2
-// for the lower occupancy, faster at level 3, where a level pixel has 64
-// children), C / that many lanes share a level pixel, and a 64-lane pass
+// C = 4^log2b children: each lane warps 1 child at log2b = 0, 2 at 1, 4 at 2
+// and 8 from 3 on (independent load chains per lane: 8 measured slower at
+// level 2 for the lower occupancy, faster at level 3, where a level pixel has
+// 64 children; at level 1, 2 beat 4 and 1), C / that many lanes share a level
+// pixel, and a 64-lane pass
 // covers 64 / that pixels.  Host launch tables and kernels both use these.
-constexpr int warp_children_per_lane(int log2b) { return log2b == 0 ? 1 : log2b >= 3 ? 8 : 4; }
+constexpr int warp_children_per_lane(int log2b)
+{
+    return log2b == 0 ? 1 : log2b == 1 ? 2 : log2b == 2 ? 4 : 8;
+}
 constexpr int warp_lanes_per_pixel(int log2b) { return (1 << (2 * log2b)) / warp_children_per_lane(log2b); }
 constexpr int warp_pixels_per_pass(int log2b) { return 64 / warp_lanes_per_pixel(log2b); }
 
