@@ -442,7 +442,7 @@ def main():
     ap.add_argument("--scale-cold", action="store_true",
                     help="every iteration's location / scale fixed point starts from mu = 0, "
                          "sigma^2 = mean r^2 and takes all 20 steps (default: warm start from "
-                         "the previous iteration with the 2^-20 sigma convergence stop)")
+                         "the previous iteration with the 2^-16 sigma convergence stop)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", choices=["uniform", "mixed"], default="uniform",
                     help="uniform: --pairs pairs at 640x480 (the headline workload); mixed: "
@@ -678,7 +678,7 @@ def main():
                    "pairs_per_step": args.pairs, "width": cam.w, "height": cam.h, "levels": 4,
                    "iters_per_level": 10, "warp": args.warp, "weight": args.weight,
                    "scale_fixed_point": "cold, 20 steps" if args.scale_cold else
-                   "warm start, stop at 2^-20 sigma, at most 20 steps",
+                   "warm start, stop at 2^-16 sigma, at most 20 steps",
                    "storage": args.storage, "parallelism": "single GPU",
                    "autotuned_us_per_iteration": tuned},
         "roofline": roofline,

@@ -93,7 +93,7 @@ typedef struct {
     int scale_warm;          /* 1 (default): the location / scale fixed point of every
                                 iteration after the first at a level starts from the
                                 previous iteration's mu, sigma, and the step that moves
-                                both by at most 2^-20 sigma is its last (at most
+                                both by at most 2^-16 sigma is its last (at most
                                 scale_iters steps); 0: every iteration starts from mu = 0,
                                 sigma^2 = mean r^2 and takes scale_iters steps (sec. 6.3) */
 } rgbid_align_params;

@@ -293,7 +293,7 @@ def digamma(x: float) -> float:
 
 
 # The convergence stop of the warm-started fixed point (fraction of sigma).
-SCALE_TOL = 2.0 ** -20
+SCALE_TOL = 2.0 ** -16
 
 
 def scale(r, kind="huber", nu=5.0, k=1.345, iters=20, floor=1e-3, start=None, tol=0.0):

@@ -61,7 +61,7 @@ typedef struct {
 
 /* Convergence stop of the warm-started fixed point: a step that moves mu and
    sigma by at most this fraction of sigma is the last. */
-#define OR_SCALE_TOL 9.5367431640625e-7   /* 2^-20 */
+#define OR_SCALE_TOL 1.52587890625e-5   /* 2^-16 */
 
 typedef struct {
     double H[36], g[6];

@@ -1179,7 +1179,7 @@ __device__ __forceinline__ void scale_fixed_point(const float (&r)[PER], LiveSlo
 // for Student-t, starting at mu = 0, sigma^2 = mean r^2 or (scale_warm, after
 // the first iteration at a level whose sample for the channel was not empty)
 // at the previous iteration's mu, sigma, with the convergence stop at
-// 2^-20 sigma; then (Student-t with
+// 2^-16 sigma; then (Student-t with
 // estimation) nu by bisection of the nu equation on [2, 10] with the
 // normalised residuals frozen: f(10) > 0 gives 10, f(2) < 0 gives 2, else 30
 // halvings of [2, 10] and the midpoint.  Thread t loads entries t + 1024 q,
@@ -1202,7 +1202,7 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
     // the previous estimate (read before thread 0 replaces it at the end)
     const bool warm = L.ip.scale_warm && S.ns[ch] > 0;
     const float mu_prev = S.mu[ch], sg_prev = S.sigma[ch];
-    const float tol = L.ip.scale_warm ? 9.5367431640625e-7f : 0.0f;   // 2^-20
+    const float tol = L.ip.scale_warm ? 1.52587890625e-5f : 0.0f;   // 2^-16
     float r[PER];
     float cs[2] = {0.0f, 0.0f};
     // every load is issued (past the end at the last entry, which the buffer
