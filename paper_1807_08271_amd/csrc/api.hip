@@ -700,12 +700,13 @@ rgbid_status build_pyramids(rgbid_ctx* c, int n, rgbid_pyr* const* pyrs, const f
     if ((st = stage_begin(c, n * sizeof(PyrFrame), &stage)) != RGBID_OK) return st;
     PyrFrame* fr = reinterpret_cast<PyrFrame*>(stage);
     int levels = 0, mw[kMaxLevels] = {0}, mh[kMaxLevels] = {0};
-    bool quad = true;
+    bool quad = true, even_h = true;
     for (int i = 0; i < n; ++i) {
         const rgbid_pyr* p = pyrs[i];
         quad = quad && p->w[0] % 4 == 0 && pitch[i] % 4 == 0 &&
                reinterpret_cast<uintptr_t>(I[i]) % 16 == 0 &&
                reinterpret_cast<uintptr_t>(W[i]) % 16 == 0;
+        even_h = even_h && p->h[0] % 2 == 0;
         PyrFrame& f = fr[i];
         std::memset(&f, 0, sizeof f);
         f.I = I[i];
@@ -726,7 +727,7 @@ rgbid_status build_pyramids(rgbid_ctx* c, int n, rgbid_pyr* const* pyrs, const f
     HIPCHK(c, hipMemcpyAsync(c->frames.p, fr, n * sizeof(PyrFrame), hipMemcpyHostToDevice, c->stream));
     if ((st = stage_end(c)) != RGBID_OK) return st;
     HIPCHK(c, launch_pyramid(c->stream, static_cast<const PyrFrame*>(c->frames.p), n, levels,
-                             pyrs[0]->f16, mw, mh, quad));
+                             pyrs[0]->f16, mw, mh, quad, quad && even_h));
     return RGBID_OK;
 }
 

@@ -86,6 +86,89 @@ __global__ void __launch_bounds__(256) k_level0_quad(const PyrFrame* __restrict_
     }
 }
 
+// The value a stored W has: 0 for a hole, and in FP16 storage the rounded
+// value (the flags and the next level are formed from what is stored).
+template <bool F16>
+__device__ __forceinline__ float stored_w(float W)
+{
+    W = w_valid(W) ? W : 0.0f;
+    if constexpr (F16) return __half2float(__float2half_rn(W));
+    else return W;
+}
+
+template <bool F16>
+__device__ __forceinline__ float stored_i(float I)
+{
+    if constexpr (F16) return __half2float(__float2half_rn(I));
+    else return I;
+}
+
+// Levels 0 and 1 and the flags of level 0 in one pass (even sizes, rows of
+// the caller's images 8-byte aligned): a thread takes the 2x2 block of
+// level-0 pixels under one level-1 pixel.  It stores the block (the values
+// of k_level0), flags it (the rule of k_mask, the neighbours' W read from the
+// caller's image at clamped positions and taken as stored) and stores the
+// level-1 pixel (the mean of k_down over the stored block values), so level
+// 0 is neither read back for the downsampling nor for the flags.
+template <bool F16>
+__global__ void __launch_bounds__(256) k_level01(const PyrFrame* __restrict__ frames)
+{
+    const PyrFrame& f = frames[blockIdx.y];
+    const int w = f.w[0], h = f.h[0], bw = w >> 1;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bw * (h >> 1)) return;
+    const int by = b / bw, bx = b - by * bw;
+    const int u0 = 2 * bx, v0 = 2 * by;
+    const long long p = f.pitch;
+    const long long r0 = (long long)v0 * p + u0, r1 = r0 + p;
+    // every load first: the block (I and W), then the W around it
+    const float2 i0 = *reinterpret_cast<const float2*>(f.I + r0);
+    const float2 i1 = *reinterpret_cast<const float2*>(f.I + r1);
+    const float2 w0 = *reinterpret_cast<const float2*>(f.W + r0);
+    const float2 w1 = *reinterpret_cast<const float2*>(f.W + r1);
+    const long long ru = (long long)max(v0 - 1, 0) * p + u0, rd = (long long)min(v0 + 2, h - 1) * p + u0;
+    const float2 wu = *reinterpret_cast<const float2*>(f.W + ru);
+    const float2 wd = *reinterpret_cast<const float2*>(f.W + rd);
+    const int ul = max(u0 - 1, 0), ur = min(u0 + 2, w - 1);
+    const float wl0 = f.W[(long long)v0 * p + ul], wl1 = f.W[(long long)(v0 + 1) * p + ul];
+    const float wr0 = f.W[(long long)v0 * p + ur], wr1 = f.W[(long long)(v0 + 1) * p + ur];
+    // the block as stored, children in the order (0,0), (1,0), (0,1), (1,1)
+    const float I00 = stored_i<F16>(i0.x), I10 = stored_i<F16>(i0.y);
+    const float I01 = stored_i<F16>(i1.x), I11 = stored_i<F16>(i1.y);
+    const float W00 = stored_w<F16>(w0.x), W10 = stored_w<F16>(w0.y);
+    const float W01 = stored_w<F16>(w1.x), W11 = stored_w<F16>(w1.y);
+    const int i = v0 * w + u0;
+    store_level<F16>(f.iw[0], f.wp[0], i, I00, W00);
+    store_level<F16>(f.iw[0], f.wp[0], i + 1, I10, W10);
+    store_level<F16>(f.iw[0], f.wp[0], i + w, I01, W01);
+    store_level<F16>(f.iw[0], f.wp[0], i + w + 1, I11, W11);
+    // flags: bit 0 interior with a valid W, bit 1 also the four neighbours
+    auto flag = [&](int u, int v, float c, float l, float r, float t, float d) -> unsigned {
+        if (!(u >= 1 && v >= 1 && u <= w - 2 && v <= h - 2 && w_valid(c))) return 0u;
+        return w_valid(l) && w_valid(r) && w_valid(t) && w_valid(d) ? 3u : 1u;
+    };
+    const float Wu0 = stored_w<F16>(wu.x), Wu1 = stored_w<F16>(wu.y);
+    const float Wd0 = stored_w<F16>(wd.x), Wd1 = stored_w<F16>(wd.y);
+    const float Wl0 = stored_w<F16>(wl0), Wl1 = stored_w<F16>(wl1);
+    const float Wr0 = stored_w<F16>(wr0), Wr1 = stored_w<F16>(wr1);
+    const unsigned m00 = flag(u0, v0, W00, Wl0, W10, Wu0, W01);
+    const unsigned m10 = flag(u0 + 1, v0, W10, W00, Wr0, Wu1, W11);
+    const unsigned m01 = flag(u0, v0 + 1, W01, Wl1, W11, W00, Wd0);
+    const unsigned m11 = flag(u0 + 1, v0 + 1, W11, W01, Wr1, W10, Wd1);
+    unsigned char* gm = static_cast<unsigned char*>(f.gm[0]);
+    *reinterpret_cast<unsigned short*>(gm + i) = (unsigned short)(m00 | m10 << 8);
+    *reinterpret_cast<unsigned short*>(gm + i + w) = (unsigned short)(m01 | m11 << 8);
+    if (f.levels < 2) return;
+    const float I = (((I00 + I10) + I01) + I11) * 0.25f;
+    float sw = 0.0f;
+    int n = 0;
+    if (w_valid(W00)) { sw += W00; ++n; }
+    if (w_valid(W10)) { sw += W10; ++n; }
+    if (w_valid(W01)) { sw += W01; ++n; }
+    if (w_valid(W11)) { sw += W11; ++n; }
+    store_level<F16>(f.iw[1], f.wp[1], by * bw + bx, I, n ? sw / (float)n : 0.0f);
+}
+
 template <bool F16>
 __global__ void __launch_bounds__(256) k_down(const PyrFrame* __restrict__ frames, int level)
 {
@@ -223,10 +306,16 @@ __global__ void __launch_bounds__(256) k_read(const void* __restrict__ iw, int n
 }  // namespace
 
 hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes, int levels,
-                          int f16, const int* max_w, const int* max_h, bool quad)
+                          int f16, const int* max_w, const int* max_h, bool quad, bool pairs)
 {
     if (nframes <= 0) return hipSuccess;
-    if (quad) {
+    if (pairs) {
+        // levels 0 and 1 and the flags of level 0 in one pass
+        const int n = (max_w[0] / 2) * (max_h[0] / 2);
+        dim3 grid((n + 255) / 256, nframes);
+        if (f16) hipLaunchKernelGGL(k_level01<true>, grid, dim3(256), 0, s, frames_dev);
+        else hipLaunchKernelGGL(k_level01<false>, grid, dim3(256), 0, s, frames_dev);
+    } else if (quad) {
         const int n = (max_w[0] / 4) * max_h[0];
         dim3 grid((n + 255) / 256, nframes);
         if (f16) hipLaunchKernelGGL(k_level0_quad<true>, grid, dim3(256), 0, s, frames_dev);
@@ -237,14 +326,14 @@ hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes
         if (f16) hipLaunchKernelGGL(k_level0<true>, grid, dim3(256), 0, s, frames_dev);
         else hipLaunchKernelGGL(k_level0<false>, grid, dim3(256), 0, s, frames_dev);
     }
-    for (int l = 1; l < levels; ++l) {
+    for (int l = pairs ? 2 : 1; l < levels; ++l) {
         const int n = max_w[l] * max_h[l];
         if (n <= 0) break;
         dim3 grid((n + 255) / 256, nframes);
         if (f16) hipLaunchKernelGGL(k_down<true>, grid, dim3(256), 0, s, frames_dev, l);
         else hipLaunchKernelGGL(k_down<false>, grid, dim3(256), 0, s, frames_dev, l);
     }
-    for (int l = 0; l < levels; ++l) {
+    for (int l = pairs ? 1 : 0; l < levels; ++l) {
         const int n = ((max_w[l] + 3) / 4) * max_h[l];   // quads
         if (n <= 0) break;
         dim3 grid((n + 255) / 256, nframes);

@@ -113,9 +113,11 @@ struct PyrFrame {
     int pad;
 };
 // quad: every frame is a multiple of 4 wide, its pitch a multiple of 4 and its
-// I and W 16-byte aligned (level 0 then moves four pixels per thread)
+// I and W 16-byte aligned (level 0 then moves four pixels per thread); pairs:
+// quad and every frame an even number of rows high (levels 0 and 1 and the
+// level-0 flags are then formed in one pass)
 hipError_t launch_pyramid(hipStream_t s, const PyrFrame* frames_dev, int nframes, int levels,
-                          int f16, const int* max_w, const int* max_h, bool quad);
+                          int f16, const int* max_w, const int* max_h, bool quad, bool pairs);
 hipError_t launch_level_read(hipStream_t s, const void* iw, int n, int f16, float* I, float* W);
 
 // One Gauss-Newton iteration (or one linearisation without update) for all

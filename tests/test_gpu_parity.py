@@ -78,11 +78,13 @@ def test_pyramid_matches_oracle(ctx, c2_pairs, storage):
 
 
 def test_pyramid_row_pitch_and_alignment(ctx, c2_pairs):
-    # Level 0 moves four pixels per thread when the rows allow it (width and
-    # pitch multiples of 4, 16-byte aligned rows), one otherwise: a contiguous
-    # image, the same image inside wider rows, and inside rows whose start is
-    # 4 bytes off 16-byte alignment give identical pyramids (all planes: I and
-    # W read back, W_A and the flags through the normal equations).
+    # When the rows allow it (width and pitch multiples of 4, 16-byte aligned
+    # rows, even height) levels 0 and 1 and the level-0 flags come from one
+    # pass over 2x2 blocks; otherwise level 0 moves one pixel per thread and
+    # levels and flags follow in passes of their own.  A contiguous image, the
+    # same image inside wider rows, and inside rows whose start is 4 bytes off
+    # 16-byte alignment give identical pyramids (all planes: I and W read
+    # back, W_A and the flags through the normal equations at every level).
     rg = _rg()
     import torch
     p = c2_pairs[0]
@@ -102,11 +104,13 @@ def test_pyramid_row_pitch_and_alignment(ctx, c2_pairs):
             for P in pyrs[1:]:
                 got = rg.rgbid_pyramid_read(ctx, P, level)
                 assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (storage, level)
-        ne = [rg.rgbid_normal_equations(ctx, P, Bs, 0, (R, t), prm) for P in pyrs]
-        for g in ne[1:]:
-            np.testing.assert_array_equal(g["H"], ne[0]["H"])
-            np.testing.assert_array_equal(g["g"], ne[0]["g"])
-            assert g["n_valid_I"] == ne[0]["n_valid_I"] and g["n_valid_W"] == ne[0]["n_valid_W"]
+        for level in range(4):
+            ne = [rg.rgbid_normal_equations(ctx, P, Bs, level, (R, t), prm) for P in pyrs]
+            for g in ne[1:]:
+                np.testing.assert_array_equal(g["H"], ne[0]["H"])
+                np.testing.assert_array_equal(g["g"], ne[0]["g"])
+                assert g["n_valid_I"] == ne[0]["n_valid_I"], (storage, level)
+                assert g["n_valid_W"] == ne[0]["n_valid_W"], (storage, level)
         for P in pyrs + [Bs]:
             rg.rgbid_pyramid_free(P)
 
