@@ -146,10 +146,12 @@ def evaluate(ctx, net, n_pairs=1000, chunk=64, schedules=None, log=print):
         for name, (warm, iters) in schedules.items():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            inits = None
             if warm:
-                inits = rg.rgbid_warmstart_predict(ctx, net, st.As[:m], st.Bs[:m], st.x)
-            poses, stats = rg.rgbid_align_batch(ctx, st.As[:m], st.Bs[:m], eval_params(iters), inits=inits)
+                # network and alignment in one call, the initial poses formed on the device
+                poses, stats = rg.rgbid_align_batch_warm(ctx, net, st.As[:m], st.Bs[:m],
+                                                         eval_params(iters))
+            else:
+                poses, stats = rg.rgbid_align_batch(ctx, st.As[:m], st.Bs[:m], eval_params(iters))
             torch.cuda.synchronize()
             res[name]["time"] += time.perf_counter() - t0
             for i in range(m):
@@ -225,6 +227,12 @@ def main(argv=None):
         torch.cuda.empty_cache()
     out = evaluate(ctx, net, args.eval_pairs, log=log)
     print(json.dumps(out))
+    # the evaluation goes into the run record beside the weights
+    rec_path = os.path.splitext(args.out)[0] + ".json"
+    rec = json.load(open(rec_path)) if os.path.exists(rec_path) else {}
+    rec["eval_%d_heldout" % args.eval_pairs] = out
+    with open(rec_path, "w") as f:
+        json.dump(rec, f, indent=1)
     rg.rgbid_warmstart_free(net)
     rg.rgbid_destroy(ctx)
     return 0
