@@ -1404,23 +1404,34 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const Geom G = make_geom<F16>(S, D.A[wl], D.B[wl]);
     if constexpr (FUSED && LOG2B == 0) {
         // The level pixel is its own warp child, so W_A comes with A's (I, W).
-        // A's loads for the next tile are issued while this tile's gathers
-        // from B are in flight.
-        const int step = waves * 64, su = step % gd.gw, sv = step / gd.gw;
-        int tile = ch.first + wave;
-        int idx = tile * 64 + lane, u, v;
-        split_index(idx, gd.gw, gd.inv_gw, gd.half_inv, u, v);
+        // A tile is a kBlockW x kBlockH block of the level (lane l at column
+        // l mod kBlockW, row l / kBlockW of it; pixels past the level's edge
+        // take no part), blocks in raster order: the centre, neighbour and
+        // tap lines of a tile are mostly the same lines, so they are fetched
+        // once.  A's loads for the next tile are issued while this tile's
+        // gathers from B are in flight.
+        const int bxn = (gd.gw + kBlockW - 1) / kBlockW, gh = A.h;
+        const int lu = lane % kBlockW, lv = lane / kBlockW;
+        auto place = [&](int t, int& idx, int& u, int& v) {
+            const int by = t / bxn, bx = t - by * bxn;   // t is uniform
+            u = bx * kBlockW + lu;
+            v = by * kBlockH + lv;
+            idx = (u < gd.gw) & (v < gh) ? v * gd.gw + u : gd.n;
+        };
+        int tile = __builtin_amdgcn_readfirstlane(ch.first + wave);
+        int idx, u, v;
+        place(tile, idx, u, v);
         // two tiles per trip, the prefetch alternating between ra and rb, so
         // the reference values are never copied from one to the other
         RefPx ra, rb;
         load_ref<F16>(A, R, gd.n, idx, u, v, ra);
         while (tile < end) {
-            advance(idx, u, v, step, su, sv, gd.gw);
+            place(tile + waves, idx, u, v);
             load_ref<F16>(A, R, gd.n, idx, u, v, rb);
             own_pixel<F16, KIND>(G, R, ra, gd.n, F, na, st, lane, cI, cW);
             tile += waves;
             if (tile >= end) break;
-            advance(idx, u, v, step, su, sv, gd.gw);
+            place(tile + waves, idx, u, v);
             load_ref<F16>(A, R, gd.n, idx, u, v, ra);
             own_pixel<F16, KIND>(G, R, rb, gd.n, F, na, st, lane, cI, cW);
             tile += waves;

@@ -395,7 +395,7 @@ rgbid_status run_batch(rgbid_ctx* c, int n, const rgbid_pyr* const* A, const rgb
                 for (long long t = 0; t < wt; t += wtiles_per_chunk)
                     wch[k][l].push_back(
                         Chunk{li, (int)t, (int)std::min<long long>(wtiles_per_chunk, wt - t)});
-                const long long rt = ((long long)w * h + 63) / 64;
+                const long long rt = reduce_tiles(w, h, tune[l].fused && b == 0);
                 for (long long t = 0; t < rt; t += rtiles_per_chunk)
                     rch[k][l].push_back(
                         Chunk{li, (int)t, (int)std::min<long long>(rtiles_per_chunk, rt - t)});
@@ -1030,7 +1030,8 @@ rgbid_status rgbid_align_noalloc(rgbid_ctx* c, const rgbid_pyr* A, const rgbid_p
         const int gpp = warp_pixels_per_pass(b);
         const int wper = tune[l].waves * tune[l].warp_passes;
         const int rper = tune[l].waves * tune[l].tiles_per_wave;
-        const int wt = (int)((ngrid + gpp - 1) / gpp), rt = (int)(((long long)w * h + 63) / 64);
+        const int wt = (int)((ngrid + gpp - 1) / gpp);
+        const int rt = (int)reduce_tiles(w, h, tune[l].fused && b == 0);
         nwarp[l] = (wt + wper - 1) / wper;
         su.n_red[l] = (rt + rper - 1) / rper;
         su.seg_first[2 * l] = nch;

@@ -31,6 +31,17 @@ constexpr int warp_children_per_lane(int log2b)
 {
     return log2b == 0 ? 1 : log2b == 1 ? 2 : log2b == 2 ? 4 : 8;
 }
+// Tiles of the reduction at a level: 64 consecutive pixels in raster order,
+// or, where the reduction warps its own pixels one to one (fused, one child
+// per pixel), blocks of kBlockW x kBlockH pixels (a lane per pixel, row by
+// row), so that a tile's neighbours and bilinear taps mostly fall inside the
+// lines the tile itself reads.
+constexpr int kBlockW = 16, kBlockH = 4;
+inline long long reduce_tiles(int w, int h, bool blocks)
+{
+    return blocks ? (long long)((w + kBlockW - 1) / kBlockW) * ((h + kBlockH - 1) / kBlockH)
+                  : ((long long)w * h + 63) / 64;
+}
 constexpr int warp_lanes_per_pixel(int log2b) { return (1 << (2 * log2b)) / warp_children_per_lane(log2b); }
 constexpr int warp_pixels_per_pass(int log2b) { return 64 / warp_lanes_per_pixel(log2b); }
 
