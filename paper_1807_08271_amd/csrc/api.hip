@@ -1190,6 +1190,8 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
     const bool saved_prof = c->profiling;
     c->profiling = false;
     std::vector<rgbid_pose> o(n);
+    // per level, the picks of the per-level round in order (best first)
+    std::vector<std::vector<LevelTune>> top(P->levels);
     for (int l = 0; l < P->levels; ++l) {
         const std::string key = tune_key(n, A, l, P->warp, f16);
         const int b = P->warp == RGBID_WARP_FULLRES ? l : 0;
@@ -1271,6 +1273,65 @@ rgbid_status rgbid_autotune(rgbid_ctx* c, int n, const rgbid_pyr* const* A,
         }
         c->tunes[key] = best;
         if (best_ms) best_ms[l] = best_t / reps;
+        top[l].push_back(best);
+        std::vector<std::pair<float, LevelTune>> rest;
+        for (size_t i = 0; i < nfin; ++i) rest.push_back({median(cands[i].ms), cands[i].t});
+        std::sort(rest.begin(), rest.end(),
+                  [](const auto& x, const auto& y) { return x.first < y.first; });
+        for (const auto& r : rest) {
+            if (top[l].size() >= 3) break;
+            const LevelTune& t = r.second;
+            bool dup = false;
+            for (const LevelTune& u : top[l])
+                dup = dup || std::memcmp(&t, &u, sizeof t) == 0;
+            if (!dup) top[l].push_back(t);
+        }
+    }
+    // Each level was timed alone; in the caller's whole schedule, on the
+    // default chains, the launch shapes also decide how one chain's kernels
+    // overlap another's.  So, level by level, the runners-up of the level and
+    // the other warp passes per wave are tried in the whole schedule against
+    // the current choice, the two timed in turn five times each (the fastest
+    // run of each counts), and a candidate is kept when it is 0.5% faster.
+    {
+        std::vector<Step> full;
+        for (int l = P->levels - 1; l >= 0; --l)
+            if (P->iters[l] > 0) full.push_back(Step{l, P->iters[l]});
+        auto run_full = [&](float* ms) {
+            return run_batch(c, n, A, B, nullptr, P, full, 0, o.data(), nullptr, ms);
+        };
+        rgbid_status st = RGBID_OK;
+        for (int l = 0; l < P->levels && st == RGBID_OK && !full.empty(); ++l) {
+            const std::string key = tune_key(n, A, l, P->warp, f16);
+            std::vector<LevelTune> tries(top[l].begin() + 1, top[l].end());
+            for (int wp : {1, 2, 4, 8}) {
+                LevelTune t = top[l][0];
+                t.warp_passes = wp;
+                if (wp != top[l][0].warp_passes) tries.push_back(t);
+            }
+            for (const LevelTune& cand : tries) {
+                const LevelTune keep = c->tunes[key];
+                if (std::memcmp(&cand, &keep, sizeof cand) == 0) continue;
+                float t_keep = 1e30f, t_cand = 1e30f, ms = 0.0f;
+                // first runs capture the graphs of both choices
+                if ((st = run_full(nullptr)) != RGBID_OK) break;
+                c->tunes[key] = cand;
+                if ((st = run_full(nullptr)) != RGBID_OK) break;
+                for (int r = 0; r < 5 && st == RGBID_OK; ++r) {
+                    c->tunes[key] = keep;
+                    if ((st = run_full(&ms)) != RGBID_OK) break;
+                    t_keep = std::min(t_keep, ms);
+                    c->tunes[key] = cand;
+                    if ((st = run_full(&ms)) != RGBID_OK) break;
+                    t_cand = std::min(t_cand, ms);
+                }
+                c->tunes[key] = st == RGBID_OK && t_cand < 0.995f * t_keep ? cand : keep;
+            }
+        }
+        if (st != RGBID_OK) {
+            c->profiling = saved_prof;
+            return st;
+        }
     }
     // drop the candidate graphs
     clear_graphs(c);
