@@ -274,13 +274,24 @@ __device__ __forceinline__ Ray3 rotate_ray(const Geom& G, float xu, float xv)
 // and W* = (R^T x)_z w_b / (1 + w_b (R^T t)_z) with w_b the bilinear W_B.
 // Valid iff w_a valid, in front, p_B in [-0.5, w-0.5) x [-0.5, h-0.5), four
 // valid W taps and W* positive and finite; I* and W* are undefined otherwise.
-// Branch-free: the four taps are always loaded (at clamped, in-bounds
-// addresses).  Split in two phases so that a lane can issue the tap loads of
-// all its pixels before it consumes any of them.
+// Branch-free: the four taps are always loaded (at in-bounds addresses).
+// Split in two phases so that a lane can issue the tap loads of all its
+// pixels before it consumes any of them.
+//
+// Taps at the image edge.  The taps are x0 = floor(u_B) and x0 + 1 (rows
+// likewise), each clamped to the image; a clamped second tap is the first
+// one, so the interpolation along that axis returns the first tap.  Instead
+// of copying the first tap over the second, the second is loaded unclamped
+// (one texel on, or one row on: the next row's first texel, or the zero
+// guard row or texel after the plane) and the interpolation weight along that
+// axis is set to 0: fma(0, t1 - t0, t0) = t0 exactly for finite texels
+// (intensities are finite; W is stored finite in FP32, and in FP16 an unused
+// second tap's W is replaced), and the second tap's validity is not asked
+// for.
 struct WarpTaps {
     float2 p00, p10, p01, p11;
     float a, b, az;
-    bool ok;
+    bool ok, dx, dy;   // dx, dy: the second tap along u, v is one texel on
 };
 
 template <bool F16>
@@ -294,34 +305,35 @@ __device__ __forceinline__ void warp_fetch(const Geom& G, const Ray3& a, float w
                     (vb >= -0.5f) & (vb < G.vlim);
     ub = ok ? ub : 0.0f;
     vb = ok ? vb : 0.0f;
-    T.a = __builtin_amdgcn_fractf(ub);
-    T.b = __builtin_amdgcn_fractf(vb);
-    T.az = a.z;
-    T.ok = ok;
-    // taps x0 = floor(u_B) (>= -1 in bounds) and x0 + 1, each clamped to
-    // the image: the second tap is one texel on iff 0 <= x0 < w - 1
+    // x0 = floor(u_B) >= -1 in bounds; the second tap is one texel on iff
+    // 0 <= x0 < w - 1
     const int xf = floor_i(ub), yf = floor_i(vb);
     const unsigned x0 = (unsigned)max(xf, 0), y0 = (unsigned)max(yf, 0);
-    const bool dx = (unsigned)xf < (unsigned)(G.w - 1);
-    const unsigned dy = (unsigned)yf < (unsigned)(G.h - 1) ? G.rowb : 0u;
+    T.dx = (unsigned)xf < (unsigned)(G.w - 1);
+    T.dy = (unsigned)yf < (unsigned)(G.h - 1);
+    T.a = T.dx ? __builtin_amdgcn_fractf(ub) : 0.0f;
+    T.b = T.dy ? __builtin_amdgcn_fractf(vb) : 0.0f;
+    T.az = a.z;
+    T.ok = ok;
+    // both taps of a row in one load, the second row from a base one row on
+    // (the texel after the last row's last texel is still guard)
     const unsigned o00 = __umul24(y0, G.rowb) + x0 * G.texb;
-    const unsigned o01 = o00 + dy;
-    // both taps of a row in one load (the texel after the last of the plane
-    // is still inside the pyramid's allocation); a clamped second tap is the
-    // first one
-    float2 a0, a1, b0, b1;
-    load_iw2_at<F16>(G.Biw, o00, a0, a1);
-    load_iw2_at<F16>(G.Biw, o01, b0, b1);
-    T.p00 = a0;
-    T.p10 = dx ? a1 : a0;
-    T.p01 = b0;
-    T.p11 = dx ? b1 : b0;
+    load_iw2_at<F16>(G.Biw, o00, T.p00, T.p10);
+    load_iw2_at<F16>(static_cast<const char*>(G.Biw) + G.rowb, o00, T.p01, T.p11);
+    if constexpr (F16) {
+        // an inverse depth beyond the half range is stored as inf: the W of
+        // an unused second tap is the first tap's, so no inf meets a weight 0
+        T.p10.y = T.dx ? T.p10.y : T.p00.y;
+        T.p11.y = T.dx ? T.p11.y : T.p01.y;
+        T.p01.y = T.dy ? T.p01.y : T.p00.y;
+        T.p11.y = T.dy ? T.p11.y : T.p10.y;
+    }
 }
 
 __device__ __forceinline__ bool warp_finish(const Geom& G, const WarpTaps& T, float& Io, float& Wo)
 {
-    const bool ok = T.ok & (int)w_valid(T.p00.y) & (int)w_valid(T.p10.y) &
-                    (int)w_valid(T.p01.y) & (int)w_valid(T.p11.y);
+    const bool ok = T.ok & (int)w_valid(T.p00.y) & ((int)w_valid(T.p10.y) | !T.dx) &
+                    ((int)w_valid(T.p01.y) | !T.dy) & ((int)w_valid(T.p11.y) | !(T.dx & T.dy));
     // bilinear: along u on both rows, then along v
     const float i0 = fmaf(T.a, T.p10.x - T.p00.x, T.p00.x);
     const float i1 = fmaf(T.a, T.p11.x - T.p01.x, T.p01.x);
@@ -577,14 +589,14 @@ __device__ __forceinline__ void residuals(float2 c, unsigned m, float Is, float 
 struct RobustF {
     float muI, isI, aI, cI;
     float muW, isW, aW, cW;
-    bool enI, enW;
+    unsigned mI, mW;   // flag bit each channel needs (0: the channel takes no part)
 };
 
 __device__ __forceinline__ RobustF robust_f(const IterLaunch& L, const PairState& S)
 {
     RobustF F;
-    F.enI = S.ns[0] > 0;
-    F.enW = S.ns[1] > 0;
+    F.mI = S.ns[0] > 0 ? 1u : 0u;
+    F.mW = S.ns[1] > 0 ? 2u : 0u;
     F.muI = S.mu[0];
     F.muW = S.mu[1];
     const float sgI = S.sigma[0], sgW = S.sigma[1];
@@ -608,7 +620,9 @@ __device__ __forceinline__ RobustF robust_f(const IterLaunch& L, const PairState
 template <int KIND>
 __device__ __forceinline__ float sqrt_weight(float d, float is, float a, float c)
 {
-    if constexpr (KIND == RGBID_W_HUBER) return fminf(is, a * rsq(fabsf(d)));
+    // Huber: min(is, a rsqrt|d|) as a median with 0 (both operands are >= 0;
+    // fminf would re-canonicalise the loop-invariant is on every call)
+    if constexpr (KIND == RGBID_W_HUBER) return __builtin_amdgcn_fmed3f(a * rsq(fabsf(d)), 0.0f, is);
     else return a * rsq(fmaf(d, d, c));
 }
 
@@ -729,11 +743,16 @@ __device__ __forceinline__ void ne_feed(NeAcc& na, float4* st, int lane)
 }
 
 // The wave's compensated totals of the 28 sums and the two counts into
-// out[0 .. 29] (LDS, as (hi, lo) pairs).
+// out[0 .. 29] (LDS, as (hi, lo) pairs); cI, cW are the lane's counts.
 __device__ __forceinline__ void ne_wave_totals(NeAcc& na, float4* st, int lane, unsigned cI,
                                                unsigned cW, float2* out)
 {
     if (na.tiles > 0) ne_flush(na, st, lane);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        cI += __shfl_xor(cI, o);
+        cW += __shfl_xor(cW, o);
+    }
     if (lane < 28) out[lane] = make_float2(na.hi, na.lo);
     else if (lane == 28) out[28] = make_float2((float)cI, 0.0f);
     else if (lane == 29) out[29] = make_float2((float)cW, 0.0f);
@@ -753,17 +772,17 @@ __device__ __forceinline__ void ne_wave_totals(NeAcc& na, float4* st, int lane, 
 // q = k_u^2 + k_v^2 + (k_3 + W_A)^2, and lambda_n = W_A / sqrt(q |x|^2).
 // A term that takes no part (invalid pixel, or its channel without a sample)
 // stages zeros: its weight is 0 and the legacy multiply gives 0 x anything
-// = 0.  The counts of contributing pixels go to the wave-uniform cI, cW.
+// = 0.  The lane's counts of contributing terms are cI, cW.
 template <int KIND>
 __device__ __forceinline__ void pixel_vectors(const LevelRay& R, float xu, float xv, float2 c,
                                               const Nbrs& n, unsigned m, float Is, float Ws,
                                               bool wv, const RobustF& F, float4* st, int lane,
                                               unsigned& cI, unsigned& cW)
 {
-    const bool tI = wv & ((m & 1u) != 0u) & F.enI;
-    const bool tW = wv & ((m & 2u) != 0u) & F.enW;
-    cI += (unsigned)__popcll(__ballot(tI));
-    cW += (unsigned)__popcll(__ballot(tW));
+    const bool tI = wv & ((m & F.mI) != 0u);
+    const bool tW = wv & ((m & F.mW) != 0u);
+    cI += tI ? 1u : 0u;
+    cW += tW ? 1u : 0u;
     const float wa = c.y;
     const float rI = Is - c.x, rW = Ws - wa;
     float sI = sqrt_weight<KIND>(rI - F.muI, F.isI, F.aI, F.cI);
@@ -1312,22 +1331,24 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
 
 // ------------------------------------------------------------------ k_reduce
 
-// A level pixel of A with everything its terms need: raster index, ray,
-// (I, W), validity flags and the four neighbours.
+// A level pixel of A with everything its terms need: whether it is a pixel
+// of the level, ray, (I, W), validity flags and the four neighbours.
 struct RefPx {
-    int idx;
+    bool in;
     float xu, xv;
     float2 c;
     unsigned m;
     Nbrs nb;
 };
 
+// Position (u, v), raster index idx; in: a pixel of the level (otherwise
+// pixel 0 is read in its place).
 template <bool F16>
-__device__ __forceinline__ void load_ref(const LevelView& A, const LevelRay& R, int n, int idx,
+__device__ __forceinline__ void load_ref(const LevelView& A, const LevelRay& R, bool in, int idx,
                                          int u, int v, RefPx& r)
 {
-    const unsigned ic = (unsigned)min(idx, n - 1);
-    r.idx = idx;
+    const unsigned ic = in ? (unsigned)idx : 0u;
+    r.in = in;
     r.xu = ray_x(R, u);
     r.xv = ray_y(R, v);
     r.c = load_iw<F16>(A.iw, ic);
@@ -1351,12 +1372,12 @@ __device__ __forceinline__ void advance(int& idx, int& u, int& v, int step, int 
 // Level pixel that is its own warp child: warp, residuals, weighted
 // Jacobians into the accumulators.
 template <bool F16, int KIND>
-__device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, const RefPx& r, int n,
+__device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, const RefPx& r,
                                           const RobustF& F, NeAcc& na, float4* st, int lane,
                                           unsigned& cI, unsigned& cW)
 {
     float Is, Ws;
-    const bool wv = warp_ray<F16>(G, r.xu, r.xv, r.c.y, Is, Ws) & (r.idx < n);
+    const bool wv = warp_ray<F16>(G, r.xu, r.xv, r.c.y, Is, Ws) & r.in;
     pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, r.m, Is, Ws, wv, F, st, lane, cI, cW);
     ne_feed(na, st, lane);
 }
@@ -1364,11 +1385,11 @@ __device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, cons
 // Level pixel whose warped values come from the store: residuals, weighted
 // Jacobians into the accumulators.
 template <int KIND>
-__device__ __forceinline__ void stored_pixel(const LevelRay& R, const RefPx& r, float2 e, int n,
+__device__ __forceinline__ void stored_pixel(const LevelRay& R, const RefPx& r, float2 e,
                                              const RobustF& F, NeAcc& na, float4* st, int lane,
                                              unsigned& cI, unsigned& cW)
 {
-    const bool wv = (e.y > 0.0f) & (r.idx < n);
+    const bool wv = (e.y > 0.0f) & r.in;
     pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, r.m, e.x, e.y, wv, F, st, lane, cI, cW);
     ne_feed(na, st, lane);
 }
@@ -1401,8 +1422,11 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
     const int waves = blockDim.x >> 6;
     const int end = ch.first + ch.count;
     const int wl = L.ip.warp_mode == RGBID_WARP_FULLRES ? 0 : l;
-    const Geom G = make_geom<F16>(S, D.A[wl], D.B[wl]);
+    Geom G = make_geom<F16>(S, D.A[wl], D.B[wl]);
     if constexpr (FUSED && LOG2B == 0) {
+        // the rotation's constant column in vector registers for the whole
+        // loop (an FMA takes one scalar operand)
+        asm volatile("" : "+v"(G.m[2]), "+v"(G.m[5]), "+v"(G.m[8]));
         // The level pixel is its own warp child, so W_A comes with A's (I, W).
         // A tile is a kBlockW x kBlockH block of the level (lane l at column
         // l mod kBlockW, row l / kBlockW of it; pixels past the level's edge
@@ -1412,28 +1436,33 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         // gathers from B are in flight.
         const int bxn = (gd.gw + kBlockW - 1) / kBlockW, gh = A.h;
         const int lu = lane % kBlockW, lv = lane / kBlockW;
-        auto place = [&](int t, int& idx, int& u, int& v) {
-            const int by = t / bxn, bx = t - by * bxn;   // t is uniform
-            u = bx * kBlockW + lu;
-            v = by * kBlockH + lv;
-            idx = (u < gd.gw) & (v < gh) ? v * gd.gw + u : gd.n;
+        int loff = lv * gd.gw + lu;
+        asm volatile("" : "+v"(loff));   // kept: not re-derived per tile as v * gw + u
+        auto place = [&](int t, bool& in, int& idx, int& u, int& v) {
+            // the block's corner (uniform) plus the lane's place in it
+            const int by = t / bxn, bx = t - by * bxn, u0 = bx * kBlockW, v0 = by * kBlockH;
+            u = u0 + lu;
+            v = v0 + lv;
+            in = (u < gd.gw) & (v < gh);
+            idx = (v0 * gd.gw + u0) + loff;
         };
         int tile = __builtin_amdgcn_readfirstlane(ch.first + wave);
+        bool in;
         int idx, u, v;
-        place(tile, idx, u, v);
+        place(tile, in, idx, u, v);
         // two tiles per trip, the prefetch alternating between ra and rb, so
         // the reference values are never copied from one to the other
         RefPx ra, rb;
-        load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+        load_ref<F16>(A, R, in, idx, u, v, ra);
         while (tile < end) {
-            place(tile + waves, idx, u, v);
-            load_ref<F16>(A, R, gd.n, idx, u, v, rb);
-            own_pixel<F16, KIND>(G, R, ra, gd.n, F, na, st, lane, cI, cW);
+            place(tile + waves, in, idx, u, v);
+            load_ref<F16>(A, R, in, idx, u, v, rb);
+            own_pixel<F16, KIND>(G, R, ra, F, na, st, lane, cI, cW);
             tile += waves;
             if (tile >= end) break;
-            place(tile + waves, idx, u, v);
-            load_ref<F16>(A, R, gd.n, idx, u, v, ra);
-            own_pixel<F16, KIND>(G, R, rb, gd.n, F, na, st, lane, cI, cW);
+            place(tile + waves, in, idx, u, v);
+            load_ref<F16>(A, R, in, idx, u, v, ra);
+            own_pixel<F16, KIND>(G, R, rb, F, na, st, lane, cI, cW);
             tile += waves;
         }
     } else if constexpr (!FUSED) {
@@ -1446,21 +1475,21 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         int idx = tile * 64 + lane, u, v;
         split_index(idx, gd.gw, gd.inv_gw, gd.half_inv, u, v);
         RefPx ra, rb;
-        load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+        load_ref<F16>(A, R, idx < gd.n, idx, u, v, ra);
         float2 ea = load_f2(warped, min(idx, gd.n - 1)), eb;
         while (tile < end) {
             advance(idx, u, v, step, su, sv, gd.gw);
-            load_ref<F16>(A, R, gd.n, idx, u, v, rb);
+            load_ref<F16>(A, R, idx < gd.n, idx, u, v, rb);
             eb = load_f2(warped, min(idx, gd.n - 1));
             __builtin_amdgcn_sched_barrier(0);
-            stored_pixel<KIND>(R, ra, ea, gd.n, F, na, st, lane, cI, cW);
+            stored_pixel<KIND>(R, ra, ea, F, na, st, lane, cI, cW);
             tile += waves;
             if (tile >= end) break;
             advance(idx, u, v, step, su, sv, gd.gw);
-            load_ref<F16>(A, R, gd.n, idx, u, v, ra);
+            load_ref<F16>(A, R, idx < gd.n, idx, u, v, ra);
             ea = load_f2(warped, min(idx, gd.n - 1));
             __builtin_amdgcn_sched_barrier(0);
-            stored_pixel<KIND>(R, rb, eb, gd.n, F, na, st, lane, cI, cW);
+            stored_pixel<KIND>(R, rb, eb, F, na, st, lane, cI, cW);
             tile += waves;
         }
     } else {
