@@ -773,14 +773,16 @@ __device__ __forceinline__ void ne_wave_totals(NeAcc& na, float4* st, int lane, 
 // A term that takes no part (invalid pixel, or its channel without a sample)
 // stages zeros: its weight is 0 and the legacy multiply gives 0 x anything
 // = 0.  The lane's counts of contributing terms are cI, cW.
+// fI, fW: the pixel's flag bits 0 and 1 (sec. 6.2 residual definitions)
+// with the channel's enable.
 template <int KIND>
 __device__ __forceinline__ void pixel_vectors(const LevelRay& R, float xu, float xv, float2 c,
-                                              const Nbrs& n, unsigned m, float Is, float Ws,
-                                              bool wv, const RobustF& F, float4* st, int lane,
-                                              unsigned& cI, unsigned& cW)
+                                              const Nbrs& n, bool fI, bool fW, float Is,
+                                              float Ws, bool wv, const RobustF& F, float4* st,
+                                              int lane, unsigned& cI, unsigned& cW)
 {
-    const bool tI = wv & ((m & F.mI) != 0u);
-    const bool tW = wv & ((m & F.mW) != 0u);
+    const bool tI = wv & fI;
+    const bool tW = wv & fW;
     cI += tI ? 1u : 0u;
     cW += tW ? 1u : 0u;
     const float wa = c.y;
@@ -1369,16 +1371,95 @@ __device__ __forceinline__ void advance(int& idx, int& u, int& v, int step, int 
     }
 }
 
-// Level pixel that is its own warp child: warp, residuals, weighted
-// Jacobians into the accumulators.
-template <bool F16, int KIND>
-__device__ __forceinline__ void own_pixel(const Geom& G, const LevelRay& R, const RefPx& r,
-                                          const RobustF& F, NeAcc& na, float4* st, int lane,
-                                          unsigned& cI, unsigned& cW)
+// The level-0 path of the fused reduction (the level pixel is its own warp
+// child) works on blocks of kBlockW x kBlockH pixels, a lane per pixel.  The
+// four neighbours of the central differences come from a per-wave tile in
+// LDS: the block's own (I, W), which the lanes load anyway, and its halo (the
+// rows above and below, the columns left and right), which lanes 0..39 load
+// with one instruction.  The tile has kBlockH + 2 rows of kBlockW + 2 texels;
+// the corners are not used.
+constexpr int kTileW = kBlockW + 2, kTileTexels = kTileW * (kBlockH + 2);
+static_assert(2 * kBlockW + 2 * kBlockH <= 64, "one halo texel per lane");
+
+// The halo texel lane `lane` brings: its offset (du, dv) from the block's
+// first pixel and its place in the tile.  Lanes 40..63 bring none; they load
+// the block's first pixel and store it in the unused corner slot 0, so that
+// every lane issues the same loads and stores.
+struct HaloLane {
+    int du, dv, slot;
+};
+
+__device__ __forceinline__ HaloLane halo_lane(int lane)
 {
+    HaloLane h{0, 0, 0};
+    if (lane < kBlockW) {                            // row above
+        h.du = lane, h.dv = -1, h.slot = lane + 1;
+    } else if (lane < 2 * kBlockW) {                 // row below
+        h.du = lane - kBlockW, h.dv = kBlockH, h.slot = (kBlockH + 1) * kTileW + h.du + 1;
+    } else if (lane < 2 * kBlockW + kBlockH) {       // column left
+        h.du = -1, h.dv = lane - 2 * kBlockW, h.slot = (h.dv + 1) * kTileW;
+    } else if (lane < 2 * kBlockW + 2 * kBlockH) {   // column right
+        h.du = kBlockW, h.dv = lane - 2 * kBlockW - kBlockH, h.slot = (h.dv + 1) * kTileW + kBlockW + 1;
+    }
+    return h;
+}
+
+// A level-0 pixel of a block tile: whether it is a pixel of the level and an
+// interior one (1 <= u <= w - 2, 1 <= v <= h - 2), the block's first pixel
+// (u0, v0) (uniform), the pixel's (I, W) and the halo texel of the lane.
+struct RefL0 {
+    bool in, inner;
+    int u0, v0;
+    float2 c, h;
+};
+
+// What a level-0 pixel carries from l0_fetch to l0_finish: its ray and taps.
+struct L0Taps {
+    float xu, xv;
+    WarpTaps T;
+};
+
+// Warp, residuals and weighted Jacobians of a level-0 pixel into the
+// accumulators, in two steps: l0_fetch issues the pixel's tap loads (the
+// caller then issues the next tile's loads, so that waiting for the taps does
+// not wait for those), l0_finish does the rest.  tl: the wave's neighbour
+// tile; cslot: the pixel's place in it, nslot: the place of its upper-left
+// diagonal neighbour, hslot: the place of the lane's halo texel.  The
+// validity flags are those the pyramid stores (bit 0: interior with valid W;
+// bit 1: also the four W neighbours valid), formed here from the values at
+// hand.
+template <bool F16>
+__device__ __forceinline__ void l0_fetch(const Geom& G, const LevelRay& R, const RefL0& r, int lu,
+                                         int lv, L0Taps& t)
+{
+    t.xu = ray_x(R, r.u0 + lu);
+    t.xv = ray_y(R, r.v0 + lv);
+    warp_fetch<F16>(G, rotate_ray(G, t.xu, t.xv), r.c.y, t.T);
+}
+
+template <int KIND>
+__device__ __forceinline__ void l0_finish(const Geom& G, const LevelRay& R, const RefL0& r,
+                                          const L0Taps& t, float2* tl, int cslot, int nslot,
+                                          int hslot, const RobustF& F, NeAcc& na, float4* st,
+                                          int lane, unsigned& cI, unsigned& cW)
+{
+    // the block and its halo into the tile (the wave's earlier reads of it
+    // are done: LDS operations of a wave complete in order), then the four
+    // neighbours
+    tl[cslot] = r.c;
+    tl[hslot] = r.h;
+    Nbrs n;
+    n.t = tl[nslot + 1];
+    n.l = tl[nslot + kTileW];
+    n.r = tl[nslot + kTileW + 2];
+    n.b = tl[nslot + 2 * kTileW + 1];
     float Is, Ws;
-    const bool wv = warp_ray<F16>(G, r.xu, r.xv, r.c.y, Is, Ws) & r.in;
-    pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, r.m, Is, Ws, wv, F, st, lane, cI, cW);
+    const bool wv = warp_finish(G, t.T, Is, Ws) & r.in;
+    const bool f0 = r.inner & (int)w_valid(r.c.y);
+    const bool f1 = f0 & (int)w_valid(n.l.y) & (int)w_valid(n.r.y) & (int)w_valid(n.t.y) &
+                    (int)w_valid(n.b.y);
+    pixel_vectors<KIND>(R, t.xu, t.xv, r.c, n, f0 & (F.mI != 0u), f1 & (F.mW != 0u), Is, Ws, wv,
+                        F, st, lane, cI, cW);
     ne_feed(na, st, lane);
 }
 
@@ -1390,7 +1471,8 @@ __device__ __forceinline__ void stored_pixel(const LevelRay& R, const RefPx& r, 
                                              unsigned& cI, unsigned& cW)
 {
     const bool wv = (e.y > 0.0f) & r.in;
-    pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, r.m, e.x, e.y, wv, F, st, lane, cI, cW);
+    pixel_vectors<KIND>(R, r.xu, r.xv, r.c, r.nb, (r.m & F.mI) != 0u, (r.m & F.mW) != 0u, e.x,
+                        e.y, wv, F, st, lane, cI, cW);
     ne_feed(na, st, lane);
 }
 
@@ -1430,39 +1512,62 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         // The level pixel is its own warp child, so W_A comes with A's (I, W).
         // A tile is a kBlockW x kBlockH block of the level (lane l at column
         // l mod kBlockW, row l / kBlockW of it; pixels past the level's edge
-        // take no part), blocks in raster order: the centre, neighbour and
-        // tap lines of a tile are mostly the same lines, so they are fetched
-        // once.  A's loads for the next tile are issued while this tile's
-        // gathers from B are in flight.
+        // take no part), blocks in raster order: the centre and tap lines of
+        // a tile are mostly the same lines, so they are fetched once.  A's
+        // loads for the next tile are issued while this tile's gathers from B
+        // are in flight.
+        __shared__ float2 nb_tiles[8 * kTileTexels];
+        float2* const tl = nb_tiles + wave * kTileTexels;
         const int bxn = (gd.gw + kBlockW - 1) / kBlockW, gh = A.h;
         const int lu = lane % kBlockW, lv = lane / kBlockW;
-        int loff = lv * gd.gw + lu;
-        asm volatile("" : "+v"(loff));   // kept: not re-derived per tile as v * gw + u
-        auto place = [&](int t, bool& in, int& idx, int& u, int& v) {
-            // the block's corner (uniform) plus the lane's place in it
+        const int cslot = (lv + 1) * kTileW + lu + 1, nslot = lv * kTileW + lu;
+        const HaloLane hl = halo_lane(lane);
+        // lane offsets from the block's first pixel, kept in registers (not
+        // re-derived per tile as v * w + u)
+        int loff = lv * gd.gw + lu, hoff = hl.dv * gd.gw + hl.du;
+        asm volatile("" : "+v"(loff), "+v"(hoff));
+        // halo texels are read from a base one row and one texel before the
+        // plane (inside its zero guard), their index clamped to the guard
+        // after it: only pixels that are not interior see clamped values
+        const unsigned texb = F16 ? 4u : 8u;
+        const char* const hbase = static_cast<const char*>(A.iw) - (gd.gw + 1) * (int)texb;
+        const int hmax = gd.n + 2 * gd.gw + 1;
+        const unsigned uin = (unsigned)max(gd.gw - 2, 0), vin = (unsigned)max(gh - 2, 0);
+        auto load = [&](int t, RefL0& r) {
+            // the block's first pixel (uniform) plus the lane's place in it
             const int by = t / bxn, bx = t - by * bxn, u0 = bx * kBlockW, v0 = by * kBlockH;
-            u = u0 + lu;
-            v = v0 + lv;
-            in = (u < gd.gw) & (v < gh);
-            idx = (v0 * gd.gw + u0) + loff;
+            const int corner = v0 * gd.gw + u0;
+            const int u = u0 + lu, v = v0 + lv;
+            r.in = (u < gd.gw) & (v < gh);
+            r.inner = ((unsigned)(u - 1) < uin) & ((unsigned)(v - 1) < vin);
+            r.u0 = u0;
+            r.v0 = v0;
+            unsigned co = (r.in ? (unsigned)(corner + loff) : 0u) * texb;
+            asm volatile("" : "+v"(co));   // a 32-bit offset from the plane's base
+            r.c = load_iw_at<F16>(A.iw, co);
+            r.h = load_iw_at<F16>(hbase, (unsigned)min(corner + hoff + gd.gw + 1, hmax) * texb);
         };
         int tile = __builtin_amdgcn_readfirstlane(ch.first + wave);
-        bool in;
-        int idx, u, v;
-        place(tile, in, idx, u, v);
         // two tiles per trip, the prefetch alternating between ra and rb, so
         // the reference values are never copied from one to the other
-        RefPx ra, rb;
-        load_ref<F16>(A, R, in, idx, u, v, ra);
+        // this tile's taps, then the next tile's loads, then this tile's
+        // arithmetic
+        RefL0 ra, rb;
+        L0Taps T;
+        load(tile, ra);
         while (tile < end) {
-            place(tile + waves, in, idx, u, v);
-            load_ref<F16>(A, R, in, idx, u, v, rb);
-            own_pixel<F16, KIND>(G, R, ra, F, na, st, lane, cI, cW);
+            l0_fetch<F16>(G, R, ra, lu, lv, T);
+            __builtin_amdgcn_sched_barrier(0);
+            load(tile + waves, rb);
+            __builtin_amdgcn_sched_barrier(0);
+            l0_finish<KIND>(G, R, ra, T, tl, cslot, nslot, hl.slot, F, na, st, lane, cI, cW);
             tile += waves;
             if (tile >= end) break;
-            place(tile + waves, in, idx, u, v);
-            load_ref<F16>(A, R, in, idx, u, v, ra);
-            own_pixel<F16, KIND>(G, R, rb, F, na, st, lane, cI, cW);
+            l0_fetch<F16>(G, R, rb, lu, lv, T);
+            __builtin_amdgcn_sched_barrier(0);
+            load(tile + waves, ra);
+            __builtin_amdgcn_sched_barrier(0);
+            l0_finish<KIND>(G, R, rb, T, tl, cslot, nslot, hl.slot, F, na, st, lane, cI, cW);
             tile += waves;
         }
     } else if constexpr (!FUSED) {
@@ -1499,9 +1604,10 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
             int u = 0, v = 0, idx;
             warp_tile<F16, LOG2B>(G, tile * 64, gd, lane, Is, Ws, wv, u, v, idx);
             const unsigned i = __umul24(v, A.w) + u;
+            const unsigned m = load_mask(A, i);
             pixel_vectors<KIND>(R, ray_x(R, u), ray_y(R, v), load_iw<F16>(A.iw, i),
-                                load_nbrs<F16>(A, i), load_mask(A, i), Is, Ws, wv, F, st, lane,
-                                cI, cW);
+                                load_nbrs<F16>(A, i), (m & F.mI) != 0u, (m & F.mW) != 0u, Is,
+                                Ws, wv, F, st, lane, cI, cW);
             ne_feed(na, st, lane);
         }
     }
