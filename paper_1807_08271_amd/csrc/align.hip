@@ -1051,6 +1051,7 @@ constexpr float kNoSample = __builtin_inff();
 struct LiveSlots {
     int full;     // slots 0 .. full-1 (full < PER) are live in every thread (uniform)
     bool tail;    // slot PER - 1 is live in this thread
+    int n;        // entries in the sample (uniform)
 };
 
 // f(q) for the slots q = Q .. N-1 in order, up to the first q >= n (n
@@ -1116,6 +1117,7 @@ __device__ __forceinline__ LiveSlots compact_sample(float (&r)[PER], float* cmp,
     LiveSlots ls;
     ls.full = min(F, PER - 1);
     ls.tail = F == PER || t < total % kScaleThreads;
+    ls.n = total;
     r[PER - 1] = ls.tail ? cmp[t + ls.full * kScaleThreads] : kNoSample;
     return ls;
 }
@@ -1240,21 +1242,22 @@ __global__ void __launch_bounds__(kScaleThreads) k_scale(IterLaunch L)
         cs[0] += ok ? 1.0f : 0.0f;
         cs[1] = ok ? fmaf(x, x, cs[1]) : cs[1];
     }
-    {
+    // a cold start takes the root mean square as its first sigma; a warm one
+    // only needs the count, which the compaction gives
+    double mu = warm ? (double)mu_prev : 0.0;
+    float sigma = sg_prev;
+    if (!warm) {
         double t[2];
         block_totals<2>(cs, part, t);
-        if (threadIdx.x == kTotalsLane) {
-            bcd[0] = t[0];
+        if (threadIdx.x == kTotalsLane)
             bcf[0] = t[0] > 0.0 ? (float)fmax(sqrt(t[1] / t[0]), (double)floor_s) : floor_s;
-        }
         __syncthreads();
+        sigma = bcf[0];
     }
-    const double n = bcd[0];
-    double mu = warm ? (double)mu_prev : 0.0;
-    float sigma = warm ? sg_prev : bcf[0];
+    const LiveSlots ls = compact_sample<PER>(r, cmp, wcnt);
+    const double n = (double)ls.n;
     float nu = 5.0f;
     if (n > 0.0) {
-        const LiveSlots ls = compact_sample<PER>(r, cmp, wcnt);
         const float inv_n = (float)(1.0 / n);
         if (L.ip.weight == RGBID_W_HUBER)
             scale_fixed_point<RGBID_W_HUBER, PER>(r, ls, inv_n, floor_s, L.ip.huber_k,
