@@ -68,13 +68,22 @@ def main(argv=None):
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--tune", default=None,
+                    help="the launch-shape file passed to the profiled command (--tune-file): "
+                         "its lines are recorded, so the command can be repeated")
     ap.add_argument("--roof-bytes", nargs="*", default=[], metavar="KERNEL=BYTES",
                     help="algorithmic bytes per launch of named kernels: adds a table of their "
                          "achieved GB/s against the 8 TB/s HBM roof")
     a = ap.parse_args(argv)
 
     lines = ["# rocprofv3: %s" % a.workload, "", "Command (from the repository root):", "",
-             "```", a.cmd, "```", "", "## Kernel trace (`--kernel-trace --stats`), library kernels", "",
+             "```", a.cmd, "```", ""]
+    if a.tune:
+        lines += ["Launch shapes (the tune file; per batch shape: fused, waves, tiles per wave, "
+                  "XCD remap, warp passes):", "", "```"]
+        lines += [ln.rstrip("\n") for ln in open(a.tune) if ln.strip()]
+        lines += ["```", ""]
+    lines += ["## Kernel trace (`--kernel-trace --stats`), library kernels", "",
              "| kernel | template args | calls | average us | total ms |", "|---|---|---|---|---|"]
     for r in csv.DictReader(open(a.stats)):
         kk = kernel_key(r["Name"])
