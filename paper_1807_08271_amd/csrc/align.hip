@@ -1552,9 +1552,8 @@ __global__ void __launch_bounds__(512) k_reduce(IterLaunch L)
         };
         int tile = __builtin_amdgcn_readfirstlane(ch.first + wave);
         // two tiles per trip, the prefetch alternating between ra and rb, so
-        // the reference values are never copied from one to the other
-        // this tile's taps, then the next tile's loads, then this tile's
-        // arithmetic
+        // the reference values are never copied from one to the other; per
+        // tile: its taps, then the next tile's loads, then its arithmetic
         RefL0 ra, rb;
         L0Taps T;
         load(tile, ra);
