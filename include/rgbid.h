@@ -124,7 +124,7 @@ void rgbid_default_params(rgbid_align_params* p);
 
 /* Creates a context on HIP device `device`, enqueuing on `hip_stream` (a
    hipStream_t; NULL = the legacy default stream).  The context owns its
-   scratch memory.  *ctx is NULL on failure.  A batch is split into up to 3
+   scratch memory.  *ctx is NULL on failure.  A batch is split into up to 4
    launch chains that run on streams of their own, forked from and joined back
    into `hip_stream`; the environment variable RGBID_CHAINS (1-8), read here,
    sets another number. */

@@ -83,7 +83,7 @@ struct rgbid_ctx {
     std::map<std::string, std::vector<hipGraphExec_t>> graphs;   // one graph per chain
     std::map<std::string, LevelTune> tunes;   // per (level shape) launch shape
     hipEvent_t tev[2] = {nullptr, nullptr};   // launch-region timing (autotuner)
-    int chains = 3;                           // parallel branches of a batch graph
+    int chains = 4;                           // parallel branches of a batch graph
     std::vector<hipStream_t> chain_streams;   // capture streams of branches 1..
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
