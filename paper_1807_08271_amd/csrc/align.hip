@@ -345,16 +345,6 @@ __device__ __forceinline__ bool warp_finish(const Geom& G, const WarpTaps& T, fl
     return ok & (int)w_valid(Wo);
 }
 
-// Warp of one pixel with ray (xu, xv, 1) at the warp level.
-template <bool F16>
-__device__ __forceinline__ bool warp_ray(const Geom& G, float xu, float xv, float wa, float& Io,
-                                         float& Wo)
-{
-    WarpTaps T;
-    warp_fetch<F16>(G, rotate_ray(G, xu, xv), wa, T);
-    return warp_finish(G, T, Io, Wo);
-}
-
 // Sum over aligned groups of LPP lanes (a power of two), the same in every
 // lane of the group, added in a fixed tree: pairs, quads (DPP quad_perm),
 // eights (row_half_mirror), rows of 16 (row_mirror), then shuffles.
