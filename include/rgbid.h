@@ -16,8 +16,8 @@
  * Conventions (all calls)
  *   Images are row-major; element (u, v) is at index v * pitch + u, with u the
  *   column and v the row, pixel centres at integer coordinates.  Intensity is
- *   in grey levels (finite values); inverse depth W = 1/Z in 1/m, and W <= 0
- *   or non-finite marks a hole.  Device pointers are HIP device memory on the context's
+ *   in grey levels (finite values, below 65504 with FP16 storage); inverse
+ *   depth W = 1/Z in 1/m, and W <= 0 or non-finite marks a hole.  Device pointers are HIP device memory on the context's
  *   device (a torch tensor's data_ptr() is fine).
  *   A pose is T = (R, t), R row-major, the pose of B in A: X_A = R X_B + t
  *   (the paper's T_A^B).  Twists are xi = (v, theta), translation first.
