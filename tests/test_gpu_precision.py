@@ -6,8 +6,8 @@ the FP64 oracle run on the same FP16-rounded inputs (arithmetic error: must be
 <= 1e-5 rad / 1e-5 m) and on the FP32 inputs (storage error: reported).
 
 By default 24 pairs of the 300-frame walk are checked; RGBID_PRECISION_FRAMES=300
-runs the whole walk.  The per-frame errors are written to
-gpurun_out/precision_walk.json."""
+runs the whole walk.  The per-frame errors are written to precision_walk.json
+in the run's output folder."""
 import json
 import os
 
