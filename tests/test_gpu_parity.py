@@ -506,6 +506,36 @@ def test_ragged_size_and_small_sample(ctx):
     rg.rgbid_pyramid_free(B)
 
 
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("size", [(17, 5), (31, 11), (48, 12), (65, 9)])
+def test_level0_block_edges_match_oracle(ctx, storage, size):
+    # Level 0 is reduced in 16 x 4 pixel blocks with the neighbours from a
+    # per-wave tile (block plus a halo row / column on each side) and the
+    # validity flags formed in the kernel.  Widths and heights below, at and
+    # just past a block multiple (partial blocks on the right and at the
+    # bottom, halos clamped to the plane's guards), in FP32 and FP16 storage,
+    # against the oracle's normal equations at a pose short of the truth.
+    rg = _rg()
+    w, h = size
+    p = synth.pair_c1(3)
+    crop = lambda a: np.ascontiguousarray(a[:h, :w])
+    I, W, Ib, Wb = crop(p.A.I), crop(p.A.W), crop(p.B.I), crop(p.B.W)
+    if storage == 1:
+        I, W, Ib, Wb = (synth.to_fp16_grid(a) for a in (I, W, Ib, Wb))
+    cam = (w, h, 131.25, 131.25, 79.5, 59.5)
+    print("level-0 block edges %dx%d storage %d" % (w, h, storage), flush=True)
+    A = rg.rgbid_pyramid(ctx, cam, 1, storage, *upload(I, W))
+    B = rg.rgbid_pyramid(ctx, cam, 1, storage, *upload(Ib, Wb))
+    R, t = oracle.exp_so3(oracle.log_so3(p.R) * 0.6), p.t * 0.6
+    g = rg.rgbid_normal_equations(ctx, A, B, 0, (R, t), _params(1, [1]))
+    r = oracle.normal_equations_at(cam, I, W, Ib, Wb, 0, R, t,
+                                   _oparams(1, [1], storage="f16" if storage else "f32"))
+    assert r["n_valid_I"] > 0
+    check_normal_equations(g, r, what="%dx%d storage %d" % (w, h, storage))
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
 def test_argument_errors(ctx):
     rg = _rg()
     import torch
