@@ -536,6 +536,57 @@ def test_level0_block_edges_match_oracle(ctx, storage, size):
     rg.rgbid_pyramid_free(B)
 
 
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("axis,sign", [(1, 1), (1, -1), (0, 1), (0, -1)])
+def test_edge_taps_match_oracle(ctx, storage, axis, sign):
+    # A rotation about the y (x) axis that moves the first interior column
+    # (row) of the middle line to -0.25, or the last interior one to w - 0.75
+    # (h - 0.75): those pixels and their neighbours along the line sample B
+    # where the bilinear taps are clamped to the image.  The kernels load the second
+    # tap unclamped and give it weight 0 there; the oracle clamps the taps.
+    rg = _rg()
+    p = synth.pair_c1(5)
+    I, W, Ib, Wb = p.A.I, p.A.W, p.B.I, p.B.W
+    if storage == 1:
+        I, W, Ib, Wb = (synth.to_fp16_grid(a) for a in (I, W, Ib, Wb))
+    cam = p.cam
+    K = np.array([[cam.fx, 0.0, cam.cx], [0.0, cam.fy, cam.cy], [0.0, 0.0, 1.0]])
+    n = cam.h if axis == 0 else cam.w
+    # the first (last) interior pixel of the middle line to n[-0.25] (n - 0.75)
+    src = 1.0 if sign > 0 else n - 2.0
+    dst = -0.25 if sign > 0 else n - 0.75
+    mid = (cam.cx, cam.cy)
+
+    def proj(a):
+        th = np.zeros(3)
+        th[axis] = a
+        x = np.array([src, mid[1], 1.0]) if axis == 1 else np.array([mid[0], src, 1.0])
+        q = K @ oracle.exp_so3(th).T @ np.linalg.solve(K, x)
+        return q[1 - axis] / q[2] if axis == 0 else q[0] / q[2]
+
+    lo, hi = -0.05, 0.05   # radians; the projection is monotone in the angle
+    flo = proj(lo) - dst
+    for _ in range(80):
+        m = 0.5 * (lo + hi)
+        if (proj(m) - dst) * flo > 0:
+            lo, flo = m, proj(m) - dst
+        else:
+            hi = m
+    th = np.zeros(3)
+    th[axis] = 0.5 * (lo + hi)
+    Rq, tq = oracle.exp_so3(th), np.zeros(3)
+    print("edge taps axis %d sign %d storage %d" % (axis, sign, storage), flush=True)
+    A = rg.rgbid_pyramid(ctx, cam, 1, storage, *upload(I, W))
+    B = rg.rgbid_pyramid(ctx, cam, 1, storage, *upload(Ib, Wb))
+    g = rg.rgbid_normal_equations(ctx, A, B, 0, (Rq, tq), _params(1, [1]))
+    r = oracle.normal_equations_at(cam, I, W, Ib, Wb, 0, Rq, tq,
+                                   _oparams(1, [1], storage="f16" if storage else "f32"))
+    check_normal_equations(g, r, what="edge taps axis %d sign %d storage %d" % (
+        axis, sign, storage))
+    rg.rgbid_pyramid_free(A)
+    rg.rgbid_pyramid_free(B)
+
+
 def test_argument_errors(ctx):
     rg = _rg()
     import torch
