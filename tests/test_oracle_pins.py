@@ -157,6 +157,32 @@ def test_warp_identity_reproduces_A():
     assert not np.any(V[W == 0])
 
 
+@pytest.mark.parametrize("shift", [-0.25, 0.25])
+def test_warp_clamped_taps_at_the_image_edge(shift):
+    # A fronto-parallel plane at depth 1 and a translation along x move every
+    # projection by `shift` pixels along u.  I_B = a + b u + c v is linear, so
+    # inside the image the bilinear sample is the line at u + shift; where
+    # u + shift falls in [-0.5, 0) or [w - 1, w - 0.5) both taps are clamped
+    # to the edge column and the sample is that column's value (sec. 5.3
+    # bounds, clamped taps): no extrapolation and no zero padding.
+    w, h = 16, 12
+    fx = 20.0
+    cam = (w, h, fx, fx, 7.5, 5.5)
+    u, v = np.meshgrid(np.arange(w, dtype=float), np.arange(h, dtype=float))
+    a, b, c = 40.0, 3.0, 1.5
+    IB = a + b * u + c * v
+    ones = np.ones((h, w))
+    t = np.array([-shift / fx, 0.0, 0.0])
+    Iw, Ww, V = oracle.warp(cam, ones, IB, ones, np.eye(3), t)
+    ub = u + shift
+    want = a + b * np.clip(ub, 0.0, w - 1.0) + c * v
+    assert np.all(V)
+    np.testing.assert_allclose(Iw, want, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(Ww, ones, rtol=0, atol=1e-12)
+    edge = (ub < 0.0) | (ub > w - 1.0)
+    assert edge.sum() == h    # one column at the edge the shift points to
+
+
 def test_warp_pure_z_translation_closed_form():
     # W_B constant and I_B linear in u: W* = W_B / (1 + W_B t_z) and
     # I*(u) = I_B(u_B) with u_B = cx + (u - cx) Z0 / (Z0 - t_z).
